@@ -1,0 +1,51 @@
+"""The oracle's pins must catch plausible mistakes: each mutant below plants
+one (a dropped syndrome flip, a self-inclusive sum, a reversed shift, ...) in
+a copy of the oracle source, built on the CPU, and at least one pin test has
+to fail against it."""
+import os
+
+import pytest
+
+import oracle
+from tests import test_oracle_pins as P
+
+MUTANTS = {
+    "no_syndrome_flip": ("int neg = s[chk] & 1;\n                        for (int b = 0; b < d; b++) {",
+                         "int neg = 0;\n                        for (int b = 0; b < d; b++) {"),
+    "sum_includes_self": ("if (b == a) continue;\n                            S += ph[b];",
+                          "S += ph[b];"),
+    "q_adds_old_message": ("q[a] = app[c->chk_vn[e0 + a]] - r[e0 + a];\n                        ph[a]",
+                           "q[a] = app[c->chk_vn[e0 + a]] + r[e0 + a];\n                        ph[a]"),
+    "shift_left": ("c->chk_vn[e] = j * Z + (k + a) % Z;", "c->chk_vn[e] = j * Z + (k + Z - a) % Z;"),
+    "app_drops_q": ("app[c->chk_vn[e0 + a]] = q[a] + rn[a];\n                    }\n                }\n            }\n        }\n    }\n    x->flags",
+                    "app[c->chk_vn[e0 + a]] = rn[a];\n                    }\n                }\n            }\n        }\n    }\n    x->flags"),
+    "phi_factor": ("return log1p(2.0 / expm1(x));", "return log1p(1.0 / expm1(x));"),
+    "half_one_bit_short": ("int qe = e - 11;", "int qe = e - 10;"),
+    "greedy_skips_rows": ("for (int cand = first + 1; cand < mb; cand++) {", "for (int cand = first + 2; cand < mb; cand++) {"),
+    "minsum_includes_self": ("if (b == a) continue;\n        double v = fabs(q[b]);", "double v = fabs(q[b]);"),
+    "backward_rold_sign": ("gR[e0 + a] = -gq[a];", "gR[e0 + a] = gq[a];"),
+    "backward_beta_sign": ("gb[w] -= gz;", "gb[w] += gz;"),
+    "backward_argmin_sign": ("gq[arg] += gz * dabs(q[arg]);", "gq[arg] += gz;"),
+    "loss_sign": ("gA[v] = -sg * sigmoid(-sg * app[v]);", "gA[v] = sg * sigmoid(-sg * app[v]);"),
+}
+
+PINS = [getattr(P, n) for n in dir(P) if n.startswith("test_")]
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = oracle.source()
+    assert src.count(old) == 1, f"mutation site for {name} not unique"
+    path = oracle.build_variant(src.replace(old, new), str(tmp_path / f"libmut_{name}.so"))
+    caught = []
+    oracle.use_library(path)
+    try:
+        for fn in PINS:
+            try:
+                fn()
+            except Exception:
+                caught.append(fn.__name__)
+    finally:
+        oracle.use_library(None)
+    assert caught, f"no pin caught mutant {name}"

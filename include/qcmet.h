@@ -1,0 +1,153 @@
+/*
+ * qcmet.h -- C ABI of libqcmet: layered belief-propagation decoding of
+ * quasi-cyclic (multi-edge-type) LDPC codes in syndrome form on gfx950.
+ *
+ * Method: Li et al., arXiv 2004.09084 (Methods, steps 1-4: layered
+ * sum-product with the syndrome flip; Results: merged layers of rows with
+ * disjoint columns, many codewords decoded in parallel, one fused check/
+ * variable update per layer).
+ *
+ * Conventions for every entry point
+ *  - Every call returns QM_OK (0) or a negative QM_ERR_* code; no call
+ *    throws.  qm_last_error() gives a message for the calling thread, valid
+ *    until that thread's next call.
+ *  - "host" pointers are read during the call only; the library copies what
+ *    it keeps.  "device" pointers are HIP device allocations owned by the
+ *    caller; they must stay valid until the work queued on the given stream
+ *    has completed.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Decoding calls are asynchronous on that stream; HIP errors raised by
+ *    queued work surface at the caller's next synchronisation.
+ *  - Bits are uint8 holding 0 or 1.  LLRs follow the paper's sign: LLR > 0
+ *    favours bit 0 (BPSK 0 -> +1), and a hard decision is 1 iff APP < 0.
+ *  - Calls on one decoder must not overlap (they share its workspace).
+ */
+#ifndef QCMET_H
+#define QCMET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QM_ABI_VERSION 1
+
+enum qm_status {
+    QM_OK = 0,
+    QM_ERR_INVALID_ARG = -1,       /* NULL pointer, value out of range */
+    QM_ERR_SHAPE = -2,             /* sizes inconsistent with the code/decoder */
+    QM_ERR_SCHEDULE_CONFLICT = -3, /* rows of one layer share a block column */
+    QM_ERR_NO_WORKSPACE = -4,      /* decode before a large-enough workspace is bound */
+    QM_ERR_OOM = -5,               /* host allocation failed */
+    QM_ERR_HIP = -6,               /* a HIP runtime call failed */
+    QM_ERR_INPUT = -7,             /* QM_VALIDATE: non-finite LLR or syndrome bit > 1 */
+    QM_ERR_UNSUPPORTED = -8,       /* code structure outside what the kernels handle */
+    QM_ERR_STATE = -9              /* call order violated (e.g. backward without forward) */
+};
+
+/* Decoder flags (qm_decoder_create). */
+#define QM_MSG_FP32   0x0  /* check-to-variable messages stored as float32 */
+#define QM_MSG_FP16   0x1  /* messages stored as IEEE binary16 (round to nearest even);
+                              all arithmetic and the APP LLRs stay float32 */
+#define QM_PERSISTENT 0x2  /* one persistent launch runs every iteration of every code */
+#define QM_VALIDATE   0x4  /* qm_decode checks inputs first (synchronises the stream) */
+#define QM_GRAPH      0x8  /* replay the launch sequence from a captured hipGraph */
+
+typedef struct qm_code qm_code;
+typedef struct qm_decoder qm_decoder;
+
+typedef struct {
+    int32_t mb, nb, Z;        /* base matrix rows, columns, lifting factor */
+    int64_t n, m;             /* code length nb*Z, number of checks mb*Z */
+    int32_t n_type1_cols;     /* block columns of degree >= 2 */
+    int32_t n_deg1_cols;      /* block columns of degree 1 (deferred, see qm_decode) */
+    int32_t n_type1_entries;  /* non-(-1) entries in degree >= 2 columns */
+    int32_t max_row_type1;    /* largest number of such entries in one row */
+    int64_t edges;            /* Tanner-graph edges (all entries times Z) */
+    int32_t G;                /* layers in the current schedule */
+} qm_code_info;
+
+/* Tuning knobs that never change results (see qm_autotune). */
+typedef struct {
+    int32_t frames_per_tile;  /* FT: frames interleaved fastest in HBM; power of two
+                                 dividing the padded frame count; 0 = default */
+    int32_t block;            /* threads per workgroup of the layer kernel (64..1024, mult. of 64) */
+    int32_t merge;            /* 1: run each merged layer as one launch; 0: one launch per row
+                                 (same row order, bit-identical results) */
+    int32_t persistent;       /* 1: persistent kernel for the whole iteration loop */
+    int32_t graph;            /* 1: replay a captured hipGraph */
+} qm_tuning;
+
+int qm_abi_version(void);
+const char *qm_last_error(void);
+
+/* Loads a QC base matrix (paper, Results: a non-negative entry a is the
+ * Z x Z identity cyclically shifted right by a, i.e. check row k of block row
+ * i meets variable (k + a) mod Z of block column j; -1 is an all-zero block).
+ *   shifts: host int32 [mb*nb], row-major, each -1 or in [0, Z).
+ * Columns with exactly one non-(-1) entry are degree-1 columns; a row may
+ * hold at most one of them (QM_ERR_UNSUPPORTED otherwise), and at most 16
+ * entries in degree >= 2 columns.  The default schedule is the greedy merge
+ * of rows with disjoint columns (Results, Eq. (m)-(m2)): open a layer with
+ * the first unassigned row, add every later unassigned row disjoint from it,
+ * repeat; layers ordered by their first row.
+ *   out: receives the new code (free with qm_code_destroy). */
+int qm_code_create(int32_t mb, int32_t nb, int32_t Z, const int32_t *shifts, qm_code **out);
+int qm_code_destroy(qm_code *code);
+int qm_code_get_info(const qm_code *code, qm_code_info *info);
+
+/* Replaces the schedule.  The rows of layer g are rows[group_ptr[g] ..
+ * group_ptr[g+1]-1]; together the layers list every row exactly once.  The
+ * row order is part of what the layered decoder computes; grouping is not
+ * (rows in one layer share no column, so they commute).  Host arrays:
+ * group_ptr int32 [G+1], rows int32 [mb].  QM_ERR_SCHEDULE_CONFLICT if two
+ * rows of a layer share a column, QM_ERR_INVALID_ARG if not a partition.
+ * Decoders created earlier keep the schedule they were created with. */
+int qm_code_set_schedule(qm_code *code, int32_t G, const int32_t *group_ptr, const int32_t *rows);
+/* Copies the schedule out: *G, group_ptr [G+1] and rows [mb] (host, caller-sized). */
+int qm_code_get_schedule(const qm_code *code, int32_t *G, int32_t *group_ptr, int32_t *rows);
+
+/* Creates a decoder for frames_per_code[c] frames of codes[c], c < ncodes.
+ * All per-frame buffers of the decode calls are the concatenation over
+ * codes (in this order) of frame-major blocks [F_c][n_c] (or [F_c][m_c]).
+ * The codes must outlive the decoder. */
+int qm_decoder_create(const qm_code *const *codes, int32_t ncodes, const int32_t *frames_per_code,
+                      int32_t flags, qm_decoder **out);
+int qm_decoder_destroy(qm_decoder *dec);
+
+/* Device workspace: size it, allocate it (any allocator, 256-byte aligned),
+ * bind it.  The decoder borrows it; the caller frees it after the last
+ * queued decode has completed.  Binding copies the schedule descriptors to
+ * the device (synchronously) and must be repeated after qm_decoder_set_tuning. */
+size_t qm_decoder_workspace_bytes(const qm_decoder *dec);
+int qm_decoder_bind_workspace(qm_decoder *dec, void *device_ptr, size_t bytes);
+int qm_decoder_set_tuning(qm_decoder *dec, const qm_tuning *tuning);
+int qm_decoder_get_tuning(const qm_decoder *dec, qm_tuning *tuning);
+
+/* Layered sum-product decode (Methods, steps 1-4) of every frame for exactly
+ * `iters` full sweeps over the layers (no early termination).
+ *   llr      device float [sum_c F_c * n_c]  channel LLRs 2R/sigma^2
+ *   syndrome device uint8 [sum_c F_c * m_c]  s (H x = s)
+ *   iters    >= 0; 0 returns the channel decisions
+ *   hard     device uint8 [sum_c F_c * n_c]  out: c_n = [APP_n < 0]
+ *   app      device float [sum_c F_c * n_c]  out: APP LLRs, or NULL
+ *   flags    device uint8 [sum_c F_c]        out: 1 iff H c = s for the frame
+ * Degree-1 variables are deferred (their single check makes q = LLR exact at
+ * every layer); their APP is formed from the messages of the last sweep. */
+int qm_decode(qm_decoder *dec, const float *llr, const uint8_t *syndrome, int32_t iters,
+              uint8_t *hard, float *app, uint8_t *flags, void *stream);
+
+/* Times the result-preserving tunings (frames per tile, block size, merged
+ * or per-row launches, persistent/graph/plain) on the given inputs and keeps
+ * the fastest; the row order is never changed.  Rebinds the workspace.
+ * cache_path (may be NULL) appends one line per trial. */
+int qm_autotune(qm_decoder *dec, const float *llr, const uint8_t *syndrome, int32_t iters,
+                const char *cache_path, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QCMET_H */

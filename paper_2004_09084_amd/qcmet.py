@@ -1,0 +1,308 @@
+"""Python binding of libqcmet (argument marshalling only).
+
+Every function named ``qm_*`` mirrors the C entry point of the same name in
+include/qcmet.h.  Device buffers are torch CUDA tensors (PyTorch supplies
+device memory and streams, nothing else); every step of a decode runs in the
+library's HIP kernels.  There is no fallback: if ``libqcmet.so`` is missing
+or fails to load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqcmet.so")
+
+QM_OK = 0
+QM_ERR_INVALID_ARG = -1
+QM_ERR_SHAPE = -2
+QM_ERR_SCHEDULE_CONFLICT = -3
+QM_ERR_NO_WORKSPACE = -4
+QM_ERR_OOM = -5
+QM_ERR_HIP = -6
+QM_ERR_INPUT = -7
+QM_ERR_UNSUPPORTED = -8
+QM_ERR_STATE = -9
+
+QM_MSG_FP32 = 0x0
+QM_MSG_FP16 = 0x1
+QM_PERSISTENT = 0x2
+QM_VALIDATE = 0x4
+QM_GRAPH = 0x8
+
+# every symbol include/qcmet.h declares
+EXPORTED = [
+    "qm_abi_version", "qm_last_error", "qm_code_create", "qm_code_destroy", "qm_code_get_info",
+    "qm_code_set_schedule", "qm_code_get_schedule", "qm_decoder_create", "qm_decoder_destroy",
+    "qm_decoder_workspace_bytes", "qm_decoder_bind_workspace", "qm_decoder_set_tuning",
+    "qm_decoder_get_tuning", "qm_decode", "qm_autotune",
+]
+
+
+class QMError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class qm_code_info(ctypes.Structure):
+    _fields_ = [("mb", ctypes.c_int32), ("nb", ctypes.c_int32), ("Z", ctypes.c_int32),
+                ("n", ctypes.c_int64), ("m", ctypes.c_int64),
+                ("n_type1_cols", ctypes.c_int32), ("n_deg1_cols", ctypes.c_int32),
+                ("n_type1_entries", ctypes.c_int32), ("max_row_type1", ctypes.c_int32),
+                ("edges", ctypes.c_int64), ("G", ctypes.c_int32)]
+
+
+class qm_tuning(ctypes.Structure):
+    _fields_ = [("frames_per_tile", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("merge", ctypes.c_int32), ("persistent", ctypes.c_int32), ("graph", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libqcmet (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                               "(python -m paper_2004_09084_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        i32, p, sz = ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t
+        L.qm_abi_version.restype = ctypes.c_int
+        L.qm_last_error.restype = ctypes.c_char_p
+        L.qm_code_create.argtypes = [i32, i32, i32, p, ctypes.POINTER(p)]
+        L.qm_code_destroy.argtypes = [p]
+        L.qm_code_get_info.argtypes = [p, ctypes.POINTER(qm_code_info)]
+        L.qm_code_set_schedule.argtypes = [p, i32, p, p]
+        L.qm_code_get_schedule.argtypes = [p, ctypes.POINTER(i32), p, p]
+        L.qm_decoder_create.argtypes = [p, i32, p, i32, ctypes.POINTER(p)]
+        L.qm_decoder_destroy.argtypes = [p]
+        L.qm_decoder_workspace_bytes.argtypes = [p]
+        L.qm_decoder_workspace_bytes.restype = sz
+        L.qm_decoder_bind_workspace.argtypes = [p, p, sz]
+        L.qm_decoder_set_tuning.argtypes = [p, ctypes.POINTER(qm_tuning)]
+        L.qm_decoder_get_tuning.argtypes = [p, ctypes.POINTER(qm_tuning)]
+        L.qm_decode.argtypes = [p, p, p, i32, p, p, p, p]
+        L.qm_autotune.argtypes = [p, p, p, i32, ctypes.c_char_p, p]
+        for name in EXPORTED:
+            f = getattr(L, name)
+            if name not in ("qm_last_error", "qm_decoder_workspace_bytes", "qm_abi_version"):
+                f.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int) -> int:
+    if rc != QM_OK:
+        raise QMError(rc, lib().qm_last_error().decode())
+    return rc
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dptr(t) -> int | None:
+    """Device address of a torch tensor (None passes NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device buffer expected (torch CUDA tensor)")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return t.data_ptr()
+
+
+def _stream_handle(stream) -> int | None:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+# ----------------------------------------------------------- thin wrappers --
+
+def qm_abi_version() -> int:
+    return lib().qm_abi_version()
+
+
+def qm_code_create(shifts: np.ndarray, Z: int) -> ctypes.c_void_p:
+    sh = np.ascontiguousarray(shifts, dtype=np.int32)
+    mb, nb = sh.shape
+    out = ctypes.c_void_p()
+    _check(lib().qm_code_create(mb, nb, int(Z), _np_ptr(sh), ctypes.byref(out)))
+    return out
+
+
+def qm_code_destroy(code) -> None:
+    _check(lib().qm_code_destroy(code))
+
+
+def qm_code_get_info(code) -> qm_code_info:
+    info = qm_code_info()
+    _check(lib().qm_code_get_info(code, ctypes.byref(info)))
+    return info
+
+
+def qm_code_set_schedule(code, group_ptr, rows) -> None:
+    gp = np.ascontiguousarray(group_ptr, dtype=np.int32)
+    rw = np.ascontiguousarray(rows, dtype=np.int32)
+    _check(lib().qm_code_set_schedule(code, len(gp) - 1, _np_ptr(gp), _np_ptr(rw)))
+
+
+def qm_code_get_schedule(code):
+    info = qm_code_get_info(code)
+    G = ctypes.c_int32(0)
+    gp = np.zeros(info.mb + 1, dtype=np.int32)
+    rw = np.zeros(info.mb, dtype=np.int32)
+    _check(lib().qm_code_get_schedule(code, ctypes.byref(G), _np_ptr(gp), _np_ptr(rw)))
+    return gp[:G.value + 1].copy(), rw
+
+
+def qm_decoder_create(codes, frames_per_code, flags: int = 0) -> ctypes.c_void_p:
+    arr = (ctypes.c_void_p * len(codes))(*[c.value if isinstance(c, ctypes.c_void_p) else c for c in codes])
+    fpc = np.ascontiguousarray(frames_per_code, dtype=np.int32)
+    out = ctypes.c_void_p()
+    _check(lib().qm_decoder_create(arr, len(codes), _np_ptr(fpc), int(flags), ctypes.byref(out)))
+    return out
+
+
+def qm_decoder_destroy(dec) -> None:
+    _check(lib().qm_decoder_destroy(dec))
+
+
+def qm_decoder_workspace_bytes(dec) -> int:
+    return int(lib().qm_decoder_workspace_bytes(dec))
+
+
+def qm_decoder_bind_workspace(dec, ws) -> None:
+    _check(lib().qm_decoder_bind_workspace(dec, _dptr(ws), ws.numel() * ws.element_size()))
+
+
+def qm_decoder_set_tuning(dec, frames_per_tile=0, block=0, merge=1, persistent=0, graph=0) -> None:
+    t = qm_tuning(frames_per_tile, block, merge, persistent, graph)
+    _check(lib().qm_decoder_set_tuning(dec, ctypes.byref(t)))
+
+
+def qm_decoder_get_tuning(dec) -> dict:
+    t = qm_tuning()
+    _check(lib().qm_decoder_get_tuning(dec, ctypes.byref(t)))
+    return {f: getattr(t, f) for f, _ in qm_tuning._fields_}
+
+
+def qm_decode(dec, llr, syndrome, iters: int, hard, app, flags, stream=None) -> None:
+    _check(lib().qm_decode(dec, _dptr(llr), _dptr(syndrome), int(iters), _dptr(hard), _dptr(app),
+                           _dptr(flags), _stream_handle(stream)))
+
+
+def qm_autotune(dec, llr, syndrome, iters: int, cache_path: str | None = None, stream=None) -> None:
+    _check(lib().qm_autotune(dec, _dptr(llr), _dptr(syndrome), int(iters),
+                             cache_path.encode() if cache_path else None, _stream_handle(stream)))
+
+
+# ------------------------------------------------------ convenience layer --
+
+class Code:
+    """A QC base matrix loaded into the library."""
+
+    def __init__(self, shifts: np.ndarray, Z: int):
+        self.shifts = np.ascontiguousarray(shifts, dtype=np.int32)
+        self.Z = int(Z)
+        self.handle = qm_code_create(self.shifts, self.Z)
+        self.info = qm_code_get_info(self.handle)
+
+    @property
+    def n(self) -> int:
+        return int(self.info.n)
+
+    @property
+    def m(self) -> int:
+        return int(self.info.m)
+
+    def schedule(self):
+        return qm_code_get_schedule(self.handle)
+
+    def set_schedule(self, group_ptr, rows):
+        qm_code_set_schedule(self.handle, group_ptr, rows)
+        self.info = qm_code_get_info(self.handle)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.qm_code_destroy(h)
+            self.handle = None
+
+
+class Decoder:
+    """Decoder for frames_per_code[c] frames of codes[c] with a torch-owned
+    device workspace."""
+
+    def __init__(self, codes, frames_per_code, flags: int = 0, device="cuda", tuning: dict | None = None):
+        import torch
+        self.codes = list(codes)          # keep the codes alive
+        self.frames = [int(f) for f in frames_per_code]
+        self.flags = int(flags)
+        self.device = torch.device(device)
+        self.handle = qm_decoder_create([c.handle for c in self.codes], self.frames, self.flags)
+        self.workspace = None
+        if tuning:
+            qm_decoder_set_tuning(self.handle, **tuning)
+        self._bind()
+
+    def _bind(self):
+        import torch
+        nbytes = qm_decoder_workspace_bytes(self.handle)
+        if self.workspace is None or self.workspace.numel() < nbytes:
+            self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        qm_decoder_bind_workspace(self.handle, self.workspace)
+
+    def set_tuning(self, **kw):
+        cur = qm_decoder_get_tuning(self.handle)
+        cur.update(kw)
+        qm_decoder_set_tuning(self.handle, **cur)
+        self._bind()
+
+    def tuning(self) -> dict:
+        return qm_decoder_get_tuning(self.handle)
+
+    @property
+    def n_total(self) -> int:
+        return sum(f * c.n for f, c in zip(self.frames, self.codes))
+
+    @property
+    def m_total(self) -> int:
+        return sum(f * c.m for f, c in zip(self.frames, self.codes))
+
+    @property
+    def F_total(self) -> int:
+        return sum(self.frames)
+
+    def alloc_outputs(self, want_app: bool = True):
+        import torch
+        hard = torch.empty(self.n_total, dtype=torch.uint8, device=self.device)
+        app = torch.empty(self.n_total, dtype=torch.float32, device=self.device) if want_app else None
+        flags = torch.empty(self.F_total, dtype=torch.uint8, device=self.device)
+        return hard, app, flags
+
+    def decode(self, llr, syndrome, iters: int, out=None, want_app: bool = True, stream=None):
+        """llr: float32 [sum F_c n_c], syndrome: uint8 [sum F_c m_c] (device).
+        Returns (hard, app, flags) device tensors."""
+        if llr.numel() != self.n_total or syndrome.numel() != self.m_total:
+            raise ValueError("llr/syndrome size does not match the decoder's frames")
+        hard, app, flags = out if out is not None else self.alloc_outputs(want_app)
+        qm_decode(self.handle, llr.reshape(-1), syndrome.reshape(-1), iters, hard, app, flags, stream)
+        return hard, app, flags
+
+    def autotune(self, llr, syndrome, iters: int, cache_path: str | None = None, stream=None):
+        qm_autotune(self.handle, llr.reshape(-1), syndrome.reshape(-1), iters, cache_path, stream)
+        self._bind()
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.qm_decoder_destroy(h)
+            self.handle = None

@@ -1,0 +1,211 @@
+"""GPU decode (through the C ABI) against the FP64 oracle on the same seeded
+inputs.  Criteria: T0 -- after a few sweeps every APP within 1e-3 relative
+(absolute below 1) and hard decisions identical wherever |APP| > 1e-3;
+T1 -- per-frame syndrome flags identical; T2 -- frames the oracle decodes
+to a valid word have identical hard decisions and APPs within tolerance."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2004_09084_amd import qcmet as Q
+from paper_2004_09084_amd import workload as W
+from tests.gpu_util import APP_TOL, assert_tiered, compare, gpu_decode, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+SMALL = W.RATE01_SMALL        # rate 0.1, 45 x 50, Z = 64, n = 3200
+
+
+def _wl(spec, F, snr=None, seed=0, graph_seed=0):
+    return W.build(spec, F, graph_seed=graph_seed, frame_seed=seed, snr=snr)
+
+
+def test_zero_iterations_return_channel_decisions():
+    wl = _wl(SMALL, 4)
+    hard, app, fl = gpu_decode(wl.shifts, SMALL.Z, wl.llr, wl.s, 0)
+    assert np.array_equal(app, wl.llr)
+    assert np.array_equal(hard, (wl.llr < 0).astype(np.uint8))
+    _, _, flo, _ = oracle.decode_sp(wl.shifts, SMALL.Z, wl.llr, wl.s, 0)
+    assert np.array_equal(fl, flo)
+
+
+@pytest.mark.parametrize("T", [1, 2, 3])
+def test_first_sweeps_match_oracle_everywhere(T):
+    wl = _wl(SMALL, 4)
+    say(f"T0 small T={T}")
+    hard, app, fl = gpu_decode(wl.shifts, SMALL.Z, wl.llr, wl.s, T)
+    appo, hardo, flo, _ = oracle.decode_sp(wl.shifts, SMALL.Z, wl.llr, wl.s, T)
+    rows = compare(app, hard, fl, appo, hardo, flo)
+    say(rows)
+    for r in rows:
+        assert r["app_viol"] == 0 and r["bits_diff_confident"] == 0, r
+    assert np.array_equal(fl, flo)
+
+
+def test_small_config_50_iterations():
+    # rate 0.1, Z = 64, 4 frames, SNR 0.161, 50 iterations
+    wl = _wl(SMALL, 4)
+    hard, app, fl = gpu_decode(wl.shifts, SMALL.Z, wl.llr, wl.s, 50)
+    appo, hardo, flo, _ = oracle.decode_sp(wl.shifts, SMALL.Z, wl.llr, wl.s, 50)
+    rows = compare(app, hard, fl, appo, hardo, flo)
+    say("small cfg 50 it:", rows)
+    assert_tiered(rows)
+
+
+@pytest.mark.parametrize("snr", [0.45, 0.8])
+def test_converging_frames_are_bit_exact(snr):
+    wl = _wl(SMALL, 24, snr=snr, seed=3)
+    hard, app, fl = gpu_decode(wl.shifts, SMALL.Z, wl.llr, wl.s, 50)
+    appo, hardo, flo, _ = oracle.decode_sp(wl.shifts, SMALL.Z, wl.llr, wl.s, 50)
+    rows = compare(app, hard, fl, appo, hardo, flo)
+    say(f"snr {snr}: converged {int(flo.sum())}/24", [r for r in rows if r["bits_diff"] or r["app_viol"]])
+    assert_tiered(rows)
+    assert flo.sum() >= 1
+
+
+def test_ragged_lift_and_padded_frames():
+    # Z = 37 and 5 frames: partial workgroups, a padded frame tile
+    spec = SMALL.with_Z(37)
+    wl = _wl(spec, 5, snr=0.6, seed=4)
+    for T in (1, 2):
+        hard, app, fl = gpu_decode(wl.shifts, spec.Z, wl.llr, wl.s, T)
+        appo, hardo, flo, _ = oracle.decode_sp(wl.shifts, spec.Z, wl.llr, wl.s, T)
+        for r in compare(app, hard, fl, appo, hardo, flo):
+            assert r["app_viol"] == 0 and r["bits_diff_confident"] == 0, r
+    hard, app, fl = gpu_decode(wl.shifts, spec.Z, wl.llr, wl.s, 40)
+    appo, hardo, flo, _ = oracle.decode_sp(wl.shifts, spec.Z, wl.llr, wl.s, 40)
+    assert_tiered(compare(app, hard, fl, appo, hardo, flo))
+
+
+def test_rate002_and_rate005_structures_small_lift():
+    for spec in (W.RATE005.with_Z(24), W.RATE002.with_Z(24)):
+        wl = _wl(spec, 6, snr=spec.snr * 3, seed=5)
+        for T in (1, 3):
+            hard, app, fl = gpu_decode(wl.shifts, spec.Z, wl.llr, wl.s, T)
+            appo, hardo, flo, _ = oracle.decode_sp(wl.shifts, spec.Z, wl.llr, wl.s, T)
+            for r in compare(app, hard, fl, appo, hardo, flo):
+                assert r["app_viol"] == 0 and r["bits_diff_confident"] == 0, (spec.name, T, r)
+
+
+def test_zero_noise_frames_decode_to_truth():
+    X, L, S = W.make_frames(W.make_code(SMALL, 0), SMALL.Z, 0.161, 8, seed=7, zero_noise=True)
+    hard, app, fl = gpu_decode(W.make_code(SMALL, 0), SMALL.Z, L, S, 5)
+    assert fl.all() and np.array_equal(hard, X)
+
+
+def test_codes_without_degree1_columns_and_tiny_checks():
+    # a general QC code: no degree-1 columns, a row with a single entry,
+    # an empty column; Z = 5
+    H = np.array([[0, 1, -1, 3, -1], [2, -1, 4, 0, -1], [-1, 3, 1, -1, -1], [-1, -1, -1, 2, -1]], dtype=np.int32)
+    Z = 5
+    rng = np.random.default_rng(8)
+    from tests.helpers import dense_H, frame_for
+    Hd = dense_H(H, Z)
+    L, S = [], []
+    for f in range(3):
+        x = rng.integers(0, 2, Hd.shape[1]).astype(np.uint8)
+        l, s = frame_for(Hd, x, 1.0, rng)
+        L.append(l); S.append(s)
+    L, S = np.array(L), np.array(S)
+    for T in (1, 4):
+        hard, app, fl = gpu_decode(H, Z, L, S, T)
+        appo, hardo, flo, _ = oracle.decode_sp(H, Z, L, S, T)
+        for r in compare(app, hard, fl, appo, hardo, flo):
+            assert r["app_viol"] == 0 and r["bits_diff_confident"] == 0 and r["flag_o"] == r["flag_g"], r
+
+
+# ------------------------------------------------- FP16 message storage --
+
+@pytest.mark.parametrize("T", [1, 2])
+def test_fp16_messages_match_oracle_binary16_mode(T):
+    wl = _wl(SMALL, 4)
+    hard, app, fl = gpu_decode(wl.shifts, SMALL.Z, wl.llr, wl.s, T, flags=Q.QM_MSG_FP16)
+    appo, hardo, flo, _ = oracle.decode_sp(wl.shifts, SMALL.Z, wl.llr, wl.s, T, fp16_messages=True)
+    for r in compare(app, hard, fl, appo, hardo, flo):
+        assert r["app_viol"] == 0 and r["bits_diff_confident"] == 0, r
+
+
+def test_fp16_messages_converging_frames():
+    wl = _wl(SMALL, 16, snr=0.8, seed=3)
+    hard, app, fl = gpu_decode(wl.shifts, SMALL.Z, wl.llr, wl.s, 40, flags=Q.QM_MSG_FP16)
+    appo, hardo, flo, _ = oracle.decode_sp(wl.shifts, SMALL.Z, wl.llr, wl.s, 40, fp16_messages=True)
+    rows = compare(app, hard, fl, appo, hardo, flo)
+    say("fp16 converging:", int(flo.sum()), [r for r in rows if r["bits_diff"] or r["app_viol"]])
+    assert_tiered(rows)
+
+
+# ------------------------------------------------- GPU-vs-GPU invariants --
+
+def test_tunings_are_bit_identical():
+    wl = _wl(SMALL, 16, snr=0.3, seed=2)
+    ref = gpu_decode(wl.shifts, SMALL.Z, wl.llr, wl.s, 12)
+    for tun in (dict(frames_per_tile=1), dict(frames_per_tile=4, block=64), dict(frames_per_tile=8, block=512),
+                dict(frames_per_tile=16, merge=0), dict(frames_per_tile=2, block=128, merge=0),
+                dict(frames_per_tile=16, graph=1)):
+        got = gpu_decode(wl.shifts, SMALL.Z, wl.llr, wl.s, 12, tuning=tun)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]) and np.array_equal(got[2], ref[2]), tun
+
+
+def test_frames_are_independent_on_gpu():
+    wl = _wl(SMALL, 12, snr=0.3, seed=6)
+    allf = gpu_decode(wl.shifts, SMALL.Z, wl.llr, wl.s, 9)
+    part = gpu_decode(wl.shifts, SMALL.Z, wl.llr[5:8], wl.s[5:8], 9)
+    assert np.array_equal(allf[1][5:8], part[1]) and np.array_equal(allf[0][5:8], part[0])
+
+
+def test_multi_code_decoder_equals_single_code_decoders():
+    import torch
+    specs = [SMALL, W.RATE005.with_Z(16), W.RATE002.with_Z(16)]
+    Fs = [6, 3, 5]
+    wls = [_wl(s, F, snr=s.snr * 2, seed=1) for s, F in zip(specs, Fs)]
+    codes = [Q.Code(w.shifts, s.Z) for w, s in zip(wls, specs)]
+    dec = Q.Decoder(codes, Fs)
+    L = np.concatenate([w.llr.reshape(-1) for w in wls])
+    S = np.concatenate([w.s.reshape(-1) for w in wls])
+    hard, app, fl = dec.decode(to_dev(L), to_dev(S), 7)
+    torch.cuda.synchronize()
+    hard, app, fl = hard.cpu().numpy(), app.cpu().numpy(), fl.cpu().numpy()
+    on = of = 0
+    for w, s, F in zip(wls, specs, Fs):
+        h1, a1, f1 = gpu_decode(w.shifts, s.Z, w.llr, w.s, 7)
+        assert np.array_equal(app[on:on + F * s.n], a1.reshape(-1))
+        assert np.array_equal(hard[on:on + F * s.n], h1.reshape(-1))
+        assert np.array_equal(fl[of:of + F], f1)
+        on += F * s.n
+        of += F
+
+
+def test_graph_replays_match_eager():
+    import torch
+    wl = _wl(SMALL, 8, snr=0.3, seed=9)
+    ref = gpu_decode(wl.shifts, SMALL.Z, wl.llr, wl.s, 6)
+    code = Q.Code(wl.shifts, SMALL.Z)
+    dec = Q.Decoder([code], [8], tuning=dict(graph=1))
+    L, S = to_dev(wl.llr), to_dev(wl.s)
+    out = dec.alloc_outputs()
+    for rep in range(4):
+        dec.decode(L, S, 6, out=out)
+        torch.cuda.synchronize()
+        junk = torch.randn(1 << 16, device="cuda").sum()   # eager work between replays
+        torch.cuda.synchronize()
+        assert np.array_equal(out[1].cpu().numpy().reshape(8, -1), ref[1]), rep
+        assert np.array_equal(out[2].cpu().numpy(), ref[2]), rep
+        out[1].fill_(7.0)
+        out[0].fill_(3)
+
+
+def test_validation_flag_rejects_bad_inputs():
+    wl = _wl(SMALL, 2)
+    code = Q.Code(wl.shifts, SMALL.Z)
+    dec = Q.Decoder([code], [2], flags=Q.QM_VALIDATE)
+    L = wl.llr.copy()
+    L[1, 17] = np.nan
+    with pytest.raises(Q.QMError) as e:
+        dec.decode(to_dev(L), to_dev(wl.s), 2)
+    assert e.value.code == Q.QM_ERR_INPUT
+    S = wl.s.copy()
+    S[0, 3] = 2
+    with pytest.raises(Q.QMError) as e:
+        dec.decode(to_dev(wl.llr), to_dev(S), 2)
+    assert e.value.code == Q.QM_ERR_INPUT
+    hard, app, fl = dec.decode(to_dev(wl.llr), to_dev(wl.s), 2)   # clean inputs pass

@@ -1,0 +1,185 @@
+"""Decode-throughput benchmark on one MI355X.
+
+A step is one qm_decode of the whole batch: init, `iters` layered
+sum-product sweeps, syndrome flags and the frame-major outputs.  Default
+workload: rate-0.1 QC-MET-LDPC code (45 x 50 base, Z = 20000, n = 10^6),
+128 frames at SNR 0.161, 200 iterations, FP32 messages; the inputs are
+generated once (seeded, synthetic) and are resident in HBM before the timed
+region starts.
+
+Prints one JSON line: decoded Mbit/s (frames x 10^6 bits per second), the
+layer kernel's achieved algorithmic HBM bandwidth against the 8 TB/s peak
+(timed live with HIP events on the decode stream), FER at the SNR, and the
+FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "decoded Mbit/s (N frames x 10^6 bits, fixed iters) + HBM GB/s; FER at SNR"
+
+WORKLOADS = {
+    # name: (spec name, frames, iterations)
+    "r0.1": ("r0.1_Z20000", 128, 200),
+    "r0.05": ("r0.05_Z10000", 128, 200),
+    "r0.02": ("r0.02_Z10000", 128, 200),
+    "small": ("r0.1_Z64", 4, 50),
+}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "api.cpp", "qcmet_internal.h"):
+        with open(os.path.join(ROOT, "paper_2004_09084_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload_key: str, fp16: bool):
+    """HBM bytes per layer launch from the committed rocprofv3 counter runs,
+    if they were taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "layer_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+    except Exception:
+        return None
+    key = f"{workload_key}{'_fp16' if fp16 else ''}"
+    ent = data.get(key)
+    if not ent or ent.get("kernel_hash") != kernel_source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(spec, shifts, frames_llr, frames_s, iters_full: int):
+    """The FP64 oracle, as it stands, on a bounded sample: `threads` frames
+    (one per host core, at most 16) for 2 iterations; scaled to Mbit/s at the
+    full iteration count."""
+    import oracle
+    threads = min(16, os.cpu_count() or 1)
+    F = min(threads, frames_llr.shape[0])
+    sample_iters = 2
+    t0 = time.perf_counter()
+    _, _, _, used = oracle.decode_sp(shifts, spec.Z, frames_llr[:F], frames_s[:F], sample_iters, threads=threads)
+    dt = time.perf_counter() - t0
+    per_decode = dt * iters_full / sample_iters          # seconds for F frames at full iterations
+    return {"value": round(F * spec.n / 1e6 / per_decode, 4), "unit": "Mbit/s", "cores": int(used),
+            "kind": "oracle",
+            "sample": f"{F} frames x {sample_iters} iterations of the same code and inputs "
+                      f"({dt:.1f} s wall), scaled to {iters_full} iterations"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="r0.1", choices=sorted(WORKLOADS))
+    ap.add_argument("--frames", type=int, default=None)
+    ap.add_argument("--iters", type=int, default=None)
+    ap.add_argument("--fp16", action="store_true", help="store messages as binary16")
+    ap.add_argument("--tuning", default=None, help="JSON dict of qm_tuning fields")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build decodes on a single MI355X "
+              "(frames would shard across GPUs with no exchange; not built). Use --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2004_09084_amd import qcmet as Q
+    from paper_2004_09084_amd import workload as W
+
+    spec_name, F, iters = WORKLOADS[args.workload]
+    F = args.frames or F
+    iters = args.iters if args.iters is not None else iters
+    spec = W.SPECS[spec_name]
+    torch.cuda.set_device(0)
+
+    print(f"[bench] generating {F} frames of {spec.name} (n={spec.n}) at SNR {spec.snr}", file=sys.stderr, flush=True)
+    wl = W.build(spec, F, graph_seed=0, frame_seed=0)
+    llr = torch.from_numpy(wl.llr.reshape(-1)).cuda()
+    syn = torch.from_numpy(wl.s.reshape(-1)).cuda()
+    code = Q.Code(wl.shifts, spec.Z)
+    tuning = json.loads(args.tuning) if args.tuning else None
+    dec = Q.Decoder([code], [F], flags=Q.QM_MSG_FP16 if args.fp16 else 0, tuning=tuning)
+    out = dec.alloc_outputs(want_app=True)
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        dec.decode(llr, syn, iters, out=out)
+    torch.cuda.synchronize()
+    print(f"[bench] warmup done; timing {args.steps} steps", file=sys.stderr, flush=True)
+
+    dec.set_profiling(not args.no_profile)
+    dec.profile(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        dec.decode(llr, syn, iters, out=out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = dec.profile(reset=True)
+    dec.set_profiling(False)
+
+    ms_per_step = dt * 1e3 / args.steps
+    mbit_s = F * spec.n / 1e6 / (dt / args.steps)
+    hard = out[0].cpu().numpy().reshape(F, -1)
+    flags = out[2].cpu().numpy()
+    fer = float((hard != wl.x).any(axis=1).mean())
+    syn_fail = float(1.0 - flags.mean())
+
+    roofline = None
+    if prof["launches"] > 0:
+        avg_ms = prof["layer_ms"] / prof["launches"]
+        bytes_per_launch = prof["layer_bytes"] / prof["launches"]
+        achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+        traffic = load_traffic(args.workload, args.fp16)
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    "kernel": "k_layer_sp", "avg_launch_us": round(avg_ms * 1e3, 3),
+                    "algorithmic_bytes_per_launch": round(bytes_per_launch),
+                    "launches_timed": prof["launches"],
+                    "sweep_ms": round(prof["sweep_ms"] / max(prof["sweeps"], 1), 4)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(spec, wl.shifts, wl.llr, wl.s, iters)
+
+    tun = dec.tuning()
+    line = {
+        "metric": METRIC, "value": round(mbit_s, 3), "unit": "Mbit/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if not args.fp16 else "f32 (binary16 messages)", "data": "synthetic",
+        "config": {"workload": f"{spec.name}: rate {spec.rate:.2f} QC-MET-LDPC, {spec.mb}x{spec.nb} base, Z={spec.Z}, "
+                               f"n={spec.n}, {F} frames, {iters} iterations, SNR {spec.snr}, layered sum-product, "
+                               f"{'FP16' if args.fp16 else 'FP32'} messages",
+                   "frames": F, "iterations": iters, "n": spec.n, "snr": spec.snr,
+                   "layers": int(code.info.G), "tuning": tun},
+        "fer": fer, "syndrome_fail_rate": syn_fail,
+        "hbm_gbs": None if roofline is None else roofline["achieved"],
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

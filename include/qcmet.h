@@ -146,6 +146,28 @@ int qm_decode(qm_decoder *dec, const float *llr, const uint8_t *syndrome, int32_
 int qm_autotune(qm_decoder *dec, const float *llr, const uint8_t *syndrome, int32_t iters,
                 const char *cache_path, void *stream);
 
+/* Live timing of the layer kernel (the decode's hot loop).
+ * qm_decoder_set_profiling(dec, 1): every later qm_decode records a pair of
+ * HIP events on its stream around each layer launch of one sweep (the middle
+ * one, never the last), and a pair around that whole sweep.  Graph replay is
+ * bypassed while profiling.  qm_decoder_get_profile waits for the recorded
+ * events, sums them into *out and, if reset, forgets them.
+ * layer_bytes counts the algorithmic HBM bytes of the timed launches: per
+ * check and frame 4 (its degree-1 term) plus, per degree>=2 edge, the message
+ * read and written (2 x 4 bytes, or 2 x 2 with QM_MSG_FP16) and the APP read
+ * and written (2 x 4 bytes). */
+typedef struct {
+    int32_t launches;     /* layer launches timed */
+    int32_t sweeps;       /* sweeps timed */
+    double layer_ms;      /* summed duration of the timed layer launches */
+    double sweep_ms;      /* summed duration of the timed sweeps */
+    double layer_bytes;   /* algorithmic bytes of the timed layer launches */
+    double checks;        /* check-frame updates in the timed launches */
+} qm_profile;
+
+int qm_decoder_set_profiling(qm_decoder *dec, int32_t enable);
+int qm_decoder_get_profile(qm_decoder *dec, qm_profile *out, int32_t reset);
+
 #ifdef __cplusplus
 }
 #endif

@@ -149,6 +149,12 @@ struct qm_decoder {
     const void *gkey[7] = {};
     int32_t giters = -1;
     hipStream_t cap = nullptr;  // private stream the graph is captured on
+    // live profiling of the layer kernel
+    int32_t profiling = 0;
+    std::vector<hipEvent_t> ev_pool;     // created lazily, reused after a reset
+    size_t ev_used = 0;
+    struct Pending { size_t a, b; double bytes, checks; int kind; };  // kind 0: layer, 1: sweep
+    std::vector<Pending> pending;
 };
 
 namespace {
@@ -186,6 +192,27 @@ void layout(qm_decoder &d) {
     d.oErr = off;
     off = align_up(off + 4);
     d.total = off;
+}
+
+int take_event(qm_decoder &d, hipEvent_t *ev, size_t *index) {
+    if (d.ev_used == d.ev_pool.size()) {
+        hipEvent_t e;
+        QM_HIP(hipEventCreate(&e));
+        d.ev_pool.push_back(e);
+    }
+    *index = d.ev_used;
+    *ev = d.ev_pool[d.ev_used++];
+    return QM_OK;
+}
+
+// algorithmic bytes / check updates of one layer launch over `rows`
+void layer_work(const Slot &s, const RowDesc *hrows, int nrows, int msg16, double *bytes, double *checks) {
+    const double per_edge = msg16 ? 12.0 : 16.0;
+    double b = 0.0;
+    for (int r = 0; r < nrows; ++r) b += per_edge * hrows[r].d + 4.0;
+    const double fz = (double)s.F * s.code->Z;
+    *bytes = b * fz;
+    *checks = (double)nrows * fz;
 }
 
 void drop_graph(qm_decoder &d) {
@@ -231,20 +258,55 @@ int enqueue_decode(qm_decoder &d, const float *llr, const uint8_t *syn, int32_t 
         la.strideR = ((int64_t)c.nent1 * c.Z) << g.ft_log2;
         la.strideK = (int64_t)s.m << g.ft_log2;
         const int G = (int)s.gptr.size() - 1;
+        // the profiled sweep: the middle one, never the last (which also
+        // forms the degree-1 APPs)
+        const int tprof = (d.profiling && iters >= 2) ? (iters - 1) / 2 : -1;
+        auto launch = [&](int p0, int nr, bool prof) -> int {
+            la.rows = rows + p0;
+            la.nrows = nr;
+            if (!prof) {
+                QM_HIP(qm_launch_layer(la, msg16, s.maxd_t, d.tun.block, st));
+                return QM_OK;
+            }
+            hipEvent_t e0, e1;
+            size_t i0, i1;
+            int rc = take_event(d, &e0, &i0);
+            if (rc == QM_OK) rc = take_event(d, &e1, &i1);
+            if (rc != QM_OK) return rc;
+            QM_HIP(hipEventRecord(e0, st));
+            QM_HIP(qm_launch_layer(la, msg16, s.maxd_t, d.tun.block, st));
+            QM_HIP(hipEventRecord(e1, st));
+            qm_decoder::Pending pd{i0, i1, 0.0, 0.0, 0};
+            layer_work(s, s.hrows.data() + p0, nr, msg16, &pd.bytes, &pd.checks);
+            d.pending.push_back(pd);
+            return QM_OK;
+        };
         for (int t = 0; t < iters; ++t) {
             la.last = (t == iters - 1) ? 1 : 0;
+            const bool prof = (t == tprof);
+            size_t sw0 = 0, sw1 = 0;
+            hipEvent_t es0 = nullptr, es1 = nullptr;
+            if (prof) {
+                const int rc = take_event(d, &es0, &sw0);
+                if (rc != QM_OK) return rc;
+                QM_HIP(hipEventRecord(es0, st));
+            }
             for (int gi = 0; gi < G; ++gi) {
                 if (d.tun.merge) {
-                    la.rows = rows + s.gptr[gi];
-                    la.nrows = s.gptr[gi + 1] - s.gptr[gi];
-                    QM_HIP(qm_launch_layer(la, msg16, s.maxd_t, d.tun.block, st));
+                    const int rc = launch(s.gptr[gi], s.gptr[gi + 1] - s.gptr[gi], prof);
+                    if (rc != QM_OK) return rc;
                 } else {
                     for (int p = s.gptr[gi]; p < s.gptr[gi + 1]; ++p) {
-                        la.rows = rows + p;
-                        la.nrows = 1;
-                        QM_HIP(qm_launch_layer(la, msg16, s.maxd_t, d.tun.block, st));
+                        const int rc = launch(p, 1, prof);
+                        if (rc != QM_OK) return rc;
                     }
                 }
+            }
+            if (prof) {
+                const int rc = take_event(d, &es1, &sw1);
+                if (rc != QM_OK) return rc;
+                QM_HIP(hipEventRecord(es1, st));
+                d.pending.push_back(qm_decoder::Pending{sw0, sw1, 0.0, 0.0, 1});
             }
         }
         QM_HIP(qm_launch_syndrome(A, S, rows, c.mb, fl, g, st));
@@ -413,6 +475,7 @@ int qm_decoder_destroy(qm_decoder *d) {
     if (!d) return QM_OK;
     drop_graph(*d);
     if (d->cap) (void)hipStreamDestroy(d->cap);
+    for (hipEvent_t e : d->ev_pool) (void)hipEventDestroy(e);
     delete d;
     return QM_OK;
 }
@@ -478,7 +541,7 @@ int qm_decode(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t iters
         if (h & 1u) return fail(QM_ERR_INPUT, "non-finite channel LLR");
         if (h & 2u) return fail(QM_ERR_INPUT, "syndrome value other than 0/1");
     }
-    if (!d->tun.graph) return enqueue_decode(*d, llr, syn, iters, hard, app, flags, st);
+    if (!d->tun.graph || d->profiling) return enqueue_decode(*d, llr, syn, iters, hard, app, flags, st);
 
     const void *key[7] = {llr, syn, hard, app, flags, stream, d->ws};
     if (!d->gexec || d->giters != iters || std::memcmp(key, d->gkey, sizeof(key)) != 0) {
@@ -501,6 +564,36 @@ int qm_decode(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t iters
         d->giters = iters;
     }
     QM_HIP(hipGraphLaunch(d->gexec, st));
+    return QM_OK;
+}
+
+int qm_decoder_set_profiling(qm_decoder *d, int32_t enable) {
+    if (!d) return fail(QM_ERR_INVALID_ARG, "decoder is NULL");
+    d->profiling = enable ? 1 : 0;
+    return QM_OK;
+}
+
+int qm_decoder_get_profile(qm_decoder *d, qm_profile *out, int32_t reset) {
+    if (!d || !out) return fail(QM_ERR_INVALID_ARG, "NULL argument");
+    std::memset(out, 0, sizeof(*out));
+    for (const auto &p : d->pending) {
+        QM_HIP(hipEventSynchronize(d->ev_pool[p.b]));
+        float ms = 0.0f;
+        QM_HIP(hipEventElapsedTime(&ms, d->ev_pool[p.a], d->ev_pool[p.b]));
+        if (p.kind == 0) {
+            out->launches++;
+            out->layer_ms += ms;
+            out->layer_bytes += p.bytes;
+            out->checks += p.checks;
+        } else {
+            out->sweeps++;
+            out->sweep_ms += ms;
+        }
+    }
+    if (reset) {
+        d->pending.clear();
+        d->ev_used = 0;
+    }
     return QM_OK;
 }
 

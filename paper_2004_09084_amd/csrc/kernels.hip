@@ -146,8 +146,9 @@ __global__ void __launch_bounds__(512) k_layer_sp(const LayerArgs a) {
 #pragma unroll
         for (int j = 0; j < MAXD; ++j)
             if (j < d) sd += ph[j];
-        // s = sign(K) ^ [lam < 0]; the degree-1 target excludes only itself
-        const uint32_t nd = neg ^ (__float_as_uint(kap) >> 31) ^ (uint32_t)(lam < 0.0f);
+        // neg = s ^ [lam < 0] ^ xor_j [q_j < 0]; the degree-1 target excludes
+        // only its own q (= lam): s ^ xor_j [q_j < 0] = neg ^ [lam < 0]
+        const uint32_t nd = neg ^ (uint32_t)(lam < 0.0f);
         const MsgT rm = to_msg<MsgT>(with_sign(qm_phi(qm_clip(sd)), nd));
         A[off] = lam + (float)rm;
     }

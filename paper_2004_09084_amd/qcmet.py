@@ -38,7 +38,8 @@ EXPORTED = [
     "qm_abi_version", "qm_last_error", "qm_code_create", "qm_code_destroy", "qm_code_get_info",
     "qm_code_set_schedule", "qm_code_get_schedule", "qm_decoder_create", "qm_decoder_destroy",
     "qm_decoder_workspace_bytes", "qm_decoder_bind_workspace", "qm_decoder_set_tuning",
-    "qm_decoder_get_tuning", "qm_decode", "qm_autotune",
+    "qm_decoder_get_tuning", "qm_decode", "qm_autotune", "qm_decoder_set_profiling",
+    "qm_decoder_get_profile",
 ]
 
 
@@ -59,6 +60,11 @@ class qm_code_info(ctypes.Structure):
 class qm_tuning(ctypes.Structure):
     _fields_ = [("frames_per_tile", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("merge", ctypes.c_int32), ("persistent", ctypes.c_int32), ("graph", ctypes.c_int32)]
+
+
+class qm_profile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int32), ("sweeps", ctypes.c_int32), ("layer_ms", ctypes.c_double),
+                ("sweep_ms", ctypes.c_double), ("layer_bytes", ctypes.c_double), ("checks", ctypes.c_double)]
 
 
 _lib = None
@@ -89,6 +95,8 @@ def lib():
         L.qm_decoder_get_tuning.argtypes = [p, ctypes.POINTER(qm_tuning)]
         L.qm_decode.argtypes = [p, p, p, i32, p, p, p, p]
         L.qm_autotune.argtypes = [p, p, p, i32, ctypes.c_char_p, p]
+        L.qm_decoder_set_profiling.argtypes = [p, i32]
+        L.qm_decoder_get_profile.argtypes = [p, ctypes.POINTER(qm_profile), i32]
         for name in EXPORTED:
             f = getattr(L, name)
             if name not in ("qm_last_error", "qm_decoder_workspace_bytes", "qm_abi_version"):
@@ -204,6 +212,16 @@ def qm_autotune(dec, llr, syndrome, iters: int, cache_path: str | None = None, s
                              cache_path.encode() if cache_path else None, _stream_handle(stream)))
 
 
+def qm_decoder_set_profiling(dec, enable: bool) -> None:
+    _check(lib().qm_decoder_set_profiling(dec, 1 if enable else 0))
+
+
+def qm_decoder_get_profile(dec, reset: bool = True) -> dict:
+    p = qm_profile()
+    _check(lib().qm_decoder_get_profile(dec, ctypes.byref(p), 1 if reset else 0))
+    return {f: getattr(p, f) for f, _ in qm_profile._fields_}
+
+
 # ------------------------------------------------------ convenience layer --
 
 class Code:
@@ -296,6 +314,12 @@ class Decoder:
         hard, app, flags = out if out is not None else self.alloc_outputs(want_app)
         qm_decode(self.handle, llr.reshape(-1), syndrome.reshape(-1), iters, hard, app, flags, stream)
         return hard, app, flags
+
+    def set_profiling(self, enable: bool):
+        qm_decoder_set_profiling(self.handle, enable)
+
+    def profile(self, reset: bool = True) -> dict:
+        return qm_decoder_get_profile(self.handle, reset)
 
     def autotune(self, llr, syndrome, iters: int, cache_path: str | None = None, stream=None):
         qm_autotune(self.handle, llr.reshape(-1), syndrome.reshape(-1), iters, cache_path, stream)

@@ -9,7 +9,7 @@ import pytest
 import oracle
 from paper_2004_09084_amd import qcmet as Q
 from paper_2004_09084_amd import workload as W
-from tests.gpu_util import APP_TOL, assert_tiered, compare, gpu_decode, say, to_dev
+from tests.gpu_util import APP_TOL, FP16_EXTRA, assert_tiered, compare, gpu_decode, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -121,15 +121,19 @@ def test_fp16_messages_match_oracle_binary16_mode(T):
     wl = _wl(SMALL, 4)
     hard, app, fl = gpu_decode(wl.shifts, SMALL.Z, wl.llr, wl.s, T, flags=Q.QM_MSG_FP16)
     appo, hardo, flo, _ = oracle.decode_sp(wl.shifts, SMALL.Z, wl.llr, wl.s, T, fp16_messages=True)
-    for r in compare(app, hard, fl, appo, hardo, flo):
+    rows = compare(app, hard, fl, appo, hardo, flo, extra=FP16_EXTRA)
+    say(f"fp16 T={T}", rows)
+    for r in rows:
         assert r["app_viol"] == 0 and r["bits_diff_confident"] == 0, r
+        # rounding-boundary disagreements are rare
+        assert r["strict_viol"] <= 1e-3 * SMALL.n, r
 
 
 def test_fp16_messages_converging_frames():
     wl = _wl(SMALL, 16, snr=0.8, seed=3)
     hard, app, fl = gpu_decode(wl.shifts, SMALL.Z, wl.llr, wl.s, 40, flags=Q.QM_MSG_FP16)
     appo, hardo, flo, _ = oracle.decode_sp(wl.shifts, SMALL.Z, wl.llr, wl.s, 40, fp16_messages=True)
-    rows = compare(app, hard, fl, appo, hardo, flo)
+    rows = compare(app, hard, fl, appo, hardo, flo, extra=FP16_EXTRA)
     say("fp16 converging:", int(flo.sum()), [r for r in rows if r["bits_diff"] or r["app_viol"]])
     assert_tiered(rows)
 

@@ -91,6 +91,8 @@ def main():
     ap.add_argument("--tuning", default=None, help="JSON dict of qm_tuning fields")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -120,6 +122,16 @@ def main():
     dec = Q.Decoder([code], [F], flags=Q.QM_MSG_FP16 if args.fp16 else 0, tuning=tuning)
     out = dec.alloc_outputs(want_app=True)
     torch.cuda.synchronize()
+
+    if args.calib_copy_mb:
+        # known traffic for the counter runs: a fill writes N bytes, an
+        # elementwise multiply reads N and writes N bytes
+        src = torch.empty(args.calib_copy_mb << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 2.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
 
     for _ in range(args.warmup):
         dec.decode(llr, syn, iters, out=out)

@@ -73,11 +73,13 @@ typedef struct {
 typedef struct {
     int32_t frames_per_tile;  /* FT: frames interleaved fastest in HBM; power of two
                                  dividing the padded frame count; 0 = default */
-    int32_t block;            /* threads per workgroup of the layer kernel (64..1024, mult. of 64) */
+    int32_t block;            /* threads per workgroup of the layer kernel (64..256, mult. of 64) */
     int32_t merge;            /* 1: run each merged layer as one launch; 0: one launch per row
                                  (same row order, bit-identical results) */
     int32_t persistent;       /* 1: persistent kernel for the whole iteration loop */
     int32_t graph;            /* 1: replay a captured hipGraph */
+    int32_t frames_per_lane;  /* 1 or 2 adjacent frames per GPU lane (<= frames_per_tile);
+                                 0 = default (2).  4 is rejected (QM_ERR_UNSUPPORTED). */
 } qm_tuning;
 
 int qm_abi_version(void);
@@ -120,7 +122,7 @@ int qm_decoder_destroy(qm_decoder *dec);
 /* Device workspace: size it, allocate it (any allocator, 256-byte aligned),
  * bind it.  The decoder borrows it; the caller frees it after the last
  * queued decode has completed.  Binding copies the schedule descriptors to
- * the device (synchronously) and must be repeated after qm_decoder_set_tuning. */
+ * the device (synchronously).  The size does not depend on the tuning. */
 size_t qm_decoder_workspace_bytes(const qm_decoder *dec);
 int qm_decoder_bind_workspace(qm_decoder *dec, void *device_ptr, size_t bytes);
 int qm_decoder_set_tuning(qm_decoder *dec, const qm_tuning *tuning);

@@ -253,7 +253,9 @@ int enqueue_decode(qm_decoder &d, const float *llr, const uint8_t *syn, int32_t 
         la.Z = c.Z;
         la.ft_log2 = g.ft_log2;
         la.ntiles = g.ntiles;
-        la.chunks = ((c.Z << g.ft_log2) + d.tun.block - 1) / d.tun.block;
+        la.fpl = std::min(d.tun.frames_per_lane, 1 << g.ft_log2);
+        const int lanes = (c.Z << g.ft_log2) / la.fpl;
+        la.chunks = (lanes + d.tun.block - 1) / d.tun.block;
         la.strideA = (int64_t)s.n << g.ft_log2;
         la.strideR = ((int64_t)c.nent1 * c.Z) << g.ft_log2;
         la.strideK = (int64_t)s.m << g.ft_log2;
@@ -265,7 +267,7 @@ int enqueue_decode(qm_decoder &d, const float *llr, const uint8_t *syn, int32_t 
             la.rows = rows + p0;
             la.nrows = nr;
             if (!prof) {
-                QM_HIP(qm_launch_layer(la, msg16, s.maxd_t, d.tun.block, st));
+                QM_HIP(qm_launch_layer(la, msg16, s.maxd_t, la.fpl, d.tun.block, st));
                 return QM_OK;
             }
             hipEvent_t e0, e1;
@@ -274,7 +276,7 @@ int enqueue_decode(qm_decoder &d, const float *llr, const uint8_t *syn, int32_t 
             if (rc == QM_OK) rc = take_event(d, &e1, &i1);
             if (rc != QM_OK) return rc;
             QM_HIP(hipEventRecord(e0, st));
-            QM_HIP(qm_launch_layer(la, msg16, s.maxd_t, d.tun.block, st));
+            QM_HIP(qm_launch_layer(la, msg16, s.maxd_t, la.fpl, d.tun.block, st));
             QM_HIP(hipEventRecord(e1, st));
             qm_decoder::Pending pd{i0, i1, 0.0, 0.0, 0};
             layer_work(s, s.hrows.data() + p0, nr, msg16, &pd.bytes, &pd.checks);
@@ -452,13 +454,16 @@ int qm_decoder_create(const qm_code *const *codes, int32_t ncodes, const int32_t
         s.n = (int64_t)s.code->nb * s.code->Z;
         s.m = (int64_t)s.code->mb * s.code->Z;
         const int64_t widest = std::max<int64_t>(std::max<int64_t>(s.n, s.m), (int64_t)s.code->nent1 * s.code->Z);
-        if (widest * 64 >= (int64_t)1 << 31) {
+        if (widest * 64 * 4 >= (int64_t)1 << 32) {
             delete d;
-            return fail(QM_ERR_UNSUPPORTED, "code too wide for 32-bit in-tile offsets");
+            return fail(QM_ERR_UNSUPPORTED, "code too wide for 32-bit in-tile byte offsets");
         }
         for (int i : s.code->rows) s.hrows.push_back(make_desc(*s.code, i));
         s.gptr = s.code->gptr;
-        s.maxd_t = s.code->max_d <= 4 ? 4 : (s.code->max_d <= 8 ? 8 : 16);
+        {
+            const int md = s.code->max_d;
+            s.maxd_t = md <= 2 ? 2 : md <= 6 ? md : md <= 8 ? 8 : 16;
+        }
         d->slots.push_back(std::move(s));
     }
     d->tun.frames_per_tile = 16;
@@ -466,6 +471,7 @@ int qm_decoder_create(const qm_code *const *codes, int32_t ncodes, const int32_t
     d->tun.merge = 1;
     d->tun.persistent = (flags & QM_PERSISTENT) ? 1 : 0;
     d->tun.graph = (flags & QM_GRAPH) ? 1 : 0;
+    d->tun.frames_per_lane = 2;
     layout(*d);
     *out = d;
     return QM_OK;
@@ -503,9 +509,15 @@ int qm_decoder_set_tuning(qm_decoder *d, const qm_tuning *t) {
     if (!is_pow2(n.frames_per_tile) || n.frames_per_tile > 64)
         return fail(QM_ERR_INVALID_ARG, "frames_per_tile must be a power of two <= 64");
     if (n.block == 0) n.block = 256;
-    if (n.block < 64 || n.block > 512 || n.block % 64)
-        return fail(QM_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 512]");
+    if (n.block < 64 || n.block > 256 || n.block % 64)
+        return fail(QM_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 256]");
     if (n.persistent) return fail(QM_ERR_UNSUPPORTED, "persistent launch not available");
+    if (n.frames_per_lane == 0) n.frames_per_lane = 2;
+    if (n.frames_per_lane == 4)
+        return fail(QM_ERR_UNSUPPORTED, "frames_per_lane 4 (128-bit buffer accesses) is switched off: it gave "
+                                        "run-to-run varying results at Z = 20000 whose cause is not established");
+    if (n.frames_per_lane != 1 && n.frames_per_lane != 2)
+        return fail(QM_ERR_INVALID_ARG, "frames_per_lane must be 1 or 2");
     n.merge = n.merge ? 1 : 0;
     n.graph = n.graph ? 1 : 0;
     d->tun = n;

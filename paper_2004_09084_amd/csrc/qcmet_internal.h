@@ -48,6 +48,7 @@ struct LayerArgs {
     int32_t ft_log2;
     int32_t ntiles;
     int32_t chunks;           // workgroups per (tile, row)
+    int32_t fpl;              // frames per lane (1, 2, 4)
     int32_t last;             // 1 in the last sweep: also form the degree-1 APPs
     int64_t strideA, strideR, strideK;  // per-tile strides (elements)
 };
@@ -60,7 +61,7 @@ hipError_t qm_launch_to_tiles_u8(const uint8_t *in, uint8_t *out, int F, int64_t
 hipError_t qm_launch_kappa(const float *A, const uint8_t *Sil, float *K, const RowDesc *rows,
                            int mb, const TileGeom &g, hipStream_t s);
 hipError_t qm_launch_fill_u32(uint32_t *p, uint32_t v, size_t count, hipStream_t s);
-hipError_t qm_launch_layer(const LayerArgs &a, int msg16, int maxd, int block, hipStream_t s);
+hipError_t qm_launch_layer(const LayerArgs &a, int msg16, int maxd, int fpl, int block, hipStream_t s);
 hipError_t qm_launch_syndrome(const float *A, const uint8_t *Sil, const RowDesc *rows, int mb,
                               uint32_t *fail, const TileGeom &g, hipStream_t s);
 hipError_t qm_launch_finalize(const float *A, const uint32_t *fail, float *app, uint8_t *hard,

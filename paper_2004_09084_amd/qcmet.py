@@ -59,7 +59,8 @@ class qm_code_info(ctypes.Structure):
 
 class qm_tuning(ctypes.Structure):
     _fields_ = [("frames_per_tile", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("merge", ctypes.c_int32), ("persistent", ctypes.c_int32), ("graph", ctypes.c_int32)]
+                ("merge", ctypes.c_int32), ("persistent", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("frames_per_lane", ctypes.c_int32)]
 
 
 class qm_profile(ctypes.Structure):
@@ -191,8 +192,9 @@ def qm_decoder_bind_workspace(dec, ws) -> None:
     _check(lib().qm_decoder_bind_workspace(dec, _dptr(ws), ws.numel() * ws.element_size()))
 
 
-def qm_decoder_set_tuning(dec, frames_per_tile=0, block=0, merge=1, persistent=0, graph=0) -> None:
-    t = qm_tuning(frames_per_tile, block, merge, persistent, graph)
+def qm_decoder_set_tuning(dec, frames_per_tile=0, block=0, merge=1, persistent=0, graph=0,
+                          frames_per_lane=0) -> None:
+    t = qm_tuning(frames_per_tile, block, merge, persistent, graph, frames_per_lane)
     _check(lib().qm_decoder_set_tuning(dec, ctypes.byref(t)))
 
 

@@ -113,10 +113,14 @@ def test_tuning_validation():
     Q.qm_decoder_set_tuning(d, frames_per_tile=8, block=128, merge=0)
     t = Q.qm_decoder_get_tuning(d)
     assert t["frames_per_tile"] == 8 and t["block"] == 128 and t["merge"] == 0
-    for bad in (dict(frames_per_tile=3), dict(frames_per_tile=128), dict(block=100), dict(block=1024)):
+    for bad in (dict(frames_per_tile=3), dict(frames_per_tile=128), dict(block=100), dict(block=512),
+                dict(frames_per_lane=3)):
         with pytest.raises(Q.QMError) as e:
             Q.qm_decoder_set_tuning(d, **bad)
         assert e.value.code == Q.QM_ERR_INVALID_ARG
+    with pytest.raises(Q.QMError) as e:
+        Q.qm_decoder_set_tuning(d, frames_per_lane=4)
+    assert e.value.code == Q.QM_ERR_UNSUPPORTED
     Q.qm_decoder_destroy(d)
 
 

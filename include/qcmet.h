@@ -80,6 +80,12 @@ typedef struct {
     int32_t graph;            /* 1: replay a captured hipGraph */
     int32_t frames_per_lane;  /* 1 or 2 adjacent frames per GPU lane (<= frames_per_tile);
                                  0 = default (2).  4 is rejected (QM_ERR_UNSUPPORTED). */
+    int32_t fuse_codes;       /* 1: with several codes (at most 4) and merge = 1, one launch runs
+                                 the current layer of every code (each code walks its own layer
+                                 sequence); 0: the codes are swept one after another */
+    int32_t stream_hint;      /* 1: messages and per-check terms are read and written with the
+                                 non-temporal cache policy (they are used once per sweep), so the
+                                 APP columns that the next layers reuse stay cached */
 } qm_tuning;
 
 int qm_abi_version(void);
@@ -141,12 +147,16 @@ int qm_decoder_get_tuning(const qm_decoder *dec, qm_tuning *tuning);
 int qm_decode(qm_decoder *dec, const float *llr, const uint8_t *syndrome, int32_t iters,
               uint8_t *hard, float *app, uint8_t *flags, void *stream);
 
-/* Times the result-preserving tunings (frames per tile, block size, merged
- * or per-row launches, persistent/graph/plain) on the given inputs and keeps
- * the fastest; the row order is never changed.  Rebinds the workspace.
- * cache_path (may be NULL) appends one line per trial. */
+/* Times result-preserving tunings on the given inputs and keeps the fastest:
+ * frames per tile {16, 32, 64} x frames per lane {1, 2} x block {128, 256},
+ * then, on the best, per-row launches, unfused codes, graph replay and the
+ * other stream_hint.  The
+ * schedule (row order) is never changed, so every trial decodes to the same
+ * bits.  Each trial decodes min(iters, 8) sweeps into the caller's output
+ * buffers (same shapes as qm_decode); the call synchronises the stream.
+ * cache_path (may be NULL) gets one JSON line appended per trial. */
 int qm_autotune(qm_decoder *dec, const float *llr, const uint8_t *syndrome, int32_t iters,
-                const char *cache_path, void *stream);
+                uint8_t *hard, float *app, uint8_t *flags, const char *cache_path, void *stream);
 
 /* Live timing of the layer kernel (the decode's hot loop).
  * qm_decoder_set_profiling(dec, 1): every later qm_decode records a pair of
@@ -169,6 +179,58 @@ typedef struct {
 
 int qm_decoder_set_profiling(qm_decoder *dec, int32_t enable);
 int qm_decoder_get_profile(qm_decoder *dec, qm_profile *out, int32_t reset);
+
+/* ---- Learned decoder: normalized/offset min-sum (not in the paper) -------
+ * The same layered sweep over the decoder's schedule, with the check update
+ *   r_e = (-1)^{s ^ xor_{e'!=e}[q_e' < 0]} * alpha * max(min_{e'!=e}|q_e'| - beta, 0)
+ * (ties of the minimum: the lowest block column wins; a check with a single
+ * edge sees 30).  Weights are per (sweep t, base row i, target edge type):
+ *   weights: device float [T][mb][2][2]; [t][i][0] = (alpha, beta) for a
+ *   target edge in a column of degree >= 2, [t][i][1] for the degree-1 edge.
+ * Degree-1 variables keep q = LLR (their single check); their message only
+ * reaches APP_d = LLR_d + r_d.  The decoder must hold exactly one code with
+ * float32 messages (QM_ERR_UNSUPPORTED otherwise).
+ * Workspace: a second device buffer, sized for at most T sweeps; train = 1
+ * adds the per-sweep checkpoints (T x (APP + messages)) and adjoints. */
+size_t qm_nms_workspace_bytes(const qm_decoder *dec, int32_t T, int32_t train);
+int qm_nms_bind_workspace(qm_decoder *dec, void *device_ptr, size_t bytes, int32_t T, int32_t train);
+
+/* Min-sum decode of every frame for up to T sweeps (T <= the bound T).
+ * early_stop = 1: after every sweep the hard decisions are tested (H c = s)
+ * and a frame that passes is frozen; iters_used[f] (device int32 [F], or
+ * NULL) receives the sweeps it ran (0 if its channel decisions already
+ * pass).  Outputs as for qm_decode. */
+int qm_nms_decode(qm_decoder *dec, const float *weights, const float *llr, const uint8_t *syndrome, int32_t T,
+                  int32_t early_stop, uint8_t *hard, float *app, uint8_t *flags, int32_t *iters_used, void *stream);
+
+/* Training step core: T fixed min-sum sweeps from the channel LLRs, the mean
+ * binary cross-entropy of the final APPs against the true bits x,
+ *   loss = mean over frames and all n bits of softplus(-(1 - 2x) APP)
+ * (P(bit = 1) = sigmoid(-APP)), and its exact gradient with respect to the
+ * weights by a reverse sweep that restores each sweep's starting state from
+ * its checkpoint and recomputes it.  Gradient sums over workgroups are
+ * reduced in a fixed order (run-to-run identical).
+ *   x: device uint8 [F][n]; loss: device float scalar; grad: device float,
+ *   same layout as weights (first T sweeps).  Needs a train workspace. */
+int qm_nms_loss_grad(qm_decoder *dec, const float *weights, const float *llr, const uint8_t *syndrome,
+                     const uint8_t *x, int32_t T, float *loss, float *grad, void *stream);
+
+/* Synthetic frames of code `code_index` of the decoder (its workspace must
+ * be bound): for frame f (global index first_frame + f) x is uniform random
+ * bits, y = 1 - 2x + N(0, 1/snr), llr = 2 snr y (Methods, step 1) and
+ * s = H x.  Random numbers are Philox4x32-10 (Salmon et al., SC 2011) with
+ * key = seed and counter (bit pair p, frame lo, frame hi, 0): bits 2p, 2p+1
+ * are the top bits of words 2 and 3; words 0 and 1 give two normals by
+ * Box-Muller (u = (word + 1/2) 2^-32).  Outputs device [F][n] x and llr,
+ * [F][m] syndrome. */
+int qm_generate_frames(qm_decoder *dec, int32_t code_index, uint64_t seed, uint64_t first_frame, float snr,
+                       int32_t F, uint8_t *x, float *llr, uint8_t *syndrome, void *stream);
+
+/* Adam (Kingma & Ba) on device arrays of `count` floats, step >= 1:
+ * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * w -= lr * (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps). */
+int qm_adam_step(float *w, const float *g, float *m, float *v, int32_t count, float lr, float b1, float b2,
+                 float eps, int32_t step, void *stream);
 
 #ifdef __cplusplus
 }

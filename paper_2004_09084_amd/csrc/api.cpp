@@ -113,6 +113,7 @@ RowDesc make_desc(const qm_code &c, int i) {
         if (c.col_deg[j] == 1) {
             d.d1col = j;
             d.d1shift = a;
+            d.d1pos = d.d;  // degree>=2 entries before it
         } else {
             d.col[d.d] = j;
             d.shift[d.d] = a;
@@ -155,6 +156,13 @@ struct qm_decoder {
     size_t ev_used = 0;
     struct Pending { size_t a, b; double bytes, checks; int kind; };  // kind 0: layer, 1: sweep
     std::vector<Pending> pending;
+    // learned-decoder (min-sum) workspace
+    char *nws = nullptr;
+    size_t nws_bytes = 0;
+    int32_t nT = 0, ntrain = 0;
+    size_t oAd = 0, oAct = 0, oIt = 0, oCols = 0, oLossP = 0, oLoss = 0, oX = 0, ogA = 0, ogAd = 0, ogR = 0, oQ = 0,
+           oCkA = 0, oCkR = 0, oPart = 0, nTotal = 0;
+    std::vector<int32_t> acols;  // columns whose APP lives in A (degree != 1)
 };
 
 namespace {
@@ -223,99 +231,319 @@ void drop_graph(qm_decoder &d) {
     d.giters = -1;
 }
 
-// The launch sequence of one decode (no host synchronisation: capturable).
-int enqueue_decode(qm_decoder &d, const float *llr, const uint8_t *syn, int32_t iters, uint8_t *hard, float *app,
-                   uint8_t *flags, hipStream_t st) {
-    size_t on = 0, om = 0, of = 0;
+struct SlotBufs {
+    float *A;
+    void *R;
+    float *K;
+    uint8_t *S;
+    uint32_t *fail;
+    const RowDesc *rows;
+};
+
+SlotBufs slot_bufs(const qm_decoder &d, const Slot &s) {
+    SlotBufs b;
+    b.A = reinterpret_cast<float *>(d.ws + s.oA);
+    b.R = d.ws + s.oR;
+    b.K = reinterpret_cast<float *>(d.ws + s.oK);
+    b.S = reinterpret_cast<uint8_t *>(d.ws + s.oS);
+    b.fail = reinterpret_cast<uint32_t *>(d.ws + s.oFail);
+    b.rows = reinterpret_cast<const RowDesc *>(d.ws + s.oRows);
+    return b;
+}
+
+LayerArgs layer_args(const qm_decoder &d, const Slot &s) {
+    const TileGeom g = geom(d, s);
+    const SlotBufs b = slot_bufs(d, s);
+    LayerArgs la;
+    std::memset(&la, 0, sizeof(la));
+    la.A = b.A;
+    la.R = b.R;
+    la.K = b.K;
+    la.Z = s.code->Z;
+    la.ft_log2 = g.ft_log2;
+    la.ntiles = g.ntiles;
+    la.fpl = std::min(d.tun.frames_per_lane, 1 << g.ft_log2);
+    const int lanes = (s.code->Z << g.ft_log2) / la.fpl;
+    la.chunks = (lanes + d.tun.block - 1) / d.tun.block;
+    la.strideA = (int64_t)s.n << g.ft_log2;
+    la.strideR = ((int64_t)s.code->nent1 * s.code->Z) << g.ft_log2;
+    la.strideK = (int64_t)s.m << g.ft_log2;
+    return la;
+}
+
+// record a pair of events around a launch (profiling)
+struct ProfScope {
+    qm_decoder &d;
+    hipStream_t st;
+    bool on;
+    size_t i0 = 0;
+    ProfScope(qm_decoder &d_, hipStream_t st_, bool on_) : d(d_), st(st_), on(on_) {}
+    int begin() {
+        if (!on) return QM_OK;
+        hipEvent_t e;
+        int rc = take_event(d, &e, &i0);
+        if (rc != QM_OK) return rc;
+        QM_HIP(hipEventRecord(e, st));
+        return QM_OK;
+    }
+    int end(double bytes, double checks, int kind) {
+        if (!on) return QM_OK;
+        hipEvent_t e;
+        size_t i1;
+        int rc = take_event(d, &e, &i1);
+        if (rc != QM_OK) return rc;
+        QM_HIP(hipEventRecord(e, st));
+        d.pending.push_back(qm_decoder::Pending{i0, i1, bytes, checks, kind});
+        return QM_OK;
+    }
+};
+
+int enqueue_init(qm_decoder &d, const float *llr, const uint8_t *syn, hipStream_t st) {
+    size_t on = 0, om = 0;
     const int msg16 = (d.flags & QM_MSG_FP16) ? 1 : 0;
     for (Slot &s : d.slots) {
         if (s.F == 0) continue;
         const qm_code &c = *s.code;
         const TileGeom g = geom(d, s);
-        float *A = reinterpret_cast<float *>(d.ws + s.oA);
-        void *R = d.ws + s.oR;
-        float *K = reinterpret_cast<float *>(d.ws + s.oK);
-        uint8_t *S = reinterpret_cast<uint8_t *>(d.ws + s.oS);
-        uint32_t *fl = reinterpret_cast<uint32_t *>(d.ws + s.oFail);
-        const RowDesc *rows = reinterpret_cast<const RowDesc *>(d.ws + s.oRows);
-
-        QM_HIP(qm_launch_to_tiles_f32(llr + on, A, s.F, s.n, g.ft_log2, g.ntiles, st));
-        QM_HIP(qm_launch_to_tiles_u8(syn + om, S, s.F, s.m, g.ft_log2, g.ntiles, st));
-        QM_HIP(qm_launch_kappa(A, S, K, rows, c.mb, g, st));
+        const SlotBufs b = slot_bufs(d, s);
+        QM_HIP(qm_launch_to_tiles_f32(llr + on, b.A, s.F, s.n, g.ft_log2, g.ntiles, st));
+        QM_HIP(qm_launch_to_tiles_u8(syn + om, b.S, s.F, s.m, g.ft_log2, g.ntiles, st));
+        QM_HIP(qm_launch_kappa(b.A, b.S, b.K, b.rows, c.mb, g, st));
         const size_t rbytes = align_up((size_t)s.Fpad * c.nent1 * c.Z * (msg16 ? 2 : 4));
-        QM_HIP(qm_launch_fill_u32(reinterpret_cast<uint32_t *>(R), 0u, rbytes / 4, st));
-        QM_HIP(qm_launch_fill_u32(fl, 0u, (size_t)s.Fpad, st));
-
-        LayerArgs la;
-        la.A = A;
-        la.R = R;
-        la.K = K;
-        la.Z = c.Z;
-        la.ft_log2 = g.ft_log2;
-        la.ntiles = g.ntiles;
-        la.fpl = std::min(d.tun.frames_per_lane, 1 << g.ft_log2);
-        const int lanes = (c.Z << g.ft_log2) / la.fpl;
-        la.chunks = (lanes + d.tun.block - 1) / d.tun.block;
-        la.strideA = (int64_t)s.n << g.ft_log2;
-        la.strideR = ((int64_t)c.nent1 * c.Z) << g.ft_log2;
-        la.strideK = (int64_t)s.m << g.ft_log2;
-        const int G = (int)s.gptr.size() - 1;
-        // the profiled sweep: the middle one, never the last (which also
-        // forms the degree-1 APPs)
-        const int tprof = (d.profiling && iters >= 2) ? (iters - 1) / 2 : -1;
-        auto launch = [&](int p0, int nr, bool prof) -> int {
-            la.rows = rows + p0;
-            la.nrows = nr;
-            if (!prof) {
-                QM_HIP(qm_launch_layer(la, msg16, s.maxd_t, la.fpl, d.tun.block, st));
-                return QM_OK;
-            }
-            hipEvent_t e0, e1;
-            size_t i0, i1;
-            int rc = take_event(d, &e0, &i0);
-            if (rc == QM_OK) rc = take_event(d, &e1, &i1);
-            if (rc != QM_OK) return rc;
-            QM_HIP(hipEventRecord(e0, st));
-            QM_HIP(qm_launch_layer(la, msg16, s.maxd_t, la.fpl, d.tun.block, st));
-            QM_HIP(hipEventRecord(e1, st));
-            qm_decoder::Pending pd{i0, i1, 0.0, 0.0, 0};
-            layer_work(s, s.hrows.data() + p0, nr, msg16, &pd.bytes, &pd.checks);
-            d.pending.push_back(pd);
-            return QM_OK;
-        };
-        for (int t = 0; t < iters; ++t) {
-            la.last = (t == iters - 1) ? 1 : 0;
-            const bool prof = (t == tprof);
-            size_t sw0 = 0, sw1 = 0;
-            hipEvent_t es0 = nullptr, es1 = nullptr;
-            if (prof) {
-                const int rc = take_event(d, &es0, &sw0);
-                if (rc != QM_OK) return rc;
-                QM_HIP(hipEventRecord(es0, st));
-            }
-            for (int gi = 0; gi < G; ++gi) {
-                if (d.tun.merge) {
-                    const int rc = launch(s.gptr[gi], s.gptr[gi + 1] - s.gptr[gi], prof);
-                    if (rc != QM_OK) return rc;
-                } else {
-                    for (int p = s.gptr[gi]; p < s.gptr[gi + 1]; ++p) {
-                        const int rc = launch(p, 1, prof);
-                        if (rc != QM_OK) return rc;
-                    }
-                }
-            }
-            if (prof) {
-                const int rc = take_event(d, &es1, &sw1);
-                if (rc != QM_OK) return rc;
-                QM_HIP(hipEventRecord(es1, st));
-                d.pending.push_back(qm_decoder::Pending{sw0, sw1, 0.0, 0.0, 1});
-            }
-        }
-        QM_HIP(qm_launch_syndrome(A, S, rows, c.mb, fl, g, st));
-        QM_HIP(qm_launch_finalize(A, fl, app ? app + on : nullptr, hard + on, flags + of, s.F, g, st));
+        QM_HIP(qm_launch_fill_u32(reinterpret_cast<uint32_t *>(b.R), 0u, rbytes / 4, st));
+        QM_HIP(qm_launch_fill_u32(b.fail, 0u, (size_t)s.Fpad, st));
         on += (size_t)s.F * s.n;
         om += (size_t)s.F * s.m;
+    }
+    return QM_OK;
+}
+
+int enqueue_finalize(qm_decoder &d, uint8_t *hard, float *app, uint8_t *flags, hipStream_t st) {
+    size_t on = 0, of = 0;
+    for (Slot &s : d.slots) {
+        if (s.F == 0) continue;
+        const TileGeom g = geom(d, s);
+        const SlotBufs b = slot_bufs(d, s);
+        QM_HIP(qm_launch_syndrome(b.A, nullptr, b.S, b.rows, s.code->mb, b.fail, g, st));
+        QM_HIP(qm_launch_finalize(b.A, b.fail, app ? app + on : nullptr, hard + on, flags + of, s.F, g, st));
+        on += (size_t)s.F * s.n;
         of += (size_t)s.F;
+    }
+    return QM_OK;
+}
+
+// Sweeps of one code, one launch per layer (or per row with merge = 0).
+int enqueue_sweeps_slot(qm_decoder &d, Slot &s, int32_t iters, hipStream_t st) {
+    const int msg16 = (d.flags & QM_MSG_FP16) ? 1 : 0;
+    const RowDesc *rows = slot_bufs(d, s).rows;
+    LayerArgs la = layer_args(d, s);
+    const int G = (int)s.gptr.size() - 1;
+    // the profiled sweep: the middle one, never the last (which also forms
+    // the degree-1 APPs)
+    const int tprof = (d.profiling && iters >= 2) ? (iters - 1) / 2 : -1;
+    for (int t = 0; t < iters; ++t) {
+        la.last = (t == iters - 1) ? 1 : 0;
+        const bool prof = (t == tprof);
+        ProfScope sweep(d, st, prof);
+        int rc = sweep.begin();
+        if (rc != QM_OK) return rc;
+        for (int gi = 0; gi < G; ++gi) {
+            const int p_lo = s.gptr[gi], p_hi = s.gptr[gi + 1];
+            const int step = d.tun.merge ? (p_hi - p_lo) : 1;
+            for (int p = p_lo; p < p_hi; p += step) {
+                la.rows = rows + p;
+                la.nrows = step;
+                ProfScope one(d, st, prof);
+                if ((rc = one.begin()) != QM_OK) return rc;
+                QM_HIP(qm_launch_layer(la, msg16, s.maxd_t, la.fpl, d.tun.block, d.tun.stream_hint, st));
+                double bytes, checks;
+                layer_work(s, s.hrows.data() + p, step, msg16, &bytes, &checks);
+                if ((rc = one.end(bytes, checks, 0)) != QM_OK) return rc;
+            }
+        }
+        if ((rc = sweep.end(0.0, 0.0, 1)) != QM_OK) return rc;
+    }
+    return QM_OK;
+}
+
+// Sweeps of every code in fused launches: step k runs layer (k mod G_c) of
+// iteration k / G_c of each code c that still has sweeps left.
+int enqueue_sweeps_fused(qm_decoder &d, int32_t iters, hipStream_t st) {
+    const int msg16 = (d.flags & QM_MSG_FP16) ? 1 : 0;
+    std::vector<Slot *> act;
+    for (Slot &s : d.slots)
+        if (s.F > 0) act.push_back(&s);
+    const int nc = (int)act.size();
+    std::vector<LayerArgs> base(nc);
+    std::vector<int> G(nc);
+    int64_t steps = 0;
+    int maxd = 2;
+    for (int c = 0; c < nc; ++c) {
+        base[c] = layer_args(d, *act[c]);
+        G[c] = (int)act[c]->gptr.size() - 1;
+        steps = std::max<int64_t>(steps, (int64_t)iters * G[c]);
+        maxd = std::max(maxd, act[c]->maxd_t);
+    }
+    // one lane width for the whole launch: no wider than any code's tile
+    int fpl = d.tun.frames_per_lane;
+    for (int c = 0; c < nc; ++c) fpl = std::min(fpl, 1 << base[c].ft_log2);
+    for (int c = 0; c < nc; ++c) {
+        base[c].fpl = fpl;
+        const int lanes = (base[c].Z << base[c].ft_log2) / fpl;
+        base[c].chunks = (lanes + d.tun.block - 1) / d.tun.block;
+    }
+    // profiled: the steps of one sweep of the code with the most layers,
+    // from the middle of the decode (never its last sweep)
+    int gmax = 1;
+    for (int c = 0; c < nc; ++c) gmax = std::max(gmax, G[c]);
+    const int64_t kprof = (d.profiling && steps >= 2 * gmax) ? (steps / 2 / gmax) * gmax - gmax : -1;
+    for (int64_t k = 0; k < steps; ++k) {
+        MultiLayerArgs m;
+        std::memset(&m, 0, sizeof(m));
+        m.ncodes = nc;
+        double bytes = 0.0, checks = 0.0;
+        int32_t off = 0;
+        for (int c = 0; c < nc; ++c) {
+            m.block_off[c] = off;
+            LayerArgs la = base[c];
+            if (k < (int64_t)iters * G[c]) {
+                const int t = (int)(k / G[c]), gi = (int)(k % G[c]);
+                const Slot &s = *act[c];
+                la.last = (t == iters - 1) ? 1 : 0;
+                la.rows = slot_bufs(d, s).rows + s.gptr[gi];
+                la.nrows = s.gptr[gi + 1] - s.gptr[gi];
+                off += la.ntiles * la.nrows * la.chunks;
+                double b, ch;
+                layer_work(s, s.hrows.data() + s.gptr[gi], la.nrows, msg16, &b, &ch);
+                bytes += b;
+                checks += ch;
+            } else {
+                la.nrows = 0;
+            }
+            m.code[c] = la;
+        }
+        m.block_off[nc] = off;
+        ProfScope one(d, st, kprof >= 0 && k >= kprof && k < kprof + gmax);
+        int rc = one.begin();
+        if (rc != QM_OK) return rc;
+        QM_HIP(qm_launch_layer_multi(m, msg16, maxd, fpl, d.tun.block, d.tun.stream_hint, st));
+        if ((rc = one.end(bytes, checks, 0)) != QM_OK) return rc;
+    }
+    return QM_OK;
+}
+
+bool fused_path(const qm_decoder &d) {
+    int nc = 0;
+    for (const Slot &s : d.slots) nc += s.F > 0 ? 1 : 0;
+    return nc >= 2 && nc <= QM_MAX_CODES && d.tun.fuse_codes && d.tun.merge;
+}
+
+// The launch sequence of one decode (no host synchronisation: capturable).
+int enqueue_decode(qm_decoder &d, const float *llr, const uint8_t *syn, int32_t iters, uint8_t *hard, float *app,
+                   uint8_t *flags, hipStream_t st) {
+    int rc = enqueue_init(d, llr, syn, st);
+    if (rc != QM_OK) return rc;
+    if (fused_path(d)) {
+        rc = enqueue_sweeps_fused(d, iters, st);
+    } else {
+        for (Slot &s : d.slots) {
+            if (s.F == 0) continue;
+            rc = enqueue_sweeps_slot(d, s, iters, st);
+            if (rc != QM_OK) break;
+        }
+    }
+    if (rc != QM_OK) return rc;
+    return enqueue_finalize(d, hard, app, flags, st);
+}
+
+// ---------------------------------------------------------- learned decoder --
+
+int nms_slot(qm_decoder &d, Slot **out) {
+    Slot *only = nullptr;
+    int n = 0;
+    for (Slot &s : d.slots)
+        if (s.F > 0) {
+            only = &s;
+            ++n;
+        }
+    if (n != 1) return fail(QM_ERR_UNSUPPORTED, "the min-sum decoder takes a decoder with exactly one code");
+    if (d.flags & QM_MSG_FP16) return fail(QM_ERR_UNSUPPORTED, "the min-sum decoder keeps float32 messages");
+    *out = only;
+    return QM_OK;
+}
+
+void nms_layout(qm_decoder &d, const Slot &s, int32_t T, int32_t train) {
+    const size_t fp = (size_t)s.Fpad, n = (size_t)s.n, m = (size_t)s.m;
+    const size_t e = (size_t)s.code->nent1 * s.code->Z;
+    size_t off = 0;
+    d.oAd = off; off = align_up(off + fp * m * 4);
+    d.oAct = off; off = align_up(off + fp * 4);
+    d.oIt = off; off = align_up(off + fp * 4);
+    d.oCols = off; off = align_up(off + (size_t)s.code->nb * 4);
+    // partial loss sums: one per workgroup of the loss kernel (256 lanes)
+    const size_t bce_blocks = (size_t)(s.code->nb + s.code->mb) * (fp * s.code->Z / 256 + fp + 1);
+    d.oLossP = off; off = align_up(off + bce_blocks * 4);
+    d.oLoss = off; off = align_up(off + 4);
+    if (train) {
+        d.oX = off; off = align_up(off + fp * n);
+        d.ogA = off; off = align_up(off + fp * n * 4);
+        d.ogAd = off; off = align_up(off + fp * m * 4);
+        d.ogR = off; off = align_up(off + fp * e * 4);
+        d.oQ = off; off = align_up(off + fp * e * 4);
+        d.oCkA = off; off = align_up(off + (size_t)T * fp * n * 4);
+        d.oCkR = off; off = align_up(off + (size_t)T * fp * e * 4);
+        // per-workgroup gradient sums of the reverse sweep: at most
+        // Fpad*Z/64 + Fpad workgroups per (sweep, row)
+        d.oPart = off; off = align_up(off + (size_t)T * s.code->mb * (fp * s.code->Z / 64 + fp + 1) * 16);
+    }
+    d.nTotal = off;
+}
+
+template <typename T>
+T *nws_ptr(const qm_decoder &d, size_t off) { return reinterpret_cast<T *>(d.nws + off); }
+
+NmsLayerArgs nms_args(qm_decoder &d, Slot &s) {
+    NmsLayerArgs na;
+    std::memset(&na, 0, sizeof(na));
+    na.L = layer_args(d, s);
+    na.Ad = nws_ptr<float>(d, d.oAd);
+    return na;
+}
+
+// initial state of a min-sum decode: frame tiles, K = |LLR_d| with sign
+// s ^ [LLR_d < 0], r = 0, Ad = LLR_d, every frame active
+int nms_init(qm_decoder &d, Slot &s, const float *llr, const uint8_t *syn, hipStream_t st) {
+    const qm_code &c = *s.code;
+    const TileGeom g = geom(d, s);
+    const SlotBufs b = slot_bufs(d, s);
+    QM_HIP(qm_launch_to_tiles_f32(llr, b.A, s.F, s.n, g.ft_log2, g.ntiles, st));
+    QM_HIP(qm_launch_to_tiles_u8(syn, b.S, s.F, s.m, g.ft_log2, g.ntiles, st));
+    QM_HIP(qm_launch_nms_kappa(b.A, b.S, b.K, b.rows, c.mb, g, st));
+    QM_HIP(qm_launch_fill_u32(reinterpret_cast<uint32_t *>(b.R), 0u, align_up((size_t)s.Fpad * c.nent1 * c.Z * 4) / 4, st));
+    QM_HIP(qm_launch_fill_u32(b.fail, 0u, (size_t)s.Fpad, st));
+    QM_HIP(qm_launch_commit_d1(b.A, nws_ptr<float>(d, d.oAd), 0, b.rows, c.mb, g, st));
+    QM_HIP(qm_launch_fill_u32(nws_ptr<uint32_t>(d, d.oAct), 1u, (size_t)s.Fpad, st));
+    QM_HIP(qm_launch_fill_u32(nws_ptr<uint32_t>(d, d.oIt), 0u, (size_t)s.Fpad, st));
+    return QM_OK;
+}
+
+// one sweep t of min-sum layers
+int nms_sweep(qm_decoder &d, Slot &s, const float *W, int t, int last, const uint32_t *act, float *Q, hipStream_t st) {
+    const RowDesc *rows = slot_bufs(d, s).rows;
+    NmsLayerArgs na = nms_args(d, s);
+    na.L.last = last;
+    na.W = W + (size_t)t * s.code->mb * 4;
+    na.act = act;
+    na.Q = Q;
+    const int G = (int)s.gptr.size() - 1;
+    for (int gi = 0; gi < G; ++gi) {
+        const int p_lo = s.gptr[gi], p_hi = s.gptr[gi + 1];
+        const int step = d.tun.merge ? (p_hi - p_lo) : 1;
+        for (int p = p_lo; p < p_hi; p += step) {
+            na.L.rows = rows + p;
+            na.L.nrows = step;
+            QM_HIP(qm_launch_nms_layer(na, s.maxd_t, na.L.fpl, d.tun.block, st));
+        }
     }
     return QM_OK;
 }
@@ -467,11 +695,13 @@ int qm_decoder_create(const qm_code *const *codes, int32_t ncodes, const int32_t
         d->slots.push_back(std::move(s));
     }
     d->tun.frames_per_tile = 16;
-    d->tun.block = 256;
+    d->tun.block = 128;
     d->tun.merge = 1;
     d->tun.persistent = (flags & QM_PERSISTENT) ? 1 : 0;
     d->tun.graph = (flags & QM_GRAPH) ? 1 : 0;
     d->tun.frames_per_lane = 2;
+    d->tun.fuse_codes = 1;
+    d->tun.stream_hint = 1;
     layout(*d);
     *out = d;
     return QM_OK;
@@ -508,7 +738,7 @@ int qm_decoder_set_tuning(qm_decoder *d, const qm_tuning *t) {
     if (n.frames_per_tile == 0) n.frames_per_tile = 16;
     if (!is_pow2(n.frames_per_tile) || n.frames_per_tile > 64)
         return fail(QM_ERR_INVALID_ARG, "frames_per_tile must be a power of two <= 64");
-    if (n.block == 0) n.block = 256;
+    if (n.block == 0) n.block = 128;
     if (n.block < 64 || n.block > 256 || n.block % 64)
         return fail(QM_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 256]");
     if (n.persistent) return fail(QM_ERR_UNSUPPORTED, "persistent launch not available");
@@ -520,6 +750,8 @@ int qm_decoder_set_tuning(qm_decoder *d, const qm_tuning *t) {
         return fail(QM_ERR_INVALID_ARG, "frames_per_lane must be 1 or 2");
     n.merge = n.merge ? 1 : 0;
     n.graph = n.graph ? 1 : 0;
+    n.fuse_codes = n.fuse_codes ? 1 : 0;
+    n.stream_hint = n.stream_hint ? 1 : 0;
     d->tun = n;
     drop_graph(*d);
     return QM_OK;
@@ -609,10 +841,247 @@ int qm_decoder_get_profile(qm_decoder *d, qm_profile *out, int32_t reset) {
     return QM_OK;
 }
 
-int qm_autotune(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t iters, const char *cache_path,
-                void *stream) {
-    (void)d; (void)llr; (void)syn; (void)iters; (void)cache_path; (void)stream;
-    return fail(QM_ERR_UNSUPPORTED, "autotune not available yet");
+size_t qm_nms_workspace_bytes(const qm_decoder *dc, int32_t T, int32_t train) {
+    if (!dc || T < 0) return 0;
+    qm_decoder &d = const_cast<qm_decoder &>(*dc);
+    Slot *s = nullptr;
+    if (nms_slot(d, &s) != QM_OK) return 0;
+    qm_decoder tmp;
+    nms_layout(tmp, *s, T, train);
+    return tmp.nTotal;
+}
+
+int qm_nms_bind_workspace(qm_decoder *d, void *dev, size_t bytes, int32_t T, int32_t train) {
+    if (!d || !dev || T < 0) return fail(QM_ERR_INVALID_ARG, "bad argument");
+    if ((reinterpret_cast<uintptr_t>(dev) % kAlign) != 0) return fail(QM_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+    Slot *s = nullptr;
+    int rc = nms_slot(*d, &s);
+    if (rc != QM_OK) return rc;
+    nms_layout(*d, *s, T, train);
+    if (bytes < d->nTotal)
+        return fail(QM_ERR_NO_WORKSPACE, "min-sum workspace too small: need " + std::to_string(d->nTotal) + " bytes");
+    d->nws = static_cast<char *>(dev);
+    d->nws_bytes = bytes;
+    d->nT = T;
+    d->ntrain = train ? 1 : 0;
+    d->acols.clear();
+    for (int j = 0; j < s->code->nb; ++j)
+        if (s->code->col_deg[j] != 1) d->acols.push_back(j);
+    if (!d->acols.empty())
+        QM_HIP(hipMemcpy(d->nws + d->oCols, d->acols.data(), d->acols.size() * 4, hipMemcpyHostToDevice));
+    return QM_OK;
+}
+
+int qm_nms_decode(qm_decoder *d, const float *W, const float *llr, const uint8_t *syn, int32_t T, int32_t early_stop,
+                  uint8_t *hard, float *app, uint8_t *flags, int32_t *iters_used, void *stream) {
+    if (!d || !W || !llr || !syn || !hard || !flags) return fail(QM_ERR_INVALID_ARG, "NULL argument");
+    if (!d->bound || !d->nws) return fail(QM_ERR_NO_WORKSPACE, "decoder or min-sum workspace not bound");
+    if (T < 0 || T > d->nT) return fail(QM_ERR_INVALID_ARG, "T must be in [0, T of the bound min-sum workspace]");
+    Slot *s = nullptr;
+    int rc = nms_slot(*d, &s);
+    if (rc != QM_OK) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const qm_code &c = *s->code;
+    const TileGeom g = geom(*d, *s);
+    const SlotBufs b = slot_bufs(*d, *s);
+    float *Ad = nws_ptr<float>(*d, d->oAd);
+    uint32_t *act = nws_ptr<uint32_t>(*d, d->oAct);
+    int32_t *it = nws_ptr<int32_t>(*d, d->oIt);
+    if ((rc = nms_init(*d, *s, llr, syn, st)) != QM_OK) return rc;
+    if (early_stop) {
+        // frames whose channel decisions already satisfy H c = s stop at 0
+        QM_HIP(qm_launch_syndrome(b.A, Ad, b.S, b.rows, c.mb, b.fail, g, st));
+        QM_HIP(qm_launch_et_update(b.fail, act, it, s->Fpad, 0, st));
+    }
+    for (int t = 0; t < T; ++t) {
+        const int last = early_stop ? 1 : (t == T - 1);
+        if ((rc = nms_sweep(*d, *s, W, t, last, early_stop ? act : nullptr, nullptr, st)) != QM_OK) return rc;
+        if (early_stop) {
+            QM_HIP(qm_launch_syndrome(b.A, Ad, b.S, b.rows, c.mb, b.fail, g, st));
+            QM_HIP(qm_launch_et_update(b.fail, act, it, s->Fpad, t + 1, st));
+        }
+    }
+    if (early_stop) {
+        QM_HIP(qm_launch_et_final(act, it, s->Fpad, T, st));
+    } else {
+        QM_HIP(qm_launch_fill_u32(reinterpret_cast<uint32_t *>(it), (uint32_t)T, (size_t)s->Fpad, st));
+    }
+    QM_HIP(qm_launch_commit_d1(b.A, Ad, 1, b.rows, c.mb, g, st));
+    QM_HIP(qm_launch_fill_u32(b.fail, 0u, (size_t)s->Fpad, st));
+    QM_HIP(qm_launch_syndrome(b.A, nullptr, b.S, b.rows, c.mb, b.fail, g, st));
+    QM_HIP(qm_launch_finalize(b.A, b.fail, app, hard, flags, s->F, g, st));
+    if (iters_used) QM_HIP(hipMemcpyAsync(iters_used, it, (size_t)s->F * 4, hipMemcpyDeviceToDevice, st));
+    return QM_OK;
+}
+
+int qm_nms_loss_grad(qm_decoder *d, const float *W, const float *llr, const uint8_t *syn, const uint8_t *x,
+                     int32_t T, float *loss, float *grad, void *stream) {
+    if (!d || !W || !llr || !syn || !x || !loss || !grad) return fail(QM_ERR_INVALID_ARG, "NULL argument");
+    if (!d->bound || !d->nws || !d->ntrain) return fail(QM_ERR_NO_WORKSPACE, "training workspace not bound");
+    if (T < 1 || T > d->nT) return fail(QM_ERR_INVALID_ARG, "T must be in [1, T of the bound workspace]");
+    Slot *s = nullptr;
+    int rc = nms_slot(*d, &s);
+    if (rc != QM_OK) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const qm_code &c = *s->code;
+    const TileGeom g = geom(*d, *s);
+    const SlotBufs b = slot_bufs(*d, *s);
+    const size_t fp = (size_t)s->Fpad;
+    const size_t bytesA = fp * (size_t)s->n * 4, bytesR = fp * (size_t)c.nent1 * c.Z * 4;
+    char *ckA = d->nws + d->oCkA, *ckR = d->nws + d->oCkR;
+    float *Ad = nws_ptr<float>(*d, d->oAd), *Q = nws_ptr<float>(*d, d->oQ);
+    float *gA = nws_ptr<float>(*d, d->ogA), *gAd = nws_ptr<float>(*d, d->ogAd), *gR = nws_ptr<float>(*d, d->ogR);
+    float *part = nws_ptr<float>(*d, d->oPart);
+    uint8_t *X = nws_ptr<uint8_t>(*d, d->oX);
+
+    if ((rc = nms_init(*d, *s, llr, syn, st)) != QM_OK) return rc;
+    QM_HIP(qm_launch_to_tiles_u8(x, X, s->F, s->n, g.ft_log2, g.ntiles, st));
+    // forward, keeping the state at the start of every sweep
+    for (int t = 0; t < T; ++t) {
+        QM_HIP(hipMemcpyAsync(ckA + (size_t)t * bytesA, b.A, bytesA, hipMemcpyDeviceToDevice, st));
+        QM_HIP(hipMemcpyAsync(ckR + (size_t)t * bytesR, b.R, bytesR, hipMemcpyDeviceToDevice, st));
+        if ((rc = nms_sweep(*d, *s, W, t, t == T - 1, nullptr, nullptr, st)) != QM_OK) return rc;
+    }
+    QM_HIP(qm_launch_bce(b.A, Ad, X, gA, gAd, nws_ptr<float>(*d, d->oLossP), nws_ptr<int32_t>(*d, d->oCols),
+                         (int)d->acols.size(), b.rows, c.mb, g, s->F, loss, st));
+    QM_HIP(qm_launch_fill_u32(reinterpret_cast<uint32_t *>(gR), 0u, bytesR / 4, st));
+    // reverse sweeps: restore the sweep's starting state, recompute it while
+    // recording q, then walk its layers backwards
+    const RowDesc *rows = b.rows;
+    NmsBwdArgs ba;
+    std::memset(&ba, 0, sizeof(ba));
+    ba.L = layer_args(*d, *s);
+    ba.Q = Q;
+    ba.gA = gA;
+    ba.gR = gR;
+    ba.gAd = gAd;
+    ba.part = part;
+    ba.mb = c.mb;
+    const int G = (int)s->gptr.size() - 1;
+    for (int t = T - 1; t >= 0; --t) {
+        QM_HIP(hipMemcpyAsync(b.A, ckA + (size_t)t * bytesA, bytesA, hipMemcpyDeviceToDevice, st));
+        QM_HIP(hipMemcpyAsync(b.R, ckR + (size_t)t * bytesR, bytesR, hipMemcpyDeviceToDevice, st));
+        if ((rc = nms_sweep(*d, *s, W, t, 0, nullptr, Q, st)) != QM_OK) return rc;
+        ba.t = t;
+        ba.L.last = (t == T - 1) ? 1 : 0;
+        ba.W = W + (size_t)t * c.mb * 4;
+        for (int gi = G - 1; gi >= 0; --gi) {
+            ba.L.rows = rows + s->gptr[gi];
+            ba.L.nrows = s->gptr[gi + 1] - s->gptr[gi];
+            QM_HIP(qm_launch_nms_bwd(ba, s->maxd_t, ba.L.fpl, d->tun.block, st));
+        }
+    }
+    QM_HIP(qm_launch_grad_reduce(part, grad, T, c.mb, ba.L.ntiles * ba.L.chunks, st));
+    return QM_OK;
+}
+
+int qm_generate_frames(qm_decoder *d, int32_t code_index, uint64_t seed, uint64_t first_frame, float snr, int32_t F,
+                       uint8_t *x, float *llr, uint8_t *syn, void *stream) {
+    if (!d || !x || !llr || !syn || F < 0 || !(snr > 0.0f)) return fail(QM_ERR_INVALID_ARG, "bad argument");
+    if (!d->bound) return fail(QM_ERR_NO_WORKSPACE, "no workspace bound");
+    if (code_index < 0 || code_index >= (int)d->slots.size()) return fail(QM_ERR_INVALID_ARG, "code_index out of range");
+    const Slot &s = d->slots[code_index];
+    QM_HIP(qm_launch_framegen(x, llr, syn, slot_bufs(*d, s).rows, s.code->mb, s.code->Z, s.n, s.m, F, seed,
+                              first_frame, snr, static_cast<hipStream_t>(stream)));
+    return QM_OK;
+}
+
+int qm_adam_step(float *w, const float *g, float *m, float *v, int32_t count, float lr, float b1, float b2, float eps,
+                 int32_t step, void *stream) {
+    if (!w || !g || !m || !v || count < 0 || step < 1) return fail(QM_ERR_INVALID_ARG, "bad argument");
+    if (count == 0) return QM_OK;
+    QM_HIP(qm_launch_adam(w, g, m, v, count, lr, b1, b2, eps, step, static_cast<hipStream_t>(stream)));
+    return QM_OK;
+}
+
+int qm_autotune(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t iters, uint8_t *hard, float *app,
+                uint8_t *flags, const char *cache_path, void *stream) {
+    if (!d) return fail(QM_ERR_INVALID_ARG, "decoder is NULL");
+    if (!d->bound) return fail(QM_ERR_NO_WORKSPACE, "no workspace bound");
+    if (!llr || !syn || !hard || !flags) return fail(QM_ERR_INVALID_ARG, "NULL buffer");
+    if (iters < 1) return fail(QM_ERR_INVALID_ARG, "iters must be >= 1");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int probe = std::min<int>(iters, 8);
+    const int saved_prof = d->profiling;
+    const int32_t saved_flags = d->flags;
+    d->profiling = 0;
+    d->flags &= ~QM_VALIDATE;
+    hipEvent_t e0, e1;
+    QM_HIP(hipEventCreate(&e0));
+    QM_HIP(hipEventCreate(&e1));
+    FILE *log = cache_path ? std::fopen(cache_path, "a") : nullptr;
+    int ncodes = 0;
+    for (const Slot &s : d->slots) ncodes += s.F > 0 ? 1 : 0;
+
+    auto trial = [&](const qm_tuning &t, float *ms) -> int {
+        d->tun = t;
+        drop_graph(*d);
+        int rc = qm_decode(d, llr, syn, probe, hard, app, flags, stream);  // warm-up (and capture)
+        if (rc != QM_OK) return rc;
+        QM_HIP(hipEventRecord(e0, st));
+        for (int r = 0; r < 2 && rc == QM_OK; ++r) rc = qm_decode(d, llr, syn, probe, hard, app, flags, stream);
+        if (rc != QM_OK) return rc;
+        QM_HIP(hipEventRecord(e1, st));
+        QM_HIP(hipEventSynchronize(e1));
+        float el = 0.0f;
+        QM_HIP(hipEventElapsedTime(&el, e0, e1));
+        *ms = el / 2.0f;
+        if (log)
+            std::fprintf(log,
+                         "{\"frames_per_tile\": %d, \"frames_per_lane\": %d, \"block\": %d, \"merge\": %d, "
+                         "\"fuse_codes\": %d, \"graph\": %d, \"stream_hint\": %d, \"iters\": %d, \"ms\": %.4f}\n",
+                         t.frames_per_tile, t.frames_per_lane, t.block, t.merge, t.fuse_codes, t.graph,
+                         t.stream_hint, probe, *ms);
+        return QM_OK;
+    };
+
+    qm_tuning best = d->tun;
+    float best_ms = 1e30f;
+    int rc = QM_OK;
+    const int fts[3] = {16, 32, 64}, fpls[2] = {1, 2}, blocks[2] = {128, 256};
+    for (int a = 0; a < 3 && rc == QM_OK; ++a)
+        for (int b = 0; b < 2 && rc == QM_OK; ++b)
+            for (int c = 0; c < 2 && rc == QM_OK; ++c) {
+                qm_tuning t = d->tun;
+                t.frames_per_tile = fts[a];
+                t.frames_per_lane = fpls[b];
+                t.block = blocks[c];
+                t.merge = 1;
+                t.fuse_codes = 1;
+                t.graph = 0;
+                t.persistent = 0;
+                float ms = 0.0f;
+                rc = trial(t, &ms);
+                if (rc == QM_OK && ms < best_ms) {
+                    best_ms = ms;
+                    best = t;
+                }
+            }
+    // structural variants on top of the best launch shape
+    for (int v = 0; v < 4 && rc == QM_OK; ++v) {
+        qm_tuning t = best;
+        if (v == 3) t.stream_hint = !t.stream_hint;
+        if (v == 0) t.merge = 0;
+        if (v == 1) {
+            if (ncodes < 2) continue;
+            t.fuse_codes = 0;
+        }
+        if (v == 2) t.graph = 1;
+        float ms = 0.0f;
+        rc = trial(t, &ms);
+        if (rc == QM_OK && ms < best_ms) {
+            best_ms = ms;
+            best = t;
+        }
+    }
+    if (log) std::fclose(log);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    d->tun = best;
+    drop_graph(*d);
+    d->profiling = saved_prof;
+    d->flags = saved_flags;
+    return rc;
 }
 
 }  // extern "C"

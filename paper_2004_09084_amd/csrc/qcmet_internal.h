@@ -21,6 +21,7 @@ struct RowDesc {
     int32_t d;                // entries in degree>=2 columns
     int32_t d1col;            // the row's degree-1 column, or -1
     int32_t d1shift;          // its shift
+    int32_t d1pos;            // its position among the row's columns (ascending column order)
     int32_t col[QM_MAXD];     // degree>=2 columns, ascending
     int32_t shift[QM_MAXD];   // their shifts
     int32_t ent[QM_MAXD];     // index of the entry among all degree>=2 entries (message slot)
@@ -53,6 +54,36 @@ struct LayerArgs {
     int64_t strideA, strideR, strideK;  // per-tile strides (elements)
 };
 
+// Codes one decoder can mix in a single fused launch.
+#define QM_MAX_CODES 4
+
+struct MultiLayerArgs {
+    LayerArgs code[QM_MAX_CODES];          // this step's layer of each code
+    int32_t block_off[QM_MAX_CODES + 1];   // workgroup ranges per code
+    int32_t ncodes;
+};
+
+// Min-sum (learned decoder) layer arguments.
+struct NmsLayerArgs {
+    LayerArgs L;              // A, R (float32), K = |LLR_d| with sign s ^ [LLR_d < 0]; L.last = 1:
+                              // also form the degree-1 APPs into Ad
+    float *Ad;                // [ntiles][m][FT] degree-1 APP per check
+    float *Q;                 // [ntiles][nent1*Z][FT] q recorded for the backward pass, or null
+    const float *W;           // this sweep's weights [mb][2 target types][alpha, beta]
+    const uint32_t *act;      // [Fpad] per-frame active flags (early termination), or null
+};
+
+struct NmsBwdArgs {
+    LayerArgs L;              // A (LLR in degree-1 columns), K, rows, geometry; L.last = last sweep
+    const float *Q;           // q of this sweep (recomputed)
+    float *gA;                // [ntiles][n][FT] dLoss/dAPP (in/out)
+    float *gR;                // [ntiles][nent1*Z][FT] dLoss/dr from later sweeps (in/out)
+    const float *gAd;         // [ntiles][m][FT] dLoss/dAPP of degree-1 variables (last sweep)
+    const float *W;           // this sweep's weights
+    float *part;              // per-workgroup sums [T][mb][ntiles][chunks][4]
+    int32_t t, mb;
+};
+
 // Kernel launchers (kernels.hip).  All return hipError_t of the launch.
 hipError_t qm_launch_to_tiles_f32(const float *in, float *out, int F, int64_t N, int ft_log2,
                                   int ntiles, hipStream_t s);
@@ -61,10 +92,34 @@ hipError_t qm_launch_to_tiles_u8(const uint8_t *in, uint8_t *out, int F, int64_t
 hipError_t qm_launch_kappa(const float *A, const uint8_t *Sil, float *K, const RowDesc *rows,
                            int mb, const TileGeom &g, hipStream_t s);
 hipError_t qm_launch_fill_u32(uint32_t *p, uint32_t v, size_t count, hipStream_t s);
-hipError_t qm_launch_layer(const LayerArgs &a, int msg16, int maxd, int fpl, int block, hipStream_t s);
-hipError_t qm_launch_syndrome(const float *A, const uint8_t *Sil, const RowDesc *rows, int mb,
+hipError_t qm_launch_layer(const LayerArgs &a, int msg16, int maxd, int fpl, int block, int hint, hipStream_t s);
+hipError_t qm_launch_layer_multi(const MultiLayerArgs &m, int msg16, int maxd, int fpl, int block, int hint,
+                                 hipStream_t s);
+hipError_t qm_launch_syndrome(const float *A, const float *Ad, const uint8_t *Sil, const RowDesc *rows, int mb,
                               uint32_t *fail, const TileGeom &g, hipStream_t s);
 hipError_t qm_launch_finalize(const float *A, const uint32_t *fail, float *app, uint8_t *hard,
                               uint8_t *flags, int F, const TileGeom &g, hipStream_t s);
+// nms.hip
+hipError_t qm_launch_nms_kappa(const float *A, const uint8_t *Sil, float *K, const RowDesc *rows, int mb,
+                               const TileGeom &g, hipStream_t s);
+hipError_t qm_launch_nms_layer(const NmsLayerArgs &na, int maxd, int fpl, int block, hipStream_t s);
+hipError_t qm_launch_nms_bwd(const NmsBwdArgs &ba, int maxd, int fpl, int block, hipStream_t s);
+// to_A = 1: A[d1col][(k + a) mod Z] = Ad[row][k]; to_A = 0: the reverse.
+hipError_t qm_launch_commit_d1(float *A, float *Ad, int to_A, const RowDesc *rows, int mb, const TileGeom &g,
+                               hipStream_t s);
+hipError_t qm_launch_et_update(uint32_t *fail, uint32_t *act, int32_t *iters, int Fpad, int done, hipStream_t s);
+hipError_t qm_launch_et_final(const uint32_t *act, int32_t *iters, int Fpad, int T, hipStream_t s);
+int qm_bce_blocks(int ncols, int mb, const TileGeom &g);
+hipError_t qm_launch_bce(const float *A, const float *Ad, const uint8_t *X, float *gA, float *gAd, float *part,
+                         const int32_t *cols, int ncols, const RowDesc *rows, int mb, const TileGeom &g, int F,
+                         float *loss, hipStream_t s);
+hipError_t qm_launch_grad_reduce(const float *part, float *grad, int T, int mb, int per_row, hipStream_t s);
+hipError_t qm_launch_adam(float *w, const float *g, float *m, float *v, int n, float lr, float b1, float b2, float eps,
+                          int step, hipStream_t s);
+
+// framegen.hip
+hipError_t qm_launch_framegen(uint8_t *x, float *llr, uint8_t *syn, const RowDesc *rows, int mb, int Z, int64_t n,
+                              int64_t m, int F, uint64_t seed, uint64_t first, float snr, hipStream_t s);
+
 hipError_t qm_launch_validate(const float *llr, size_t nl, const uint8_t *syn, size_t ns,
                               uint32_t *err, hipStream_t s);

@@ -39,7 +39,8 @@ EXPORTED = [
     "qm_code_set_schedule", "qm_code_get_schedule", "qm_decoder_create", "qm_decoder_destroy",
     "qm_decoder_workspace_bytes", "qm_decoder_bind_workspace", "qm_decoder_set_tuning",
     "qm_decoder_get_tuning", "qm_decode", "qm_autotune", "qm_decoder_set_profiling",
-    "qm_decoder_get_profile",
+    "qm_decoder_get_profile", "qm_nms_workspace_bytes", "qm_nms_bind_workspace", "qm_nms_decode",
+    "qm_nms_loss_grad", "qm_adam_step", "qm_generate_frames",
 ]
 
 
@@ -60,7 +61,8 @@ class qm_code_info(ctypes.Structure):
 class qm_tuning(ctypes.Structure):
     _fields_ = [("frames_per_tile", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("merge", ctypes.c_int32), ("persistent", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("frames_per_lane", ctypes.c_int32)]
+                ("frames_per_lane", ctypes.c_int32), ("fuse_codes", ctypes.c_int32),
+                ("stream_hint", ctypes.c_int32)]
 
 
 class qm_profile(ctypes.Structure):
@@ -95,12 +97,22 @@ def lib():
         L.qm_decoder_set_tuning.argtypes = [p, ctypes.POINTER(qm_tuning)]
         L.qm_decoder_get_tuning.argtypes = [p, ctypes.POINTER(qm_tuning)]
         L.qm_decode.argtypes = [p, p, p, i32, p, p, p, p]
-        L.qm_autotune.argtypes = [p, p, p, i32, ctypes.c_char_p, p]
+        L.qm_autotune.argtypes = [p, p, p, i32, p, p, p, ctypes.c_char_p, p]
         L.qm_decoder_set_profiling.argtypes = [p, i32]
         L.qm_decoder_get_profile.argtypes = [p, ctypes.POINTER(qm_profile), i32]
+        L.qm_nms_workspace_bytes.argtypes = [p, i32, i32]
+        L.qm_nms_workspace_bytes.restype = sz
+        L.qm_nms_bind_workspace.argtypes = [p, p, sz, i32, i32]
+        L.qm_nms_decode.argtypes = [p, p, p, p, i32, i32, p, p, p, p, p]
+        L.qm_nms_loss_grad.argtypes = [p, p, p, p, p, i32, p, p, p]
+        f32 = ctypes.c_float
+        L.qm_adam_step.argtypes = [p, p, p, p, i32, f32, f32, f32, f32, i32, p]
+        u64 = ctypes.c_uint64
+        L.qm_generate_frames.argtypes = [p, i32, u64, u64, f32, i32, p, p, p, p]
         for name in EXPORTED:
             f = getattr(L, name)
-            if name not in ("qm_last_error", "qm_decoder_workspace_bytes", "qm_abi_version"):
+            if name not in ("qm_last_error", "qm_decoder_workspace_bytes", "qm_abi_version",
+                            "qm_nms_workspace_bytes"):
                 f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -193,8 +205,8 @@ def qm_decoder_bind_workspace(dec, ws) -> None:
 
 
 def qm_decoder_set_tuning(dec, frames_per_tile=0, block=0, merge=1, persistent=0, graph=0,
-                          frames_per_lane=0) -> None:
-    t = qm_tuning(frames_per_tile, block, merge, persistent, graph, frames_per_lane)
+                          frames_per_lane=0, fuse_codes=1, stream_hint=1) -> None:
+    t = qm_tuning(frames_per_tile, block, merge, persistent, graph, frames_per_lane, fuse_codes, stream_hint)
     _check(lib().qm_decoder_set_tuning(dec, ctypes.byref(t)))
 
 
@@ -209,9 +221,10 @@ def qm_decode(dec, llr, syndrome, iters: int, hard, app, flags, stream=None) -> 
                            _dptr(flags), _stream_handle(stream)))
 
 
-def qm_autotune(dec, llr, syndrome, iters: int, cache_path: str | None = None, stream=None) -> None:
-    _check(lib().qm_autotune(dec, _dptr(llr), _dptr(syndrome), int(iters),
-                             cache_path.encode() if cache_path else None, _stream_handle(stream)))
+def qm_autotune(dec, llr, syndrome, iters: int, hard, app, flags, cache_path: str | None = None,
+                stream=None) -> None:
+    _check(lib().qm_autotune(dec, _dptr(llr), _dptr(syndrome), int(iters), _dptr(hard), _dptr(app),
+                             _dptr(flags), cache_path.encode() if cache_path else None, _stream_handle(stream)))
 
 
 def qm_decoder_set_profiling(dec, enable: bool) -> None:
@@ -222,6 +235,36 @@ def qm_decoder_get_profile(dec, reset: bool = True) -> dict:
     p = qm_profile()
     _check(lib().qm_decoder_get_profile(dec, ctypes.byref(p), 1 if reset else 0))
     return {f: getattr(p, f) for f, _ in qm_profile._fields_}
+
+
+def qm_nms_workspace_bytes(dec, T: int, train: bool) -> int:
+    return int(lib().qm_nms_workspace_bytes(dec, int(T), 1 if train else 0))
+
+
+def qm_nms_bind_workspace(dec, ws, T: int, train: bool) -> None:
+    _check(lib().qm_nms_bind_workspace(dec, _dptr(ws), ws.numel() * ws.element_size(), int(T), 1 if train else 0))
+
+
+def qm_nms_decode(dec, weights, llr, syndrome, T: int, early_stop: bool, hard, app, flags, iters_used,
+                  stream=None) -> None:
+    _check(lib().qm_nms_decode(dec, _dptr(weights), _dptr(llr), _dptr(syndrome), int(T), 1 if early_stop else 0,
+                               _dptr(hard), _dptr(app), _dptr(flags), _dptr(iters_used), _stream_handle(stream)))
+
+
+def qm_nms_loss_grad(dec, weights, llr, syndrome, x, T: int, loss, grad, stream=None) -> None:
+    _check(lib().qm_nms_loss_grad(dec, _dptr(weights), _dptr(llr), _dptr(syndrome), _dptr(x), int(T), _dptr(loss),
+                                  _dptr(grad), _stream_handle(stream)))
+
+
+def qm_generate_frames(dec, code_index: int, seed: int, first_frame: int, snr: float, F: int, x, llr, syndrome,
+                       stream=None) -> None:
+    _check(lib().qm_generate_frames(dec, int(code_index), int(seed), int(first_frame), float(snr), int(F), _dptr(x),
+                                    _dptr(llr), _dptr(syndrome), _stream_handle(stream)))
+
+
+def qm_adam_step(w, g, m, v, lr: float, b1: float, b2: float, eps: float, step: int, stream=None) -> None:
+    _check(lib().qm_adam_step(_dptr(w), _dptr(g), _dptr(m), _dptr(v), w.numel(), float(lr), float(b1), float(b2),
+                              float(eps), int(step), _stream_handle(stream)))
 
 
 # ------------------------------------------------------ convenience layer --
@@ -323,9 +366,35 @@ class Decoder:
     def profile(self, reset: bool = True) -> dict:
         return qm_decoder_get_profile(self.handle, reset)
 
-    def autotune(self, llr, syndrome, iters: int, cache_path: str | None = None, stream=None):
-        qm_autotune(self.handle, llr.reshape(-1), syndrome.reshape(-1), iters, cache_path, stream)
-        self._bind()
+    def autotune(self, llr, syndrome, iters: int, cache_path: str | None = None, stream=None, out=None):
+        hard, app, flags = out if out is not None else self.alloc_outputs(True)
+        qm_autotune(self.handle, llr.reshape(-1), syndrome.reshape(-1), iters, hard, app, flags, cache_path, stream)
+        return self.tuning()
+
+    # ---- learned decoder (normalized/offset min-sum) ----
+    def nms_bind(self, T: int, train: bool = False):
+        import torch
+        nbytes = qm_nms_workspace_bytes(self.handle, T, train)
+        if nbytes == 0:
+            raise QMError(QM_ERR_UNSUPPORTED, "min-sum needs exactly one code with float32 messages")
+        self.nms_workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        qm_nms_bind_workspace(self.handle, self.nms_workspace, T, train)
+
+    def nms_decode(self, weights, llr, syndrome, T: int, early_stop: bool = False, out=None, stream=None):
+        import torch
+        hard, app, flags = out if out is not None else self.alloc_outputs(True)
+        iters = torch.empty(self.F_total, dtype=torch.int32, device=self.device)
+        qm_nms_decode(self.handle, weights.reshape(-1), llr.reshape(-1), syndrome.reshape(-1), T, early_stop,
+                      hard, app, flags, iters, stream)
+        return hard, app, flags, iters
+
+    def nms_loss_grad(self, weights, llr, syndrome, x, T: int, stream=None):
+        import torch
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        grad = torch.empty_like(weights)
+        qm_nms_loss_grad(self.handle, weights.reshape(-1), llr.reshape(-1), syndrome.reshape(-1), x.reshape(-1), T,
+                         loss, grad, stream)
+        return loss, grad
 
     def __del__(self):
         h = getattr(self, "handle", None)

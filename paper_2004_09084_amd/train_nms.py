@@ -1,0 +1,173 @@
+"""Train and evaluate the learned (normalized/offset min-sum) decoder on the GPU.
+
+Training: every step draws fresh frames on the GPU (Philox4x32-10; half at
+each training SNR), runs T unrolled min-sum sweeps with per-sweep
+checkpoints, the mean binary cross-entropy of the final APPs and its exact
+gradient (qm_nms_loss_grad), then one Adam step (qm_adam_step).  Weights
+start at plain min-sum (alpha = 1, beta = 0).
+
+Evaluation: a seeded batch from the workload module, decoded by the trained
+min-sum with per-sweep syndrome tests (early stop, mean iterations); frames
+that do not reach a valid word are decoded again from their channel LLRs by
+plain sum-product, which also serves as the reference.  Reports FER, mean
+iterations and decoded Mbit/s for: trained min-sum + sum-product fallback,
+untrained min-sum + fallback, plain sum-product.
+
+Every step of the decoders runs in libqcmet's kernels; this file only
+sequences calls and moves a few scalars to the host for logging.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+if os.path.dirname(HERE) not in sys.path:
+    sys.path.insert(0, os.path.dirname(HERE))
+
+from paper_2004_09084_amd import qcmet as Q  # noqa: E402
+from paper_2004_09084_amd import workload as W  # noqa: E402
+
+
+def plain_minsum_weights(T, mb, device="cuda"):
+    import torch
+    w = torch.zeros((T, mb, 2, 2), dtype=torch.float32, device=device)
+    w[..., 0] = 1.0
+    return w
+
+
+def train(spec, shifts, steps=2000, frames=16, T=100, lr=1e-3, snrs=(0.161, 0.15), seed=0, log_every=100,
+          weights=None, log=print):
+    import torch
+    code = Q.Code(shifts, spec.Z)
+    dec = Q.Decoder([code], [frames])
+    dec.nms_bind(T, train=True)
+    w = plain_minsum_weights(T, spec.mb) if weights is None else weights.clone()
+    m = torch.zeros_like(w)
+    v = torch.zeros_like(w)
+    x = torch.empty(frames * spec.n, dtype=torch.uint8, device="cuda")
+    llr = torch.empty(frames * spec.n, dtype=torch.float32, device="cuda")
+    syn = torch.empty(frames * spec.m, dtype=torch.uint8, device="cuda")
+    per = frames // len(snrs)
+    history = []
+    t0 = time.perf_counter()
+    for step in range(1, steps + 1):
+        for i, snr in enumerate(snrs):
+            F = per if i < len(snrs) - 1 else frames - per * (len(snrs) - 1)
+            o = i * per
+            Q.qm_generate_frames(dec.handle, 0, seed, (step * frames + o), snr, F,
+                                 x[o * spec.n:(o + F) * spec.n], llr[o * spec.n:(o + F) * spec.n],
+                                 syn[o * spec.m:(o + F) * spec.m])
+        loss, grad = dec.nms_loss_grad(w, llr, syn, x, T)
+        Q.qm_adam_step(w, grad, m, v, lr, 0.9, 0.999, 1e-8, step)
+        if step % log_every == 0 or step == 1 or step == steps:
+            lv = float(loss.item())
+            history.append((step, lv))
+            log(json.dumps({"step": step, "loss": round(lv, 6), "elapsed_s": round(time.perf_counter() - t0, 1)}))
+    torch.cuda.synchronize()
+    return w, history, time.perf_counter() - t0
+
+
+def evaluate(spec, shifts, weights, T_nms=100, T_sp=200, frames=128, frame_seed=2, snr=None, log=print):
+    """FER / mean iterations / Mbit/s of min-sum (+ sum-product fallback) and
+    of plain sum-product on one seeded batch."""
+    import torch
+    wl = W.build(spec, frames, graph_seed=0, frame_seed=frame_seed, snr=snr)
+    L = torch.from_numpy(wl.llr.reshape(-1)).cuda()
+    S = torch.from_numpy(wl.s.reshape(-1)).cuda()
+    code = Q.Code(shifts, spec.Z)
+
+    def frame_errors(hard):
+        return (hard.cpu().numpy().reshape(frames, -1) != wl.x).any(axis=1)
+
+    # plain sum-product (the fallback decoder and the reference)
+    sp = Q.Decoder([code], [frames])
+    sp.decode(L, S, T_sp)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hs, _, fs = sp.decode(L, S, T_sp)
+    torch.cuda.synchronize()
+    t_sp = time.perf_counter() - t0
+    err_sp = frame_errors(hs)
+
+    res = {"snr": wl.meta["snr"], "frames": frames,
+           "sum_product": {"fer": float(err_sp.mean()), "syndrome_fail": float(1 - fs.cpu().numpy().mean()),
+                           "iterations": T_sp, "mbit_s": frames * spec.n / 1e6 / t_sp}}
+    nm = Q.Decoder([code], [frames])
+    nm.nms_bind(T_nms, train=False)
+    for name, w in (("trained_minsum", weights), ("plain_minsum", plain_minsum_weights(T_nms, spec.mb))):
+        w = w[:T_nms].contiguous()
+        nm.nms_decode(w, L, S, T_nms, early_stop=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hn, an, fn, it = nm.nms_decode(w, L, S, T_nms, early_stop=True)
+        torch.cuda.synchronize()
+        t_nms = time.perf_counter() - t0
+        ok = fn.cpu().numpy().astype(bool)
+        hard = hn.cpu().numpy().reshape(frames, -1).copy()
+        t_fb = 0.0
+        nfail = int((~ok).sum())
+        if nfail:
+            idx = np.nonzero(~ok)[0]
+            fb = Q.Decoder([code], [nfail])
+            Lf = torch.from_numpy(wl.llr[idx].reshape(-1)).cuda()
+            Sf = torch.from_numpy(wl.s[idx].reshape(-1)).cuda()
+            fb.decode(Lf, Sf, T_sp)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            hf, _, _ = fb.decode(Lf, Sf, T_sp)
+            torch.cuda.synchronize()
+            t_fb = time.perf_counter() - t0
+            hard[idx] = hf.cpu().numpy().reshape(nfail, -1)
+        err = (hard != wl.x).any(axis=1)
+        res[name] = {"fer_minsum_only": float(frame_errors(hn).mean()),
+                     "converged": int(ok.sum()),
+                     "mean_iterations": float(it.cpu().numpy().mean()),
+                     "fer_with_fallback": float(err.mean()),
+                     "fallback_frames": nfail,
+                     "mbit_s_with_fallback": frames * spec.n / 1e6 / (t_nms + t_fb),
+                     "seconds_minsum": t_nms, "seconds_fallback": t_fb}
+    log(json.dumps(res))
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--spec", default="r0.1_Z20000")
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--frames", type=int, default=16)
+    ap.add_argument("--T", type=int, default=100)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--eval-frames", type=int, default=128)
+    ap.add_argument("--eval-snrs", default="0.161")
+    ap.add_argument("--save", default=None, help="write trained weights (.npy)")
+    ap.add_argument("--load", default=None, help="start from weights (.npy)")
+    args = ap.parse_args()
+    import torch
+    spec = W.SPECS[args.spec]
+    shifts = W.make_code(spec, 0)
+    w0 = None
+    if args.load:
+        w0 = torch.from_numpy(np.load(args.load)).cuda()
+    w = w0
+    if args.steps > 0:
+        w, hist, secs = train(spec, shifts, steps=args.steps, frames=args.frames, T=args.T, lr=args.lr,
+                              seed=args.seed, weights=w0)
+        print(json.dumps({"trained_steps": args.steps, "train_seconds": round(secs, 1),
+                          "loss_first": hist[0][1], "loss_last": hist[-1][1]}), flush=True)
+    if w is None:
+        w = plain_minsum_weights(args.T, spec.mb)
+    if args.save:
+        np.save(args.save, w.cpu().numpy())
+    for snr in [float(s) for s in args.eval_snrs.split(",") if s]:
+        evaluate(spec, shifts, w, T_nms=args.T, frames=args.eval_frames, snr=snr)
+
+
+if __name__ == "__main__":
+    main()

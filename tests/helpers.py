@@ -83,3 +83,40 @@ def frame_for(H_dense, x, snr, rng):
     llr = (2.0 * y / sigma2).astype(np.float32)
     s = (H_dense.astype(np.int64) @ x.astype(np.int64) % 2).astype(np.uint8)
     return llr, s
+
+
+# Philox4x32-10 (Salmon et al., SC 2011), vectorised over counters.
+_M0, _M1 = 0xD2511F53, 0xCD9E8D57
+_W0, _W1 = 0x9E3779B9, 0xBB67AE85
+
+
+def philox4x32_10(c0, c1, c2, c3, k0, k1):
+    mask = np.uint64(0xFFFFFFFF)
+    c0, c1, c2, c3 = (np.asarray(v, dtype=np.uint64) & mask for v in (c0, c1, c2, c3))
+    k0, k1 = np.uint64(k0), np.uint64(k1)
+    for r in range(10):
+        if r > 0:
+            k0 = (k0 + np.uint64(_W0)) & mask
+            k1 = (k1 + np.uint64(_W1)) & mask
+        p0 = np.uint64(_M0) * c0
+        p1 = np.uint64(_M1) * c2
+        hi0, lo0 = p0 >> np.uint64(32), p0 & mask
+        hi1, lo1 = p1 >> np.uint64(32), p1 & mask
+        c0, c1, c2, c3 = (hi1 ^ c1 ^ k0) & mask, lo1, (hi0 ^ c3 ^ k1) & mask, lo0
+    return c0, c1, c2, c3
+
+
+def philox_frame(n, seed, frame, snr):
+    """The GPU frame generator's definition in FP64: (x bits, standard normals)."""
+    p = np.arange((n + 1) // 2, dtype=np.uint64)
+    r0, r1, r2, r3 = philox4x32_10(p, frame & 0xFFFFFFFF, frame >> 32, 0, seed & 0xFFFFFFFF, seed >> 32)
+    u1 = (r0.astype(np.float64) + 0.5) * 2.0 ** -32
+    u2 = (r1.astype(np.float64) + 0.5) * 2.0 ** -32
+    rad = np.sqrt(-2.0 * np.log(u1))
+    x = np.empty(2 * len(p), dtype=np.uint8)
+    x[0::2] = (r2 >> np.uint64(31)).astype(np.uint8)
+    x[1::2] = (r3 >> np.uint64(31)).astype(np.uint8)
+    nrm = np.empty(2 * len(p))
+    nrm[0::2] = rad * np.cos(2 * np.pi * u2)
+    nrm[1::2] = rad * np.sin(2 * np.pi * u2)
+    return x[:n], nrm[:n]

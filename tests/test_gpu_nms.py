@@ -1,0 +1,174 @@
+"""Learned decoder (normalized/offset min-sum) on the GPU against the FP64
+oracle: forward APPs, early-stop iteration counts, loss and weight
+gradients; determinism of the gradient reduction; the Adam step."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2004_09084_amd import qcmet as Q
+from paper_2004_09084_amd import workload as W
+from tests.gpu_util import compare, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+SMALL = W.RATE01_SMALL
+
+
+def _weights(T, mb, seed=0, lo=0.6, hi=1.0, bmax=0.3):
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(lo, hi, (T, mb, 2))
+    b = rng.uniform(0.0, bmax, (T, mb, 2))
+    w = np.stack([a, b], axis=-1).astype(np.float32)   # [T][mb][2][2]
+    return w, a, b
+
+
+def _dec(H, Z, F, T, train=False, tuning=None):
+    code = Q.Code(H, Z)
+    dec = Q.Decoder([code], [F], tuning=tuning)
+    dec.nms_bind(T, train)
+    return code, dec
+
+
+@pytest.mark.parametrize("T", [1, 2, 5])
+def test_nms_forward_matches_oracle(T):
+    import torch
+    wl = W.build(SMALL, 6, snr=0.3, frame_seed=2)
+    w, a, b = _weights(T, SMALL.mb, seed=T)
+    # the oracle takes the float32 weights the GPU uses
+    a, b = w[..., 0].astype(np.float64), w[..., 1].astype(np.float64)
+    code, dec = _dec(wl.shifts, SMALL.Z, 6, T)
+    hard, app, fl, it = dec.nms_decode(to_dev(w), to_dev(wl.llr), to_dev(wl.s), T)
+    torch.cuda.synchronize()
+    appo, hardo, flo, ito = oracle.nms_decode(wl.shifts, SMALL.Z, wl.llr, wl.s, T, a, b)
+    rows = compare(app.cpu().numpy().reshape(6, -1), hard.cpu().numpy().reshape(6, -1), fl.cpu().numpy(),
+                   appo, hardo, flo)
+    say(f"nms T={T}", [r["max_rel"] for r in rows])
+    for r in rows:
+        assert r["app_viol"] == 0 and r["bits_diff_confident"] == 0 and r["flag_o"] == r["flag_g"], r
+    assert (it.cpu().numpy() == T).all()
+
+
+def test_nms_early_stop_matches_oracle():
+    import torch
+    T = 30
+    wl = W.build(SMALL, 16, snr=0.8, frame_seed=5)
+    w = np.zeros((T, SMALL.mb, 2, 2), dtype=np.float32)
+    w[..., 0] = 0.8
+    w[..., 1] = 0.05
+    a, b = w[..., 0].astype(np.float64), w[..., 1].astype(np.float64)
+    code, dec = _dec(wl.shifts, SMALL.Z, 16, T)
+    hard, app, fl, it = dec.nms_decode(to_dev(w), to_dev(wl.llr), to_dev(wl.s), T, early_stop=True)
+    torch.cuda.synchronize()
+    appo, hardo, flo, ito = oracle.nms_decode(wl.shifts, SMALL.Z, wl.llr, wl.s, T, a, b, early_stop=True)
+    say("early stop iters", it.cpu().numpy().tolist(), ito.tolist())
+    assert np.array_equal(it.cpu().numpy(), ito)
+    assert np.array_equal(fl.cpu().numpy(), flo)
+    assert flo.sum() >= 8
+    assert np.array_equal(hard.cpu().numpy().reshape(16, -1), hardo)
+
+
+def test_nms_zero_noise_stops_at_zero_iterations():
+    import torch
+    H = W.make_code(SMALL, 0)
+    X, L, S = W.make_frames(H, SMALL.Z, 0.161, 4, seed=3, zero_noise=True)
+    w = np.ones((5, SMALL.mb, 2, 2), dtype=np.float32)
+    w[..., 1] = 0.0
+    code, dec = _dec(H, SMALL.Z, 4, 5)
+    hard, app, fl, it = dec.nms_decode(to_dev(w), to_dev(L), to_dev(S), 5, early_stop=True)
+    torch.cuda.synchronize()
+    assert (it.cpu().numpy() == 0).all() and fl.cpu().numpy().all()
+    assert np.array_equal(hard.cpu().numpy().reshape(4, -1), X)
+
+
+@pytest.mark.parametrize("T,F", [(2, 4), (4, 5)])
+def test_nms_loss_and_gradients_match_oracle(T, F):
+    import torch
+    wl = W.build(SMALL, F, snr=0.5, frame_seed=7)
+    w, _, _ = _weights(T, SMALL.mb, seed=11)
+    a, b = w[..., 0].astype(np.float64), w[..., 1].astype(np.float64)
+    code, dec = _dec(wl.shifts, SMALL.Z, F, T, train=True)
+    loss, grad = dec.nms_loss_grad(to_dev(w), to_dev(wl.llr), to_dev(wl.s), to_dev(wl.x), T)
+    torch.cuda.synchronize()
+    lo, ga, gb, _ = oracle.nms_loss_grad(wl.shifts, SMALL.Z, wl.llr, wl.s, wl.x, T, a, b)
+    g = grad.cpu().numpy().reshape(T, SMALL.mb, 2, 2).astype(np.float64)
+    say(f"loss gpu {float(loss.cpu()):.8f} oracle {lo:.8f}")
+    assert abs(float(loss.cpu()) - lo) <= 1e-5 * abs(lo)
+    for comp, ref in ((0, ga), (1, gb)):
+        got = g[..., comp]
+        scale = np.abs(ref).max()
+        err = np.abs(got - ref)
+        say(f"grad comp {comp}: max |g| {scale:.3e} max err {err.max():.3e}")
+        assert np.all(err <= 1e-3 * np.abs(ref) + 2e-4 * scale), (comp, np.argwhere(err > 1e-3 * np.abs(ref) + 2e-4 * scale)[:5])
+    # degree-1 weights act only in the last sweep
+    assert np.all(g[:T - 1, :, 1, :] == 0.0)
+
+
+def test_nms_gradients_are_deterministic():
+    import torch
+    T, F = 3, 8
+    wl = W.build(SMALL, F, snr=0.4, frame_seed=8)
+    w, _, _ = _weights(T, SMALL.mb, seed=3)
+    code, dec = _dec(wl.shifts, SMALL.Z, F, T, train=True)
+    args = (to_dev(w), to_dev(wl.llr), to_dev(wl.s), to_dev(wl.x), T)
+    l1, g1 = dec.nms_loss_grad(*args)
+    l2, g2 = dec.nms_loss_grad(*args)
+    torch.cuda.synchronize()
+    assert np.array_equal(g1.cpu().numpy(), g2.cpu().numpy())
+    assert np.array_equal(l1.cpu().numpy(), l2.cpu().numpy())
+
+
+def test_sum_product_and_minsum_agree_on_degree2_codes_on_gpu():
+    # on all-degree-2 checks SP passes the other message through, as does
+    # min-sum with alpha = 1, beta = 0 (clip range aside)
+    import torch
+    rng = np.random.default_rng(4)
+    Z, nb, T = 16, 6, 3
+    H = np.full((nb, nb), -1, dtype=np.int32)
+    for i in range(nb):
+        H[i, i] = rng.integers(0, Z)
+        H[i, (i + 1) % nb] = rng.integers(0, Z)
+    from tests.helpers import dense_H, frame_for
+    Hd = dense_H(H, Z)
+    L, S = [], []
+    for f in range(4):
+        x = rng.integers(0, 2, nb * Z).astype(np.uint8)
+        l, s = frame_for(Hd, x, 2.0, rng)
+        L.append(np.clip(l, -3, 3)); S.append(s)
+    L, S = np.array(L, dtype=np.float32), np.array(S)
+    code = Q.Code(H, Z)
+    dsp = Q.Decoder([code], [4])
+    _, app_sp, _ = dsp.decode(to_dev(L), to_dev(S), T)
+    w = np.zeros((T, nb, 2, 2), dtype=np.float32)
+    w[..., 0] = 1.0
+    dn = Q.Decoder([code], [4])
+    dn.nms_bind(T)
+    _, app_ms, _, _ = dn.nms_decode(to_dev(w), to_dev(L), to_dev(S), T)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(app_sp.cpu().numpy() - app_ms.cpu().numpy())) < 1e-4
+
+
+def test_adam_step_matches_numpy():
+    import torch
+    rng = np.random.default_rng(0)
+    n = 1000
+    w = rng.normal(size=n).astype(np.float32)
+    g = rng.normal(size=n).astype(np.float32)
+    m = rng.normal(size=n).astype(np.float32) * 0.1
+    v = np.abs(rng.normal(size=n)).astype(np.float32) * 0.1
+    wd, gd, md, vd = (torch.from_numpy(a.copy()).cuda() for a in (w, g, m, v))
+    Q.qm_adam_step(wd, gd, md, vd, 1e-3, 0.9, 0.999, 1e-8, 5)
+    torch.cuda.synchronize()
+    m2 = 0.9 * m.astype(np.float64) + 0.1 * g
+    v2 = 0.999 * v.astype(np.float64) + 0.001 * g.astype(np.float64) ** 2
+    w2 = w - 1e-3 * (m2 / (1 - 0.9 ** 5)) / (np.sqrt(v2 / (1 - 0.999 ** 5)) + 1e-8)
+    assert np.allclose(wd.cpu().numpy(), w2, rtol=1e-5, atol=1e-7)
+    assert np.allclose(md.cpu().numpy(), m2, rtol=1e-5, atol=1e-7)
+
+
+def test_nms_requires_one_float32_code():
+    H = W.make_code(SMALL, 0)
+    code = Q.Code(H, SMALL.Z)
+    d16 = Q.Decoder([code], [4], flags=Q.QM_MSG_FP16)
+    assert Q.qm_nms_workspace_bytes(d16.handle, 3, False) == 0
+    d2 = Q.Decoder([code, code], [2, 2])
+    assert Q.qm_nms_workspace_bytes(d2.handle, 3, False) == 0

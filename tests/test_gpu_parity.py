@@ -148,7 +148,7 @@ def test_tunings_are_bit_identical():
     ref = gpu_decode(wl.shifts, SMALL.Z, wl.llr, wl.s, 12)
     for tun in (dict(frames_per_tile=1, frames_per_lane=1), dict(frames_per_tile=4, block=64, frames_per_lane=1), dict(frames_per_tile=8, block=128, frames_per_lane=2),
                 dict(frames_per_tile=16, merge=0), dict(frames_per_tile=2, block=128, merge=0),
-                dict(frames_per_tile=16, graph=1)):
+                dict(frames_per_tile=16, graph=1), dict(stream_hint=1), dict(frames_per_tile=32, stream_hint=1, merge=0)):
         got = gpu_decode(wl.shifts, SMALL.Z, wl.llr, wl.s, 12, tuning=tun)
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]) and np.array_equal(got[2], ref[2]), tun
 
@@ -216,3 +216,78 @@ def test_validation_flag_rejects_bad_inputs():
         dec.decode(to_dev(wl.llr), to_dev(S), 2)
     assert e.value.code == Q.QM_ERR_INPUT
     hard, app, fl = dec.decode(to_dev(wl.llr), to_dev(wl.s), 2)   # clean inputs pass
+
+
+# ------------------------------------------------------- mixed batches --
+
+def _mixed(specs, Fs, snr_scale=2.0, T=6):
+    import torch
+    wls = [_wl(s, F, snr=s.snr * snr_scale, seed=1) for s, F in zip(specs, Fs)]
+    codes = [Q.Code(w.shifts, s.Z) for w, s in zip(wls, specs)]
+    L = to_dev(np.concatenate([w.llr.reshape(-1) for w in wls]))
+    S = to_dev(np.concatenate([w.s.reshape(-1) for w in wls]))
+    return wls, codes, L, S
+
+
+def test_fused_mixed_batch_equals_unfused_and_single_code():
+    import torch
+    specs = [SMALL, W.RATE005.with_Z(16), W.RATE002.with_Z(16)]
+    Fs = [64, 32, 32]
+    wls, codes, L, S = _mixed(specs, Fs)
+    outs = {}
+    for fuse in (1, 0):
+        for flags in (0, Q.QM_MSG_FP16):
+            dec = Q.Decoder(codes, Fs, flags=flags, tuning=dict(fuse_codes=fuse))
+            h, a, f = dec.decode(L, S, 9)
+            torch.cuda.synchronize()
+            outs[(fuse, flags)] = (h.cpu().numpy(), a.cpu().numpy(), f.cpu().numpy())
+    for flags in (0, Q.QM_MSG_FP16):
+        for x, y in zip(outs[(1, flags)], outs[(0, flags)]):
+            assert np.array_equal(x, y)
+    # and against one decoder per code (FP32)
+    on = of = 0
+    for w, s, F in zip(wls, specs, Fs):
+        h1, a1, f1 = gpu_decode(w.shifts, s.Z, w.llr, w.s, 9)
+        assert np.array_equal(outs[(1, 0)][1][on:on + F * s.n], a1.reshape(-1))
+        assert np.array_equal(outs[(1, 0)][2][of:of + F], f1)
+        on += F * s.n
+        of += F
+
+
+def test_fused_mixed_batch_matches_oracle_per_code():
+    import torch
+    specs = [SMALL, W.RATE005.with_Z(16), W.RATE002.with_Z(16)]
+    Fs = [5, 3, 4]
+    wls, codes, L, S = _mixed(specs, Fs, snr_scale=3.0)
+    dec = Q.Decoder(codes, Fs, tuning=dict(fuse_codes=1))
+    for T in (1, 2):
+        h, a, f = dec.decode(L, S, T)
+        torch.cuda.synchronize()
+        a, h, f = a.cpu().numpy(), h.cpu().numpy(), f.cpu().numpy()
+        on = of = 0
+        for w, s, F in zip(wls, specs, Fs):
+            appo, hardo, flo, _ = oracle.decode_sp(w.shifts, s.Z, w.llr, w.s, T)
+            rows = compare(a[on:on + F * s.n].reshape(F, -1), h[on:on + F * s.n].reshape(F, -1), f[of:of + F],
+                           appo, hardo, flo)
+            for r in rows:
+                assert r["app_viol"] == 0 and r["bits_diff_confident"] == 0 and r["flag_o"] == r["flag_g"], (s.name, r)
+            on += F * s.n
+            of += F
+
+
+def test_autotune_picks_a_result_preserving_tuning(tmp_path):
+    import json
+    import torch
+    specs = [SMALL, W.RATE002.with_Z(16)]
+    Fs = [32, 16]
+    wls, codes, L, S = _mixed(specs, Fs)
+    dec = Q.Decoder(codes, Fs)
+    ref = [t.cpu().numpy() for t in dec.decode(L, S, 7)]
+    log = str(tmp_path / "tune.jsonl")
+    tun = dec.autotune(L, S, 7, cache_path=log)
+    trials = [json.loads(l) for l in open(log)]
+    assert len(trials) >= 12
+    got = [t.cpu().numpy() for t in dec.decode(L, S, 7)]
+    torch.cuda.synchronize()
+    for x, y in zip(ref, got):
+        assert np.array_equal(x, y), tun

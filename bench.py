@@ -28,25 +28,28 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "decoded Mbit/s (N frames x 10^6 bits, fixed iters) + HBM GB/s; FER at SNR"
 
 WORKLOADS = {
-    # name: (spec name, frames, iterations)
-    "r0.1": ("r0.1_Z20000", 128, 200),
-    "r0.05": ("r0.05_Z10000", 128, 200),
-    "r0.02": ("r0.02_Z10000", 128, 200),
-    "small": ("r0.1_Z64", 4, 50),
+    # name: ([(spec name, frames), ...], iterations)
+    "r0.1": ([("r0.1_Z20000", 128)], 200),
+    "r0.05": ([("r0.05_Z10000", 128)], 200),
+    "r0.02": ([("r0.02_Z10000", 128)], 200),
+    "small": ([("r0.1_Z64", 4)], 50),
+    # mixed-rate batch: 64 + 32 + 32 frames of the three codes, fused launches
+    "mixed": ([("r0.1_Z20000", 64), ("r0.05_Z10000", 32), ("r0.02_Z10000", 32)], 200),
 }
 
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("kernels.hip", "api.cpp", "qcmet_internal.h"):
+    for f in ("kernels.hip", "device_common.h", "qcmet_internal.h"):
         with open(os.path.join(ROOT, "paper_2004_09084_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
 def load_traffic(workload_key: str, fp16: bool):
-    """HBM bytes per layer launch from the committed rocprofv3 counter runs,
-    if they were taken on the current kernel source; else None."""
+    """Off-chip bytes per layer launch from the committed rocprofv3 counter
+    runs (FETCH_SIZE, WRITE_SIZE, calibrated), if they were taken on the
+    current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "layer_traffic.json")
     if not os.path.exists(path):
         return None
@@ -85,7 +88,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="r0.1", choices=sorted(WORKLOADS))
-    ap.add_argument("--frames", type=int, default=None)
+    ap.add_argument("--frames", type=int, default=None, help="frames (single-code workloads)")
+    ap.add_argument("--snr", type=float, default=None, help="override the workload SNR")
+    ap.add_argument("--frame-seed", type=int, default=0)
+    ap.add_argument("--autotune", action="store_true", help="run qm_autotune before timing")
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--fp16", action="store_true", help="store messages as binary16")
     ap.add_argument("--tuning", default=None, help="JSON dict of qm_tuning fields")
@@ -107,19 +113,25 @@ def main():
     from paper_2004_09084_amd import qcmet as Q
     from paper_2004_09084_amd import workload as W
 
-    spec_name, F, iters = WORKLOADS[args.workload]
-    F = args.frames or F
+    parts, iters = WORKLOADS[args.workload]
+    if args.frames and len(parts) == 1:
+        parts = [(parts[0][0], args.frames)]
     iters = args.iters if args.iters is not None else iters
-    spec = W.SPECS[spec_name]
+    specs = [W.SPECS[p[0]] for p in parts]
+    Fs = [p[1] for p in parts]
+    F = sum(Fs)
     torch.cuda.set_device(0)
 
-    print(f"[bench] generating {F} frames of {spec.name} (n={spec.n}) at SNR {spec.snr}", file=sys.stderr, flush=True)
-    wl = W.build(spec, F, graph_seed=0, frame_seed=0)
-    llr = torch.from_numpy(wl.llr.reshape(-1)).cuda()
-    syn = torch.from_numpy(wl.s.reshape(-1)).cuda()
-    code = Q.Code(wl.shifts, spec.Z)
+    wls = []
+    for spec, Fc in zip(specs, Fs):
+        snr = spec.snr if args.snr is None else args.snr
+        print(f"[bench] generating {Fc} frames of {spec.name} (n={spec.n}) at SNR {snr}", file=sys.stderr, flush=True)
+        wls.append(W.build(spec, Fc, graph_seed=0, frame_seed=args.frame_seed, snr=snr))
+    llr = torch.from_numpy(np.concatenate([w.llr.reshape(-1) for w in wls])).cuda()
+    syn = torch.from_numpy(np.concatenate([w.s.reshape(-1) for w in wls])).cuda()
+    codes = [Q.Code(w.shifts, spec.Z) for w, spec in zip(wls, specs)]
     tuning = json.loads(args.tuning) if args.tuning else None
-    dec = Q.Decoder([code], [F], flags=Q.QM_MSG_FP16 if args.fp16 else 0, tuning=tuning)
+    dec = Q.Decoder(codes, Fs, flags=Q.QM_MSG_FP16 if args.fp16 else 0, tuning=tuning)
     out = dec.alloc_outputs(want_app=True)
     torch.cuda.synchronize()
 
@@ -132,6 +144,10 @@ def main():
         torch.mul(src, 2.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
+
+    if args.autotune:
+        print("[bench] autotuning", file=sys.stderr, flush=True)
+        dec.autotune(llr, syn, iters, out=out)
 
     for _ in range(args.warmup):
         dec.decode(llr, syn, iters, out=out)
@@ -150,10 +166,21 @@ def main():
     dec.set_profiling(False)
 
     ms_per_step = dt * 1e3 / args.steps
-    mbit_s = F * spec.n / 1e6 / (dt / args.steps)
-    hard = out[0].cpu().numpy().reshape(F, -1)
+    bits = sum(Fc * spec.n for Fc, spec in zip(Fs, specs))
+    mbit_s = bits / 1e6 / (dt / args.steps)
+    hard_all = out[0].cpu().numpy()
     flags = out[2].cpu().numpy()
-    fer = float((hard != wl.x).any(axis=1).mean())
+    per_code = []
+    frame_err = []
+    on = of = 0
+    for w, spec, Fc in zip(wls, specs, Fs):
+        err = (hard_all[on:on + Fc * spec.n].reshape(Fc, -1) != w.x).any(axis=1)
+        frame_err.append(err)
+        per_code.append({"code": spec.name, "frames": Fc, "snr": w.meta["snr"], "fer": float(err.mean()),
+                         "syndrome_fail_rate": float(1.0 - flags[of:of + Fc].mean())})
+        on += Fc * spec.n
+        of += Fc
+    fer = float(np.concatenate(frame_err).mean())
     syn_fail = float(1.0 - flags.mean())
 
     roofline = None
@@ -166,13 +193,12 @@ def main():
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "kernel": "k_layer_sp", "avg_launch_us": round(avg_ms * 1e3, 3),
                     "algorithmic_bytes_per_launch": round(bytes_per_launch),
-                    "launches_timed": prof["launches"],
-                    "sweep_ms": round(prof["sweep_ms"] / max(prof["sweeps"], 1), 4)}
+                    "launches_timed": prof["launches"], "timing": "HIP events around whole sweeps on the decode stream"}
 
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(spec, wl.shifts, wl.llr, wl.s, iters)
+        cpu = cpu_baseline(specs[0], wls[0].shifts, wls[0].llr, wls[0].s, iters)
 
     tun = dec.tuning()
     line = {
@@ -180,11 +206,12 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if not args.fp16 else "f32 (binary16 messages)", "data": "synthetic",
-        "config": {"workload": f"{spec.name}: rate {spec.rate:.2f} QC-MET-LDPC, {spec.mb}x{spec.nb} base, Z={spec.Z}, "
-                               f"n={spec.n}, {F} frames, {iters} iterations, SNR {spec.snr}, layered sum-product, "
-                               f"{'FP16' if args.fp16 else 'FP32'} messages",
-                   "frames": F, "iterations": iters, "n": spec.n, "snr": spec.snr,
-                   "layers": int(code.info.G), "tuning": tun},
+        "config": {"workload": " + ".join(
+                       f"{Fc} x {spec.name} (rate {spec.rate:.2f} QC-MET-LDPC, {spec.mb}x{spec.nb} base, Z={spec.Z}, "
+                       f"n={spec.n}, SNR {w.meta['snr']})" for w, spec, Fc in zip(wls, specs, Fs))
+                   + f", {iters} iterations, layered sum-product, {'FP16' if args.fp16 else 'FP32'} messages",
+                   "frames": F, "iterations": iters, "layers": [int(c.info.G) for c in codes], "tuning": tun,
+                   "per_code": per_code},
         "fer": fer, "syndrome_fail_rate": syn_fail,
         "hbm_gbs": None if roofline is None else roofline["achieved"],
         "roofline": roofline,

@@ -51,9 +51,9 @@ enum qm_status {
 #define QM_MSG_FP32   0x0  /* check-to-variable messages stored as float32 */
 #define QM_MSG_FP16   0x1  /* messages stored as IEEE binary16 (round to nearest even);
                               all arithmetic and the APP LLRs stay float32 */
-#define QM_PERSISTENT 0x2  /* one persistent launch runs every iteration of every code */
 #define QM_VALIDATE   0x4  /* qm_decode checks inputs first (synchronises the stream) */
-#define QM_GRAPH      0x8  /* replay the launch sequence from a captured hipGraph */
+#define QM_GRAPH      0x8  /* replay the whole decode (every code, every sweep) as one captured
+                              hipGraph, re-captured when buffers or iters change */
 
 typedef struct qm_code qm_code;
 typedef struct qm_decoder qm_decoder;
@@ -76,8 +76,7 @@ typedef struct {
     int32_t block;            /* threads per workgroup of the layer kernel (64..256, mult. of 64) */
     int32_t merge;            /* 1: run each merged layer as one launch; 0: one launch per row
                                  (same row order, bit-identical results) */
-    int32_t persistent;       /* 1: persistent kernel for the whole iteration loop */
-    int32_t graph;            /* 1: replay a captured hipGraph */
+    int32_t graph;            /* 1: replay a captured hipGraph (as QM_GRAPH) */
     int32_t frames_per_lane;  /* 1 or 2 adjacent frames per GPU lane (<= frames_per_tile);
                                  0 = default (2).  4 is rejected (QM_ERR_UNSUPPORTED). */
     int32_t fuse_codes;       /* 1: with several codes (at most 4) and merge = 1, one launch runs
@@ -159,20 +158,23 @@ int qm_autotune(qm_decoder *dec, const float *llr, const uint8_t *syndrome, int3
                 uint8_t *hard, float *app, uint8_t *flags, const char *cache_path, void *stream);
 
 /* Live timing of the layer kernel (the decode's hot loop).
- * qm_decoder_set_profiling(dec, 1): every later qm_decode records a pair of
- * HIP events on its stream around each layer launch of one sweep (the middle
- * one, never the last), and a pair around that whole sweep.  Graph replay is
- * bypassed while profiling.  qm_decoder_get_profile waits for the recorded
- * events, sums them into *out and, if reset, forgets them.
+ * qm_decoder_set_profiling(dec, 1): every later qm_decode records one pair of
+ * HIP events on its stream around each of up to 4 sweeps from the middle of
+ * the decode (never the last sweep; with fused codes, around one sweep's
+ * worth of fused launches).  No event sits between two layer launches, so
+ * layer_ms / launches is the average launch duration including the launch
+ * gaps.  Graph replay is bypassed while profiling.  qm_decoder_get_profile
+ * waits for the recorded events, sums them into *out and, if reset, forgets
+ * them.
  * layer_bytes counts the algorithmic HBM bytes of the timed launches: per
  * check and frame 4 (its degree-1 term) plus, per degree>=2 edge, the message
  * read and written (2 x 4 bytes, or 2 x 2 with QM_MSG_FP16) and the APP read
  * and written (2 x 4 bytes). */
 typedef struct {
-    int32_t launches;     /* layer launches timed */
-    int32_t sweeps;       /* sweeps timed */
-    double layer_ms;      /* summed duration of the timed layer launches */
-    double sweep_ms;      /* summed duration of the timed sweeps */
+    int32_t launches;     /* layer launches inside the timed windows */
+    int32_t sweeps;       /* timed windows */
+    double layer_ms;      /* summed duration of the timed windows */
+    double sweep_ms;      /* unused (0) */
     double layer_bytes;   /* algorithmic bytes of the timed layer launches */
     double checks;        /* check-frame updates in the timed launches */
 } qm_profile;

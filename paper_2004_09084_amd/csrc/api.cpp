@@ -154,7 +154,7 @@ struct qm_decoder {
     int32_t profiling = 0;
     std::vector<hipEvent_t> ev_pool;     // created lazily, reused after a reset
     size_t ev_used = 0;
-    struct Pending { size_t a, b; double bytes, checks; int kind; };  // kind 0: layer, 1: sweep
+    struct Pending { size_t a, b; double bytes, checks; int launches; };  // one timed window of layer launches
     std::vector<Pending> pending;
     // learned-decoder (min-sum) workspace
     char *nws = nullptr;
@@ -286,14 +286,14 @@ struct ProfScope {
         QM_HIP(hipEventRecord(e, st));
         return QM_OK;
     }
-    int end(double bytes, double checks, int kind) {
+    int end(double bytes, double checks, int launches) {
         if (!on) return QM_OK;
         hipEvent_t e;
         size_t i1;
         int rc = take_event(d, &e, &i1);
         if (rc != QM_OK) return rc;
         QM_HIP(hipEventRecord(e, st));
-        d.pending.push_back(qm_decoder::Pending{i0, i1, bytes, checks, kind});
+        d.pending.push_back(qm_decoder::Pending{i0, i1, bytes, checks, launches});
         return QM_OK;
     }
 };
@@ -338,30 +338,33 @@ int enqueue_sweeps_slot(qm_decoder &d, Slot &s, int32_t iters, hipStream_t st) {
     const RowDesc *rows = slot_bufs(d, s).rows;
     LayerArgs la = layer_args(d, s);
     const int G = (int)s.gptr.size() - 1;
-    // the profiled sweep: the middle one, never the last (which also forms
-    // the degree-1 APPs)
-    const int tprof = (d.profiling && iters >= 2) ? (iters - 1) / 2 : -1;
+    // profiled: up to 4 sweeps from the middle of the decode, never the last
+    // (which also forms the degree-1 APPs); one event pair per sweep, so no
+    // event sits between two layer launches
+    const int t0p = (iters - 1) / 2, t1p = d.profiling ? std::min(t0p + 4, iters - 1) : -1;
     for (int t = 0; t < iters; ++t) {
         la.last = (t == iters - 1) ? 1 : 0;
-        const bool prof = (t == tprof);
+        const bool prof = t >= t0p && t < t1p;
         ProfScope sweep(d, st, prof);
         int rc = sweep.begin();
         if (rc != QM_OK) return rc;
+        double bytes = 0.0, checks = 0.0;
+        int launches = 0;
         for (int gi = 0; gi < G; ++gi) {
             const int p_lo = s.gptr[gi], p_hi = s.gptr[gi + 1];
             const int step = d.tun.merge ? (p_hi - p_lo) : 1;
             for (int p = p_lo; p < p_hi; p += step) {
                 la.rows = rows + p;
                 la.nrows = step;
-                ProfScope one(d, st, prof);
-                if ((rc = one.begin()) != QM_OK) return rc;
                 QM_HIP(qm_launch_layer(la, msg16, s.maxd_t, la.fpl, d.tun.block, d.tun.stream_hint, st));
-                double bytes, checks;
-                layer_work(s, s.hrows.data() + p, step, msg16, &bytes, &checks);
-                if ((rc = one.end(bytes, checks, 0)) != QM_OK) return rc;
+                double b, ch;
+                layer_work(s, s.hrows.data() + p, step, msg16, &b, &ch);
+                bytes += b;
+                checks += ch;
+                ++launches;
             }
         }
-        if ((rc = sweep.end(0.0, 0.0, 1)) != QM_OK) return rc;
+        if ((rc = sweep.end(bytes, checks, launches)) != QM_OK) return rc;
     }
     return QM_OK;
 }
@@ -397,7 +400,14 @@ int enqueue_sweeps_fused(qm_decoder &d, int32_t iters, hipStream_t st) {
     int gmax = 1;
     for (int c = 0; c < nc; ++c) gmax = std::max(gmax, G[c]);
     const int64_t kprof = (d.profiling && steps >= 2 * gmax) ? (steps / 2 / gmax) * gmax - gmax : -1;
+    ProfScope window(d, st, kprof >= 0);
+    double wbytes = 0.0, wchecks = 0.0;
     for (int64_t k = 0; k < steps; ++k) {
+        const bool in_window = kprof >= 0 && k >= kprof && k < kprof + gmax;
+        if (k == kprof) {
+            const int rc = window.begin();
+            if (rc != QM_OK) return rc;
+        }
         MultiLayerArgs m;
         std::memset(&m, 0, sizeof(m));
         m.ncodes = nc;
@@ -423,11 +433,15 @@ int enqueue_sweeps_fused(qm_decoder &d, int32_t iters, hipStream_t st) {
             m.code[c] = la;
         }
         m.block_off[nc] = off;
-        ProfScope one(d, st, kprof >= 0 && k >= kprof && k < kprof + gmax);
-        int rc = one.begin();
-        if (rc != QM_OK) return rc;
         QM_HIP(qm_launch_layer_multi(m, msg16, maxd, fpl, d.tun.block, d.tun.stream_hint, st));
-        if ((rc = one.end(bytes, checks, 0)) != QM_OK) return rc;
+        if (in_window) {
+            wbytes += bytes;
+            wchecks += checks;
+        }
+        if (kprof >= 0 && k == kprof + gmax - 1) {
+            const int rc = window.end(wbytes, wchecks, gmax);
+            if (rc != QM_OK) return rc;
+        }
     }
     return QM_OK;
 }
@@ -657,7 +671,7 @@ int qm_decoder_create(const qm_code *const *codes, int32_t ncodes, const int32_t
     if (!out) return fail(QM_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (!codes || !frames_per_code || ncodes <= 0) return fail(QM_ERR_INVALID_ARG, "need at least one code");
-    if (flags & ~(QM_MSG_FP16 | QM_PERSISTENT | QM_VALIDATE | QM_GRAPH))
+    if (flags & ~(QM_MSG_FP16 | QM_VALIDATE | QM_GRAPH))
         return fail(QM_ERR_INVALID_ARG, "unknown flag bits");
     qm_decoder *d = new (std::nothrow) qm_decoder;
     if (!d) return fail(QM_ERR_OOM, "out of host memory");
@@ -697,7 +711,6 @@ int qm_decoder_create(const qm_code *const *codes, int32_t ncodes, const int32_t
     d->tun.frames_per_tile = 16;
     d->tun.block = 128;
     d->tun.merge = 1;
-    d->tun.persistent = (flags & QM_PERSISTENT) ? 1 : 0;
     d->tun.graph = (flags & QM_GRAPH) ? 1 : 0;
     d->tun.frames_per_lane = 2;
     d->tun.fuse_codes = 1;
@@ -741,7 +754,6 @@ int qm_decoder_set_tuning(qm_decoder *d, const qm_tuning *t) {
     if (n.block == 0) n.block = 128;
     if (n.block < 64 || n.block > 256 || n.block % 64)
         return fail(QM_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 256]");
-    if (n.persistent) return fail(QM_ERR_UNSUPPORTED, "persistent launch not available");
     if (n.frames_per_lane == 0) n.frames_per_lane = 2;
     if (n.frames_per_lane == 4)
         return fail(QM_ERR_UNSUPPORTED, "frames_per_lane 4 (128-bit buffer accesses) is switched off: it gave "
@@ -824,15 +836,11 @@ int qm_decoder_get_profile(qm_decoder *d, qm_profile *out, int32_t reset) {
         QM_HIP(hipEventSynchronize(d->ev_pool[p.b]));
         float ms = 0.0f;
         QM_HIP(hipEventElapsedTime(&ms, d->ev_pool[p.a], d->ev_pool[p.b]));
-        if (p.kind == 0) {
-            out->launches++;
-            out->layer_ms += ms;
-            out->layer_bytes += p.bytes;
-            out->checks += p.checks;
-        } else {
-            out->sweeps++;
-            out->sweep_ms += ms;
-        }
+        out->launches += p.launches;
+        out->sweeps++;
+        out->layer_ms += ms;
+        out->layer_bytes += p.bytes;
+        out->checks += p.checks;
     }
     if (reset) {
         d->pending.clear();
@@ -1049,7 +1057,6 @@ int qm_autotune(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t ite
                 t.merge = 1;
                 t.fuse_codes = 1;
                 t.graph = 0;
-                t.persistent = 0;
                 float ms = 0.0f;
                 rc = trial(t, &ms);
                 if (rc == QM_OK && ms < best_ms) {

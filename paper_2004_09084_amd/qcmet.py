@@ -29,7 +29,6 @@ QM_ERR_STATE = -9
 
 QM_MSG_FP32 = 0x0
 QM_MSG_FP16 = 0x1
-QM_PERSISTENT = 0x2
 QM_VALIDATE = 0x4
 QM_GRAPH = 0x8
 
@@ -60,7 +59,7 @@ class qm_code_info(ctypes.Structure):
 
 class qm_tuning(ctypes.Structure):
     _fields_ = [("frames_per_tile", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("merge", ctypes.c_int32), ("persistent", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("merge", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("frames_per_lane", ctypes.c_int32), ("fuse_codes", ctypes.c_int32),
                 ("stream_hint", ctypes.c_int32)]
 
@@ -204,9 +203,9 @@ def qm_decoder_bind_workspace(dec, ws) -> None:
     _check(lib().qm_decoder_bind_workspace(dec, _dptr(ws), ws.numel() * ws.element_size()))
 
 
-def qm_decoder_set_tuning(dec, frames_per_tile=0, block=0, merge=1, persistent=0, graph=0,
-                          frames_per_lane=0, fuse_codes=1, stream_hint=1) -> None:
-    t = qm_tuning(frames_per_tile, block, merge, persistent, graph, frames_per_lane, fuse_codes, stream_hint)
+def qm_decoder_set_tuning(dec, frames_per_tile=0, block=0, merge=1, graph=0, frames_per_lane=0, fuse_codes=1,
+                          stream_hint=1) -> None:
+    t = qm_tuning(frames_per_tile, block, merge, graph, frames_per_lane, fuse_codes, stream_hint)
     _check(lib().qm_decoder_set_tuning(dec, ctypes.byref(t)))
 
 

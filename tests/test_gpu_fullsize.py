@@ -1,0 +1,84 @@
+"""Parity at the full workload sizes (n = 10^6, 128 frames) in the launch
+configuration bench.py times (default tuning).  The GPU decodes the whole
+batch; sampled frames are compared with the FP64 oracle, which decodes them
+alone (frames are independent): live for the first sweeps, and against
+oracle results stored by tests/golden/make_fullsize_golden.py for full
+decodes."""
+import hashlib
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2004_09084_amd import qcmet as Q
+from paper_2004_09084_amd import workload as W
+from tests.gpu_util import APP_TOL, compare, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "fullsize_oracle.npz")
+SPECS = {"r0.1": W.RATE01, "r0.05": W.RATE005, "r0.02": W.RATE002}
+F = 128
+
+
+def _decode(spec, snr, T):
+    import torch
+    wl = W.build(spec, F, graph_seed=0, frame_seed=0, snr=snr)
+    code = Q.Code(wl.shifts, spec.Z)
+    dec = Q.Decoder([code], [F])
+    hard, app, fl = dec.decode(to_dev(wl.llr), to_dev(wl.s), T)
+    torch.cuda.synchronize()
+    out = hard.cpu().numpy().reshape(F, -1), app.cpu().numpy().reshape(F, -1), fl.cpu().numpy()
+    del dec
+    torch.cuda.empty_cache()
+    return wl, out
+
+
+@pytest.mark.parametrize("name", sorted(SPECS))
+def test_fullsize_first_sweeps(name):
+    spec = SPECS[name]
+    frames = [0, 77]
+    for T in (1, 2):
+        say(f"full size {name} T={T}")
+        wl, (hard, app, fl) = _decode(spec, None, T)
+        appo, hardo, flo, _ = oracle.decode_sp(wl.shifts, spec.Z, wl.llr[frames], wl.s[frames], T, threads=2)
+        rows = compare(app[frames], hard[frames], fl[frames], appo, hardo, flo)
+        say(rows)
+        for r in rows:
+            assert r["app_viol"] == 0 and r["bits_diff_confident"] == 0 and r["flag_o"] == r["flag_g"], r
+
+
+def _golden_cases():
+    if not os.path.exists(GOLD):
+        return []
+    g = np.load(GOLD)
+    return sorted({k.split("/")[0] for k in g.files})
+
+
+@pytest.mark.parametrize("case", _golden_cases())
+def test_fullsize_against_stored_oracle(case):
+    g = np.load(GOLD)
+    snr, T, Z = g[f"{case}/meta"][:3]
+    frames = [int(f) for f in g[f"{case}/meta"][3:]]
+    spec = SPECS[case.split("_")[0]]
+    assert int(Z) == spec.Z
+    say(f"{case}: SNR {snr} T {int(T)} frames {frames}")
+    wl, (hard, app, fl) = _decode(spec, float(snr), int(T))
+    for f in frames:
+        p = f"{case}/f{f}/"
+        flag_o = int(g[p + "flag"])
+        pos = g[p + "pos"]
+        same_hash = hashlib.sha256(hard[f].tobytes()).digest() == g[p + "hard_sha256"].tobytes()
+        o = g[p + "app_at"]
+        a = app[f][pos].astype(np.float64)
+        viol = int((np.abs(a - o) > APP_TOL * np.maximum(np.abs(o), 1.0)).sum())
+        bits_at = int((hard[f][pos] != g[p + "hard_at"]).sum())
+        errors_g = int((hard[f] != wl.x[f]).sum())
+        say(dict(frame=f, flag_o=flag_o, flag_g=int(fl[f]), errors_o=int(g[p + "errors"]), errors_g=errors_g,
+                 hard_identical=same_hash, sampled_bits_diff=bits_at, sampled_app_viol=viol))
+        # T1: per-frame flags identical
+        assert int(fl[f]) == flag_o
+        # T2: frames the oracle decodes to a valid word are bit-identical
+        if flag_o:
+            assert same_hash and viol == 0

@@ -44,6 +44,8 @@ def _load(path: str):
     L.qo_check_schedule.argtypes = [i32, i32, p, i32, p, p]
     L.qo_decode_sp.restype = i32
     L.qo_decode_sp.argtypes = [i32, i32, i32, p, i32, p, p, i32, p, p, i32, i32, p, p, p, i32]
+    L.qo_decode_sp_early.restype = i32
+    L.qo_decode_sp_early.argtypes = [i32, i32, i32, p, i32, p, p, i32, p, p, i32, i32, p, p, p, p, i32]
     L.qo_nms_decode.restype = i32
     L.qo_nms_decode.argtypes = [i32, i32, i32, p, i32, p, p, i32, p, p, i32, p, p, i32,
                                 p, p, p, p, i32]
@@ -161,6 +163,24 @@ def decode_sp(shifts, Z, llr, syn, T, schedule=None, fp16_messages=False, thread
     if rc <= 0:
         raise RuntimeError(f"qo_decode_sp failed: {rc}")
     return app, hard, flags, rc
+
+
+def decode_sp_early(shifts, Z, llr, syn, T, schedule=None, fp16_messages=False, threads=0):
+    """Layered sum-product with early termination: each frame stops at the
+    first sweep count in [0, T] whose hard decisions satisfy the syndrome.
+    Returns (app, hard, flags, iters_used)."""
+    sh, mb, nb, n, m, L, S, gp, rw = _prep(shifts, Z, llr, syn, schedule)
+    F = L.shape[0]
+    app = np.empty((F, n), dtype=np.float64)
+    hard = np.empty((F, n), dtype=np.uint8)
+    flags = np.empty(F, dtype=np.uint8)
+    iters = np.empty(F, dtype=np.int32)
+    rc = lib().qo_decode_sp_early(mb, nb, Z, _ptr(sh), len(gp) - 1, _ptr(gp), _ptr(rw), F, _ptr(L), _ptr(S),
+                                  int(T), 1 if fp16_messages else 0, _ptr(app), _ptr(hard), _ptr(flags),
+                                  _ptr(iters), int(threads))
+    if rc <= 0:
+        raise RuntimeError(f"qo_decode_sp_early failed: {rc}")
+    return app, hard, flags, iters
 
 
 def nms_decode(shifts, Z, llr, syn, T, alpha, beta, early_stop=False, schedule=None, threads=0):

@@ -30,11 +30,17 @@
  *                     variables included: the oracle does not defer them.
  *                     msg_mode 1 rounds every new r to IEEE binary16
  *                     (round to nearest even) and keeps all else in FP64.
+ *   qo_decode_sp_early The same with early termination (Results, Table
+ *                     tabearly): a frame stops at the first sweep count
+ *                     whose hard decisions satisfy the syndrome.
  *   qo_nms_*          Normalised/offset min-sum variant of the same layered
  *                     sweep (a learned decoder that is not in the paper):
- *                     r = sign * alpha[t][row][type] * max(min|q| - beta, 0);
- *                     analytic reverse-mode gradients of the mean
- *                     binary cross-entropy of the final APP.
+ *                     r = sign * alpha[t][row][type] * max(min(min|q|, 30) - beta, 0);
+ *                     the minimum saturates at the sum-product clip level
+ *                     (Results, kernel optimisations: clipping keeps the
+ *                     iterated values finite); analytic reverse-mode
+ *                     gradients of the mean binary cross-entropy of the
+ *                     final APP (no gradient through an active clip).
  *
  * Parity pins (tests): brute-force bitwise MAP on cycle-free lifts, brute-
  * force ML on tiny loopy codes, single-check closed form (tanh rule),
@@ -245,8 +251,9 @@ typedef struct {
     const code_t *c;
     int G; const int *gptr, *rows;
     const float *llr; const uint8_t *syn;
-    int T, mode;
+    int T, mode, early_stop;
     double *app; uint8_t *hard, *flags;
+    int32_t *iters;
     int err;
 } sp_ctx;
 
@@ -266,7 +273,14 @@ static void sp_frame(void *vctx, int f) {
     /* step 1: APP starts at the channel LLR 2R/sigma^2 (given); r = 0 */
     for (int v = 0; v < n; v++) app[v] = (double)llr[v];
 
+    /* early termination (Results, Table tabearly): before every sweep the
+     * hard decisions of the current APPs are tested against the syndrome and
+     * the frame stops at the first sweep count where H c = s holds */
+    uint8_t *hard = x->hard + (size_t)f * n;
+    int used = 0;
     for (int t = 0; t < x->T; t++) {
+        if (x->early_stop && hard_and_check(c, app, s, hard)) break;
+        used = t + 1;
         for (int g = 0; g < x->G; g++) {
             for (int p = x->gptr[g]; p < x->gptr[g + 1]; p++) {
                 int i = x->rows[p];
@@ -302,7 +316,8 @@ static void sp_frame(void *vctx, int f) {
             }
         }
     }
-    x->flags[f] = (uint8_t)hard_and_check(c, app, s, x->hard + (size_t)f * n);
+    x->flags[f] = (uint8_t)hard_and_check(c, app, s, hard);
+    if (x->iters) x->iters[f] = used;
     free(r); free(q); free(ph); free(rn);
 }
 
@@ -321,7 +336,25 @@ int qo_decode_sp(int mb, int nb, int Z, const int *sh, int G, const int *gptr, c
     code_t c;
     int rc = code_build(&c, mb, nb, Z, sh);
     if (rc) { code_free(&c); return rc; }
-    sp_ctx x = {&c, G, gptr, rows, llr, syn, T, mode, app, hard, flags, 0};
+    sp_ctx x = {&c, G, gptr, rows, llr, syn, T, mode, 0, app, hard, flags, NULL, 0};
+    int used = F > 0 ? run_frames(sp_frame, &x, F, nthreads) : 0;
+    code_free(&c);
+    return x.err ? x.err : (used > 0 ? used : 1);
+}
+
+/* The same decode with early termination: a frame stops after the first
+ * sweep count t in [0, T] at which its hard decisions satisfy H c = s
+ * (tested before every sweep and after the last); iters[f] = the sweeps it
+ * ran.  A frame that stops at t has exactly the outputs of a T = t decode. */
+int qo_decode_sp_early(int mb, int nb, int Z, const int *sh, int G, const int *gptr, const int *rows,
+                       int F, const float *llr, const uint8_t *syn, int T, int mode,
+                       double *app, uint8_t *hard, uint8_t *flags, int32_t *iters, int nthreads) {
+    if (mb <= 0 || nb <= 0 || Z <= 0 || F < 0 || T < 0 || (mode != 0 && mode != 1)) return -1;
+    if (qo_check_schedule(mb, nb, sh, G, gptr, rows) != 0) return -3;
+    code_t c;
+    int rc = code_build(&c, mb, nb, Z, sh);
+    if (rc) { code_free(&c); return rc; }
+    sp_ctx x = {&c, G, gptr, rows, llr, syn, T, mode, 1, app, hard, flags, iters, 0};
     int used = F > 0 ? run_frames(sp_frame, &x, F, nthreads) : 0;
     code_free(&c);
     return x.err ? x.err : (used > 0 ? used : 1);
@@ -331,7 +364,8 @@ int qo_decode_sp(int mb, int nb, int Z, const int *sh, int G, const int *gptr, c
 
 /* Weights: alpha, beta double [T][mb][2]; index 0 = target edge in a column
  * of degree >= 2 ("type-1"), 1 = target edge in a degree-1 column.  A check
- * with a single edge sees an empty minimum, read as X_HI. */
+ * with a single edge sees an empty minimum, read as X_HI; every minimum
+ * saturates at X_HI. */
 
 typedef struct {
     const code_t *c;
@@ -355,7 +389,8 @@ static double dabs(double v) { return v > 0.0 ? 1.0 : (v < 0.0 ? -1.0 : 0.0); }
 static double softplus(double u) { return (u > 0 ? u : 0.0) + log1p(exp(-fabs(u))); }
 static double sigmoid(double u) { return u >= 0 ? 1.0 / (1.0 + exp(-u)) : exp(u) / (1.0 + exp(u)); }
 
-/* exclusive minimum for edge a: value and the lowest index attaining it */
+/* exclusive minimum for edge a, saturated at X_HI: value and the lowest
+ * index attaining it (-1 if the set is empty or the saturation is active) */
 static double excl_min(const double *q, int d, int a, int *arg) {
     double mu = QO_X_HI;
     int best = -1;
@@ -363,6 +398,10 @@ static double excl_min(const double *q, int d, int a, int *arg) {
         if (b == a) continue;
         double v = fabs(q[b]);
         if (best < 0 || v < mu) { mu = v; best = b; }
+    }
+    if (mu > QO_X_HI) {
+        mu = QO_X_HI;
+        best = -1;
     }
     *arg = best;
     return mu;

@@ -8,7 +8,9 @@
 //   mu_e = min_{e' != e} |q_e'|           (ties: the lowest column wins)
 //   r_e  = (-1)^{s ^ xor_{e'!=e}[q_e' < 0]} * alpha[t][i][tau_e] * max(mu_e - beta[t][i][tau_e], 0)
 // tau_e = 0 for an edge in a column of degree >= 2, 1 for the degree-1 edge.
-// A check with a single edge sees an empty minimum, read as 30.
+// The minimum saturates at 30, the sum-product clip level (iterated min-sum
+// messages otherwise grow without bound and overflow); a check with a single
+// edge sees an empty minimum, read as 30.
 // The degree-1 edge's q is its channel LLR at every visit (its variable has
 // this check only), so |LLR_d| and s ^ [LLR_d < 0] sit in K; its own message
 // only reaches the output APP_d = LLR_d + r_d, formed when requested.
@@ -44,10 +46,17 @@ struct Min2 {
             p2 = p;
         }
     }
-    // exclusive minimum for the edge at position p (30 if it is the only edge)
+    // exclusive minimum for the edge at position p, saturated at 30 (also
+    // when p is the only edge)
     __device__ __forceinline__ float excl(int p) const {
         const float mu = (p == p1) ? m2 : m1;
-        return mu == kInf ? QM_X_HI : mu;
+        return fminf(mu, QM_X_HI);
+    }
+    // the position that attains the exclusive minimum for p, or -1 if the
+    // set is empty or the saturation is active (no gradient flows then)
+    __device__ __forceinline__ int excl_arg(int p) const {
+        const float mu = (p == p1) ? m2 : m1;
+        return mu > QM_X_HI ? -1 : ((p == p1) ? p2 : p1);
     }
 };
 
@@ -408,17 +417,15 @@ __device__ __forceinline__ void check_nms_bwd(const LaneCtx &c, ConstRowDesc *rd
 #pragma unroll
         for (int f = 0; f < FPL; ++f) {
             const float sg = (neg[f] != (q[j][f] < 0.0f)) ? -1.0f : 1.0f;
-            const bool at_p1 = pos[j] == mn[f].p1;
-            const float mu = mn[f].excl(pos[j]);
-            const float z = mu - b1;
+            const int arg = mn[f].excl_arg(pos[j]);
+            const float z = mn[f].excl(pos[j]) - b1;
             acc[0] += gr[j][f] * sg * fmaxf(z, 0.0f);
             if (z > 0.0f) {
                 const float gz = gr[j][f] * sg * a1;
                 acc[1] -= gz;
-                if (at_p1) {
-                    if (mn[f].p2 >= 0) G2[f] += gz;
-                } else {
-                    G1[f] += gz;
+                if (arg >= 0) {
+                    if (arg == mn[f].p1) G1[f] += gz;
+                    else G2[f] += gz;
                 }
             }
         }
@@ -432,17 +439,15 @@ __device__ __forceinline__ void check_nms_bwd(const LaneCtx &c, ConstRowDesc *rd
 #pragma unroll
         for (int f = 0; f < FPL; ++f) {
             const float sg = (neg[f] != (lam[f] < 0.0f)) ? -1.0f : 1.0f;
-            const bool at_p1 = d1pos == mn[f].p1;
-            const float mu = mn[f].excl(d1pos);
-            const float z = mu - b2;
+            const int arg = mn[f].excl_arg(d1pos);
+            const float z = mn[f].excl(d1pos) - b2;
             acc[2] += gd[f] * sg * fmaxf(z, 0.0f);
             if (z > 0.0f) {
                 const float gz = gd[f] * sg * a2;
                 acc[3] -= gz;
-                if (at_p1) {
-                    if (mn[f].p2 >= 0) G2[f] += gz;
-                } else {
-                    G1[f] += gz;
+                if (arg >= 0) {
+                    if (arg == mn[f].p1) G1[f] += gz;
+                    else G2[f] += gz;
                 }
             }
         }

@@ -82,8 +82,12 @@ def evaluate(spec, shifts, weights, T_nms=100, T_sp=200, frames=128, frame_seed=
     S = torch.from_numpy(wl.s.reshape(-1)).cuda()
     code = Q.Code(shifts, spec.Z)
 
+    def bit_errors(hard):
+        h = hard.cpu().numpy().reshape(frames, -1) if hasattr(hard, "cpu") else hard
+        return (h != wl.x)
+
     def frame_errors(hard):
-        return (hard.cpu().numpy().reshape(frames, -1) != wl.x).any(axis=1)
+        return bit_errors(hard).any(axis=1)
 
     # plain sum-product (the fallback decoder and the reference)
     sp = Q.Decoder([code], [frames])
@@ -93,10 +97,11 @@ def evaluate(spec, shifts, weights, T_nms=100, T_sp=200, frames=128, frame_seed=
     hs, _, fs = sp.decode(L, S, T_sp)
     torch.cuda.synchronize()
     t_sp = time.perf_counter() - t0
-    err_sp = frame_errors(hs)
+    be_sp = bit_errors(hs)
+    err_sp = be_sp.any(axis=1)
 
     res = {"snr": wl.meta["snr"], "frames": frames,
-           "sum_product": {"fer": float(err_sp.mean()), "syndrome_fail": float(1 - fs.cpu().numpy().mean()),
+           "sum_product": {"fer": float(err_sp.mean()), "ber": float(be_sp.mean()), "syndrome_fail": float(1 - fs.cpu().numpy().mean()),
                            "iterations": T_sp, "mbit_s": frames * spec.n / 1e6 / t_sp}}
     nm = Q.Decoder([code], [frames])
     nm.nms_bind(T_nms, train=False)
@@ -124,9 +129,12 @@ def evaluate(spec, shifts, weights, T_nms=100, T_sp=200, frames=128, frame_seed=
             torch.cuda.synchronize()
             t_fb = time.perf_counter() - t0
             hard[idx] = hf.cpu().numpy().reshape(nfail, -1)
-        err = (hard != wl.x).any(axis=1)
+        be = bit_errors(hard)
+        err = be.any(axis=1)
         res[name] = {"fer_minsum_only": float(frame_errors(hn).mean()),
+                     "syndrome_fail_minsum_only": float(1 - ok.mean()),
                      "converged": int(ok.sum()),
+                     "ber_with_fallback": float(be.mean()),
                      "mean_iterations": float(it.cpu().numpy().mean()),
                      "fer_with_fallback": float(err.mean()),
                      "fallback_frames": nfail,

@@ -26,6 +26,10 @@ MUTANTS = {
     "backward_rold_sign": ("gR[e0 + a] = -gq[a];", "gR[e0 + a] = gq[a];"),
     "backward_beta_sign": ("gb[w] -= gz;", "gb[w] += gz;"),
     "backward_argmin_sign": ("gq[arg] += gz * dabs(q[arg]);", "gq[arg] += gz;"),
+    "minsum_unsaturated": ("if (mu > QO_X_HI) {\n        mu = QO_X_HI;", "if (mu > 1e300) {\n        mu = QO_X_HI;"),
+    "gradient_through_saturation": ("mu = QO_X_HI;\n        best = -1;", "mu = QO_X_HI;"),
+    "early_stop_counts_late": ("used = t + 1;\n        for (int g = 0; g < x->G; g++) {", "used = t + 2;\n        for (int g = 0; g < x->G; g++) {"),
+    "early_stop_one_sweep_late": ("if (x->early_stop && hard_and_check(c, app, s, hard)) break;", "if (x->early_stop && t > 0 && hard_and_check(c, app, s, hard)) break;"),
     "loss_sign": ("gA[v] = -sg * sigmoid(-sg * app[v]);", "gA[v] = sg * sigmoid(-sg * app[v]);"),
 }
 

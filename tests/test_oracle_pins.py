@@ -260,17 +260,33 @@ def test_frames_are_independent():
 # ------------------------------------------------------- min-sum NMS --
 
 def test_nms_beta0_is_scale_invariant():
-    # with beta = 0 the min-sum update is positively homogeneous: scaling the
-    # LLRs by 2 scales every APP by exactly 2
+    # with beta = 0 and no minimum reaching the saturation level, the min-sum
+    # update is positively homogeneous: halving the LLRs halves every APP
+    # exactly (|LLR| <= 0.4 keeps every |q| of one sweep below 0.4 * 30)
     H = W.make_code(W.RATE01_SMALL, 0)
     Z = W.RATE01_SMALL.Z
     X, L, S = W.make_frames(H, Z, 0.3, 2, seed=8)
-    T = 5
+    L = np.clip(L, -0.4, 0.4).astype(np.float32)
+    T = 1
     rng = np.random.default_rng(9)
     alpha = rng.uniform(0.5, 1.0, (T, H.shape[0], 2))
-    a1, _, _, _ = oracle.nms_decode(H, Z, L, S, T, alpha, 0.0)
-    a2, _, _, _ = oracle.nms_decode(H, Z, (2 * L).astype(np.float32), S, T, alpha, 0.0)
+    a1, _, _, _ = oracle.nms_decode(H, Z, (L / 2).astype(np.float32), S, T, alpha, 0.0)
+    a2, _, _, _ = oracle.nms_decode(H, Z, L, S, T, alpha, 0.0)
+    assert np.abs(a2).max() < 30
     assert np.array_equal(2 * a1, a2)
+
+
+def test_nms_minimum_saturates_at_30():
+    # a single check of degree 3 with very reliable inputs: each message is
+    # alpha * (min(others, 30) - beta) with the check's sign rule
+    H = np.zeros((1, 3), dtype=np.int32)
+    llr = np.array([[100.0, -200.0, 12.0]], dtype=np.float32)
+    alpha, beta = 0.75, 0.5
+    app, _, _, _ = oracle.nms_decode(H, 1, llr, np.array([[0]], np.uint8), 1, alpha, beta)
+    # r0 from {-200, 12}: sign -, min 12; r1 from {100, 12}: sign +, min 12;
+    # r2 from {100, -200}: sign -, min 100 -> saturated at 30
+    expect = [100 - alpha * (12 - beta), -200 + alpha * (12 - beta), 12 - alpha * (30 - beta)]
+    assert np.allclose(app[0], expect, rtol=0, atol=1e-12)
 
 
 def test_nms_early_stop_counts_iterations():
@@ -283,6 +299,40 @@ def test_nms_early_stop_counts_iterations():
     _, hard, flags, iters = oracle.nms_decode(H, Z, L, S, 30, 0.8, 0.0, early_stop=True)
     assert flags.all() and np.array_equal(hard, X)
     assert (iters >= 1).all() and (iters < 30).all()
+
+
+def test_sp_early_stop_is_the_first_valid_sweep_count():
+    # Results, Table tabearly: a frame stops once its hard decisions satisfy
+    # the syndrome.  Each frame's output must equal a fixed-T decode with
+    # T = its iteration count, and the syndrome (checked here with a dense H,
+    # not the oracle's own test) must fail at every smaller count.
+    spec = W.RATE01_SMALL
+    H = W.make_code(spec, 0)
+    Z = spec.Z
+    Hd = dense_H(H, Z)
+    X, L, S = W.make_frames(H, Z, 0.9, 6, seed=21)
+    Tmax = 25
+    app, hard, flags, iters = oracle.decode_sp_early(H, Z, L, S, Tmax)
+    assert iters.min() >= 1 and (flags == 1).sum() >= 3
+    for f in range(len(L)):
+        t_f = int(iters[f])
+        a_t, h_t, fl_t, _ = oracle.decode_sp(H, Z, L[f:f + 1], S[f:f + 1], t_f)
+        assert np.array_equal(a_t[0], app[f]) and np.array_equal(h_t[0], hard[f]) and fl_t[0] == flags[f]
+        ok = lambda h: not np.any((Hd.dot(h.astype(np.int64)) + S[f]) % 2)
+        assert flags[f] == ok(hard[f])
+        if t_f < Tmax:
+            assert flags[f] == 1
+        for t in range(t_f):
+            _, h_s, _, _ = oracle.decode_sp(H, Z, L[f:f + 1], S[f:f + 1], t)
+            assert not ok(h_s[0]), (f, t)
+
+
+def test_sp_early_stop_zero_noise_stops_at_zero():
+    H = W.make_code(W.RATE01_SMALL, 0)
+    Z = W.RATE01_SMALL.Z
+    X, L, S = W.make_frames(H, Z, 0.161, 2, seed=2, zero_noise=True)
+    _, hard, flags, iters = oracle.decode_sp_early(H, Z, L, S, 10)
+    assert np.all(iters == 0) and np.all(flags == 1) and np.array_equal(hard, X)
 
 
 def _fd_setup():
@@ -316,6 +366,27 @@ def test_nms_gradients_match_finite_differences():
             assert abs(fd - G[t, i, tau]) <= 1e-6 * max(abs(fd), 1e-4) + 1e-9, (which, t, i, tau, fd, G[t, i, tau])
             checked += 1
     assert checked == 14
+
+
+def test_nms_gradients_match_finite_differences_under_saturation():
+    # reliable inputs drive many minima past 30; the loss is flat in q there,
+    # so the exact gradient carries nothing through an active saturation
+    H, Z, X, L, S = _fd_setup()
+    L = (L * 12).astype(np.float32)
+    T, mb = 3, H.shape[0]
+    rng = np.random.default_rng(13)
+    alpha = rng.uniform(0.6, 1.0, (T, mb, 2))
+    beta = rng.uniform(0.0, 0.3, (T, mb, 2))
+    _, ga, gb, _ = oracle.nms_loss_grad(H, Z, L, S, X, T, alpha, beta)
+    h = 1e-5
+    worst = 0.0
+    for (t, i, tau) in [(0, 0, 0), (0, 4, 0), (1, 3, 0), (1, 8, 0), (2, 5, 0), (2, 7, 1), (1, 20, 0), (2, 30, 1)]:
+        Pp = alpha.copy(); Pp[t, i, tau] += h
+        Pm = alpha.copy(); Pm[t, i, tau] -= h
+        fd = (oracle.nms_loss_grad(H, Z, L, S, X, T, Pp, beta)[0]
+              - oracle.nms_loss_grad(H, Z, L, S, X, T, Pm, beta)[0]) / (2 * h)
+        worst = max(worst, abs(fd - ga[t, i, tau]) / max(abs(fd), 1e-7))
+    assert worst < 1e-4, worst
 
 
 def test_nms_degree1_weights_only_act_in_the_last_iteration():

@@ -64,10 +64,10 @@ def load_traffic(workload_key: str, fp16: bool):
     return ent.get("bytes_per_launch")
 
 
-def cpu_baseline(spec, shifts, frames_llr, frames_s, iters_full: int):
+def cpu_baseline(spec, shifts, frames_llr, frames_s, iters_full):
     """The FP64 oracle, as it stands, on a bounded sample: `threads` frames
     (one per host core, at most 16) for 2 iterations; scaled to Mbit/s at the
-    full iteration count."""
+    full iteration count (with early termination: the GPU's mean count)."""
     import oracle
     threads = min(16, os.cpu_count() or 1)
     F = min(threads, frames_llr.shape[0])
@@ -79,7 +79,7 @@ def cpu_baseline(spec, shifts, frames_llr, frames_s, iters_full: int):
     return {"value": round(F * spec.n / 1e6 / per_decode, 4), "unit": "Mbit/s", "cores": int(used),
             "kind": "oracle",
             "sample": f"{F} frames x {sample_iters} iterations of the same code and inputs "
-                      f"({dt:.1f} s wall), scaled to {iters_full} iterations"}
+                      f"({dt:.1f} s wall), scaled to {iters_full:g} iterations"}
 
 
 def main():
@@ -97,6 +97,8 @@ def main():
     ap.add_argument("--tuning", default=None, help="JSON dict of qm_tuning fields")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--early-stop", action="store_true",
+                    help="qm_decode_early: frames stop once H c = s (iterations = the maximum)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run one plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -131,8 +133,17 @@ def main():
     syn = torch.from_numpy(np.concatenate([w.s.reshape(-1) for w in wls])).cuda()
     codes = [Q.Code(w.shifts, spec.Z) for w, spec in zip(wls, specs)]
     tuning = json.loads(args.tuning) if args.tuning else None
-    dec = Q.Decoder(codes, Fs, flags=Q.QM_MSG_FP16 if args.fp16 else 0, tuning=tuning)
+    flags = (Q.QM_MSG_FP16 if args.fp16 else 0) | (Q.QM_EARLY_STOP if args.early_stop else 0)
+    dec = Q.Decoder(codes, Fs, flags=flags, tuning=tuning)
     out = dec.alloc_outputs(want_app=True)
+    iters_used = None
+
+    def step():
+        nonlocal iters_used
+        if args.early_stop:
+            iters_used = dec.decode_early(llr, syn, iters, out=out)[3]
+        else:
+            dec.decode(llr, syn, iters, out=out)
     torch.cuda.synchronize()
 
     if args.calib_copy_mb:
@@ -150,7 +161,7 @@ def main():
         dec.autotune(llr, syn, iters, out=out)
 
     for _ in range(args.warmup):
-        dec.decode(llr, syn, iters, out=out)
+        step()
     torch.cuda.synchronize()
     print(f"[bench] warmup done; timing {args.steps} steps", file=sys.stderr, flush=True)
 
@@ -159,7 +170,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        dec.decode(llr, syn, iters, out=out)
+        step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof = dec.profile(reset=True)
@@ -189,30 +200,45 @@ def main():
         bytes_per_launch = prof["layer_bytes"] / prof["launches"]
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
         traffic = load_traffic(args.workload, args.fp16)
+        if args.early_stop:
+            traffic = None
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                    "kernel": "k_layer_sp", "avg_launch_us": round(avg_ms * 1e3, 3),
+                    "kernel": "k_layer_sp_et" if args.early_stop else "k_layer_sp",
+                    "avg_launch_us": round(avg_ms * 1e3, 3),
                     "algorithmic_bytes_per_launch": round(bytes_per_launch),
-                    "launches_timed": prof["launches"], "timing": "HIP events around whole sweeps on the decode stream"}
+                    "launches_timed": prof["launches"],
+                    "timing": "HIP events around whole sweeps on the decode stream"
+                              + (" (first sweep of each decode, every tile decoding)" if args.early_stop else "")}
+
+    early = None
+    cpu_iters = iters
+    if args.early_stop:
+        it = iters_used.cpu().numpy()
+        early = {"max_iterations": iters, "mean_iterations": round(float(it.mean()), 3),
+                 "iterations_histogram": np.bincount(it, minlength=iters + 1).tolist()}
+        cpu_iters = float(it.mean())
 
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(specs[0], wls[0].shifts, wls[0].llr, wls[0].s, iters)
+        cpu = cpu_baseline(specs[0], wls[0].shifts, wls[0].llr, wls[0].s, cpu_iters)
 
     tun = dec.tuning()
     line = {
-        "metric": METRIC, "value": round(mbit_s, 3), "unit": "Mbit/s", "n_gpus": 1,
+        "metric": METRIC.replace("fixed iters", "early termination") if args.early_stop else METRIC,
+        "value": round(mbit_s, 3), "unit": "Mbit/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if not args.fp16 else "f32 (binary16 messages)", "data": "synthetic",
         "config": {"workload": " + ".join(
                        f"{Fc} x {spec.name} (rate {spec.rate:.2f} QC-MET-LDPC, {spec.mb}x{spec.nb} base, Z={spec.Z}, "
                        f"n={spec.n}, SNR {w.meta['snr']})" for w, spec, Fc in zip(wls, specs, Fs))
-                   + f", {iters} iterations, layered sum-product, {'FP16' if args.fp16 else 'FP32'} messages",
+                   + (f", at most {iters} iterations with early termination" if args.early_stop
+                      else f", {iters} iterations") + f", layered sum-product, {'FP16' if args.fp16 else 'FP32'} messages",
                    "frames": F, "iterations": iters, "layers": [int(c.info.G) for c in codes], "tuning": tun,
                    "per_code": per_code},
-        "fer": fer, "syndrome_fail_rate": syn_fail,
+        "fer": fer, "syndrome_fail_rate": syn_fail, "early_stop": early,
         "hbm_gbs": None if roofline is None else roofline["achieved"],
         "roofline": roofline,
         "cpu_baseline": cpu,

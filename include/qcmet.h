@@ -54,6 +54,8 @@ enum qm_status {
 #define QM_VALIDATE   0x4  /* qm_decode checks inputs first (synchronises the stream) */
 #define QM_GRAPH      0x8  /* replay the whole decode (every code, every sweep) as one captured
                               hipGraph, re-captured when buffers or iters change */
+#define QM_EARLY_STOP 0x10 /* reserve the workspace of qm_decode_early (per code and frame:
+                              4 B per check plus 20 B; at most 8192 frames per code) */
 
 typedef struct qm_code qm_code;
 typedef struct qm_decoder qm_decoder;
@@ -145,6 +147,27 @@ int qm_decoder_get_tuning(const qm_decoder *dec, qm_tuning *tuning);
  * every layer); their APP is formed from the messages of the last sweep. */
 int qm_decode(qm_decoder *dec, const float *llr, const uint8_t *syndrome, int32_t iters,
               uint8_t *hard, float *app, uint8_t *flags, void *stream);
+
+/* Layered sum-product decode with early termination (Results, Table
+ * tabearly): before the first sweep and after every sweep each frame's hard
+ * decisions are tested against its syndrome, and a frame that passes stops
+ * there.  A frame that stops after t sweeps gets exactly the outputs of a
+ * qm_decode with iters = t.  Frames that stop free their tile slots: once
+ * enough have stopped to empty a tile of frames, the frames still decoding
+ * are moved to the leading tiles and later sweeps skip the empty ones.
+ * Needs a decoder created with QM_EARLY_STOP (else QM_ERR_UNSUPPORTED).
+ *   max_iters  >= 0: sweeps for frames that never pass
+ *   iters_used device int32 [sum_c F_c] out: sweeps each frame ran (or NULL)
+ *   other arguments as qm_decode.
+ * The host polls the device every 4 sweeps (pinned memory, one poll late) and
+ * stops enqueueing sweeps once no frame is left, so the call returns before
+ * the decode has finished but may block on earlier sweeps; it is not
+ * captured into a graph (QM_GRAPH does not apply).  With profiling on, the
+ * layer launches of the first sweep are timed (every tile still decodes);
+ * their layer_bytes add, per check with a degree-1 column, the LLR_d read and
+ * the degree-1 APP written every sweep (2 x 4 bytes). */
+int qm_decode_early(qm_decoder *dec, const float *llr, const uint8_t *syndrome, int32_t max_iters,
+                    uint8_t *hard, float *app, uint8_t *flags, int32_t *iters_used, void *stream);
 
 /* Times result-preserving tunings on the given inputs and keeps the fastest:
  * frames per tile {16, 32, 64} x frames per lane {1, 2} x block {128, 256},

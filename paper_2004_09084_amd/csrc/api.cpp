@@ -129,6 +129,8 @@ struct Slot {
     int32_t F = 0, Fpad = 0;
     int64_t n = 0, m = 0;
     size_t oA = 0, oR = 0, oK = 0, oS = 0, oFail = 0, oRows = 0;
+    // early termination (decoders created with QM_EARLY_STOP)
+    size_t oAd = 0, oAct = 0, oMap = 0, oPerm = 0, oIt = 0, oCtl = 0;
     std::vector<RowDesc> hrows;  // schedule order
     std::vector<int32_t> gptr;
     int maxd_t = 4;
@@ -163,6 +165,9 @@ struct qm_decoder {
     size_t oAd = 0, oAct = 0, oIt = 0, oCols = 0, oLossP = 0, oLoss = 0, oX = 0, ogA = 0, ogAd = 0, ogR = 0, oQ = 0,
            oCkA = 0, oCkR = 0, oPart = 0, nTotal = 0;
     std::vector<int32_t> acols;  // columns whose APP lives in A (degree != 1)
+    // early termination: host polls of the frames still decoding
+    int32_t *h_poll = nullptr;   // pinned, 2 words
+    hipEvent_t poll_ev[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -196,6 +201,14 @@ void layout(qm_decoder &d) {
         s.oS = off; off = align_up(off + fp * (size_t)s.m);
         s.oFail = off; off = align_up(off + fp * 4);
         s.oRows = off; off = align_up(off + s.hrows.size() * sizeof(RowDesc));
+        if (d.flags & QM_EARLY_STOP) {
+            s.oAd = off; off = align_up(off + fp * (size_t)s.m * 4);
+            s.oAct = off; off = align_up(off + fp * 4);
+            s.oMap = off; off = align_up(off + fp * 4);
+            s.oPerm = off; off = align_up(off + fp * 4);
+            s.oIt = off; off = align_up(off + fp * 4);
+            s.oCtl = off; off = align_up(off + QM_ET_CTL_WORDS * 4);
+        }
     }
     d.oErr = off;
     off = align_up(off + 4);
@@ -214,10 +227,13 @@ int take_event(qm_decoder &d, hipEvent_t *ev, size_t *index) {
 }
 
 // algorithmic bytes / check updates of one layer launch over `rows`
-void layer_work(const Slot &s, const RowDesc *hrows, int nrows, int msg16, double *bytes, double *checks) {
+// (early: the early-terminating form, which also reads LLR_d and writes the
+// degree-1 APP of every check that has a degree-1 column, every sweep)
+void layer_work(const Slot &s, const RowDesc *hrows, int nrows, int msg16, double *bytes, double *checks,
+                bool early = false) {
     const double per_edge = msg16 ? 12.0 : 16.0;
     double b = 0.0;
-    for (int r = 0; r < nrows; ++r) b += per_edge * hrows[r].d + 4.0;
+    for (int r = 0; r < nrows; ++r) b += per_edge * hrows[r].d + 4.0 + ((early && hrows[r].d1col >= 0) ? 8.0 : 0.0);
     const double fz = (double)s.F * s.code->Z;
     *bytes = b * fz;
     *checks = (double)nrows * fz;
@@ -470,6 +486,106 @@ int enqueue_decode(qm_decoder &d, const float *llr, const uint8_t *syn, int32_t 
     return enqueue_finalize(d, hard, app, flags, st);
 }
 
+// ------------------------------------------------------ early termination --
+
+// Sweeps of one code until every frame has met its syndrome or T sweeps
+// have run (Results, Table tabearly): after each sweep the frames still
+// decoding are tested, those that pass stop with the state they have, and
+// frames are compacted into the leading tiles when that frees a tile.  The
+// host stops enqueueing once a poll (every 4 sweeps, read one poll late so
+// the queue never drains) shows no frame left.
+int enqueue_early_slot(qm_decoder &d, Slot &s, int32_t T, uint8_t *hard, float *app, uint8_t *flags,
+                       int32_t *iters_out, hipStream_t st) {
+    const qm_code &c = *s.code;
+    const TileGeom g = geom(d, s);
+    const SlotBufs b = slot_bufs(d, s);
+    const int msg16 = (d.flags & QM_MSG_FP16) ? 1 : 0;
+    float *Ad = reinterpret_cast<float *>(d.ws + s.oAd);
+    uint32_t *act = reinterpret_cast<uint32_t *>(d.ws + s.oAct);
+    int32_t *map = reinterpret_cast<int32_t *>(d.ws + s.oMap);
+    int32_t *perm = reinterpret_cast<int32_t *>(d.ws + s.oPerm);
+    int32_t *it = reinterpret_cast<int32_t *>(d.ws + s.oIt);
+    int32_t *ctl = reinterpret_cast<int32_t *>(d.ws + s.oCtl);
+    QM_HIP(qm_launch_et_init(act, map, it, ctl, s.Fpad, g.ntiles, st));
+    QM_HIP(qm_launch_commit_d1(b.A, Ad, 0, b.rows, c.mb, g, st));  // Ad = LLR_d
+    const CompactArray arr[QM_COMPACT_ARRAYS] = {
+        {b.A, s.n, 4}, {b.R, (int64_t)c.nent1 * c.Z, msg16 ? 2 : 4}, {b.K, s.m, 4}, {b.S, s.m, 1}, {Ad, s.m, 4}};
+    auto test = [&](int t) -> int {
+        QM_HIP(qm_launch_syndrome_et(b.A, Ad, b.S, b.rows, c.mb, b.fail, ctl, g, st));
+        QM_HIP(qm_launch_et_plan(b.fail, act, map, perm, it, ctl, s.Fpad, g.ft_log2, t, 0, st));
+        QM_HIP(qm_launch_compact(arr, QM_COMPACT_ARRAYS, perm, ctl, s.Fpad, g.ft_log2, st));
+        return QM_OK;
+    };
+    int rc = test(0);
+    if (rc != QM_OK) return rc;
+    LayerArgs la = layer_args(d, s);
+    la.Ad = Ad;
+    la.act = act;
+    la.ctl = ctl;
+    la.last = 0;
+    const RowDesc *rows = b.rows;
+    const int G = (int)s.gptr.size() - 1;
+    int pending = -1;
+    for (int t = 0; t < T; ++t) {
+        // profiled: the first sweep, while every tile still decodes (frames
+        // whose channel decisions already pass are the exception)
+        ProfScope sweep(d, st, d.profiling && t == 0);
+        if ((rc = sweep.begin()) != QM_OK) return rc;
+        double bytes = 0.0, checks = 0.0;
+        int launches = 0;
+        for (int gi = 0; gi < G; ++gi) {
+            const int p_lo = s.gptr[gi], p_hi = s.gptr[gi + 1];
+            const int step = d.tun.merge ? (p_hi - p_lo) : 1;
+            for (int p = p_lo; p < p_hi; p += step) {
+                la.rows = rows + p;
+                la.nrows = step;
+                QM_HIP(qm_launch_layer_et(la, msg16, s.maxd_t, la.fpl, d.tun.block, d.tun.stream_hint, st));
+                double bb, ch;
+                layer_work(s, s.hrows.data() + p, step, msg16, &bb, &ch, true);
+                bytes += bb;
+                checks += ch;
+                ++launches;
+            }
+        }
+        if ((rc = sweep.end(bytes, checks, launches)) != QM_OK) return rc;
+        if ((rc = test(t + 1)) != QM_OK) return rc;
+        if ((t + 1) % 4 == 0 && t + 1 < T) {
+            if (pending >= 0) {
+                QM_HIP(hipEventSynchronize(d.poll_ev[pending]));
+                if (d.h_poll[pending] == 0) break;
+            }
+            pending = pending < 0 ? 0 : 1 - pending;
+            QM_HIP(hipMemcpyAsync(&d.h_poll[pending], ctl, 4, hipMemcpyDeviceToHost, st));
+            QM_HIP(hipEventRecord(d.poll_ev[pending], st));
+        }
+    }
+    // frames still decoding ran all T sweeps
+    QM_HIP(qm_launch_et_plan(b.fail, act, map, perm, it, ctl, s.Fpad, g.ft_log2, T, 1, st));
+    QM_HIP(qm_launch_commit_d1(b.A, Ad, 1, b.rows, c.mb, g, st));  // degree-1 APPs into A
+    QM_HIP(qm_launch_syndrome(b.A, nullptr, b.S, b.rows, c.mb, b.fail, g, st));
+    QM_HIP(qm_launch_finalize(b.A, b.fail, app, hard, flags, s.F, g, st, map));
+    if (iters_out && s.F > 0)
+        QM_HIP(hipMemcpyAsync(iters_out, it, (size_t)s.F * 4, hipMemcpyDeviceToDevice, st));
+    return QM_OK;
+}
+
+int validate_inputs(qm_decoder &d, const float *llr, const uint8_t *syn, hipStream_t st) {
+    size_t nl = 0, ns = 0;
+    for (const Slot &s : d.slots) {
+        nl += (size_t)s.F * s.n;
+        ns += (size_t)s.F * s.m;
+    }
+    uint32_t *err = reinterpret_cast<uint32_t *>(d.ws + d.oErr);
+    QM_HIP(qm_launch_fill_u32(err, 0u, 1, st));
+    QM_HIP(qm_launch_validate(llr, nl, syn, ns, err, st));
+    uint32_t h = 0;
+    QM_HIP(hipMemcpyAsync(&h, err, 4, hipMemcpyDeviceToHost, st));
+    QM_HIP(hipStreamSynchronize(st));
+    if (h & 1u) return fail(QM_ERR_INPUT, "non-finite channel LLR");
+    if (h & 2u) return fail(QM_ERR_INPUT, "syndrome value other than 0/1");
+    return QM_OK;
+}
+
 // ---------------------------------------------------------- learned decoder --
 
 int nms_slot(qm_decoder &d, Slot **out) {
@@ -671,7 +787,7 @@ int qm_decoder_create(const qm_code *const *codes, int32_t ncodes, const int32_t
     if (!out) return fail(QM_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (!codes || !frames_per_code || ncodes <= 0) return fail(QM_ERR_INVALID_ARG, "need at least one code");
-    if (flags & ~(QM_MSG_FP16 | QM_VALIDATE | QM_GRAPH))
+    if (flags & ~(QM_MSG_FP16 | QM_VALIDATE | QM_GRAPH | QM_EARLY_STOP))
         return fail(QM_ERR_INVALID_ARG, "unknown flag bits");
     qm_decoder *d = new (std::nothrow) qm_decoder;
     if (!d) return fail(QM_ERR_OOM, "out of host memory");
@@ -692,6 +808,11 @@ int qm_decoder_create(const qm_code *const *codes, int32_t ncodes, const int32_t
                 s.Fpad = 1;
                 while (s.Fpad < s.F) s.Fpad <<= 1;
             }
+        }
+        if ((flags & QM_EARLY_STOP) && s.Fpad > QM_ET_MAXF) {
+            delete d;
+            return fail(QM_ERR_UNSUPPORTED, "early termination takes at most " + std::to_string(QM_ET_MAXF) +
+                                                " frames per code");
         }
         s.n = (int64_t)s.code->nb * s.code->Z;
         s.m = (int64_t)s.code->mb * s.code->Z;
@@ -725,6 +846,9 @@ int qm_decoder_destroy(qm_decoder *d) {
     drop_graph(*d);
     if (d->cap) (void)hipStreamDestroy(d->cap);
     for (hipEvent_t e : d->ev_pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : d->poll_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (d->h_poll) (void)hipHostFree(d->h_poll);
     delete d;
     return QM_OK;
 }
@@ -783,19 +907,8 @@ int qm_decode(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t iters
     if (iters < 0) return fail(QM_ERR_INVALID_ARG, "iters must be >= 0");
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (d->flags & QM_VALIDATE) {
-        size_t nl = 0, ns = 0;
-        for (const Slot &s : d->slots) {
-            nl += (size_t)s.F * s.n;
-            ns += (size_t)s.F * s.m;
-        }
-        uint32_t *err = reinterpret_cast<uint32_t *>(d->ws + d->oErr);
-        QM_HIP(qm_launch_fill_u32(err, 0u, 1, st));
-        QM_HIP(qm_launch_validate(llr, nl, syn, ns, err, st));
-        uint32_t h = 0;
-        QM_HIP(hipMemcpyAsync(&h, err, 4, hipMemcpyDeviceToHost, st));
-        QM_HIP(hipStreamSynchronize(st));
-        if (h & 1u) return fail(QM_ERR_INPUT, "non-finite channel LLR");
-        if (h & 2u) return fail(QM_ERR_INPUT, "syndrome value other than 0/1");
+        const int rc = validate_inputs(*d, llr, syn, st);
+        if (rc != QM_OK) return rc;
     }
     if (!d->tun.graph || d->profiling) return enqueue_decode(*d, llr, syn, iters, hard, app, flags, st);
 
@@ -820,6 +933,39 @@ int qm_decode(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t iters
         d->giters = iters;
     }
     QM_HIP(hipGraphLaunch(d->gexec, st));
+    return QM_OK;
+}
+
+int qm_decode_early(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t max_iters, uint8_t *hard,
+                    float *app, uint8_t *flags, int32_t *iters_used, void *stream) {
+    if (!d) return fail(QM_ERR_INVALID_ARG, "decoder is NULL");
+    if (!(d->flags & QM_EARLY_STOP)) return fail(QM_ERR_UNSUPPORTED, "decoder was not created with QM_EARLY_STOP");
+    if (!d->bound) return fail(QM_ERR_NO_WORKSPACE, "no workspace bound");
+    if (!llr || !syn || !hard || !flags) return fail(QM_ERR_INVALID_ARG, "NULL buffer");
+    if (max_iters < 0) return fail(QM_ERR_INVALID_ARG, "max_iters must be >= 0");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (d->flags & QM_VALIDATE) {
+        const int rc = validate_inputs(*d, llr, syn, st);
+        if (rc != QM_OK) return rc;
+    }
+    if (!d->h_poll) {
+        void *p = nullptr;
+        QM_HIP(hipHostMalloc(&p, 2 * sizeof(int32_t), hipHostMallocDefault));
+        d->h_poll = static_cast<int32_t *>(p);
+        QM_HIP(hipEventCreateWithFlags(&d->poll_ev[0], hipEventDisableTiming));
+        QM_HIP(hipEventCreateWithFlags(&d->poll_ev[1], hipEventDisableTiming));
+    }
+    int rc = enqueue_init(*d, llr, syn, st);
+    if (rc != QM_OK) return rc;
+    size_t on = 0, of = 0;
+    for (Slot &s : d->slots) {
+        if (s.F == 0) continue;
+        rc = enqueue_early_slot(*d, s, max_iters, hard + on, app ? app + on : nullptr, flags + of,
+                                iters_used ? iters_used + of : nullptr, st);
+        if (rc != QM_OK) return rc;
+        on += (size_t)s.F * s.n;
+        of += (size_t)s.F;
+    }
     return QM_OK;
 }
 

@@ -52,7 +52,23 @@ struct LayerArgs {
     int32_t fpl;              // frames per lane (1, 2, 4)
     int32_t last;             // 1 in the last sweep: also form the degree-1 APPs
     int64_t strideA, strideR, strideK;  // per-tile strides (elements)
+    // early termination (null otherwise): every sweep forms the degree-1
+    // APPs into Ad instead of A; frames with act = 0 are left untouched;
+    // tiles at or past ctl[1] are skipped
+    float *Ad;                // [ntiles][m][FT]
+    const uint32_t *act;      // [Fpad] 1 = frame slot still decoding
+    const int32_t *ctl;       // EtCtl
 };
+
+// Device-side control words of an early-terminating decode of one code.
+//   [0] nact: slots >= nact hold stopped frames
+//   [1] tiles that still hold a decoding frame (ceil(nact / FT))
+//   [2], [3] slots [ctl[3], ctl[2]) to permute by perm before the next
+//        sweep (ctl[2] = 0: none)
+#define QM_ET_CTL_WORDS 4
+// Largest padded frame count of one code in an early-terminating decode
+// (the planning kernel keeps per-slot state in LDS).
+#define QM_ET_MAXF 8192
 
 // Codes one decoder can mix in a single fused launch.
 #define QM_MAX_CODES 4
@@ -98,7 +114,24 @@ hipError_t qm_launch_layer_multi(const MultiLayerArgs &m, int msg16, int maxd, i
 hipError_t qm_launch_syndrome(const float *A, const float *Ad, const uint8_t *Sil, const RowDesc *rows, int mb,
                               uint32_t *fail, const TileGeom &g, hipStream_t s);
 hipError_t qm_launch_finalize(const float *A, const uint32_t *fail, float *app, uint8_t *hard,
-                              uint8_t *flags, int F, const TileGeom &g, hipStream_t s);
+                              uint8_t *flags, int F, const TileGeom &g, hipStream_t s, const int32_t *map = nullptr);
+// early termination (kernels.hip)
+hipError_t qm_launch_layer_et(const LayerArgs &a, int msg16, int maxd, int fpl, int block, int hint, hipStream_t s);
+hipError_t qm_launch_syndrome_et(const float *A, const float *Ad, const uint8_t *Sil, const RowDesc *rows, int mb,
+                                 uint32_t *fail, const int32_t *ctl, const TileGeom &g, hipStream_t s);
+hipError_t qm_launch_et_init(uint32_t *act, int32_t *map, int32_t *iters, int32_t *ctl, int Fpad, int ntiles,
+                             hipStream_t s);
+hipError_t qm_launch_et_plan(uint32_t *fail, uint32_t *act, int32_t *map, int32_t *perm, int32_t *iters,
+                             int32_t *ctl, int Fpad, int ft_log2, int t, int final_pass, hipStream_t s);
+// permute frame slots [ctl[3], ctl[2]) of every per-node array by perm
+struct CompactArray {
+    void *p;                  // [ntiles][N][FT] elements of esz bytes
+    int64_t N;
+    int32_t esz;              // 1, 2 or 4
+};
+#define QM_COMPACT_ARRAYS 5
+hipError_t qm_launch_compact(const CompactArray *arr, int narr, const int32_t *perm, const int32_t *ctl, int Fpad,
+                             int ft_log2, hipStream_t s);
 // nms.hip
 hipError_t qm_launch_nms_kappa(const float *A, const uint8_t *Sil, float *K, const RowDesc *rows, int mb,
                                const TileGeom &g, hipStream_t s);

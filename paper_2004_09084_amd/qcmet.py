@@ -31,13 +31,14 @@ QM_MSG_FP32 = 0x0
 QM_MSG_FP16 = 0x1
 QM_VALIDATE = 0x4
 QM_GRAPH = 0x8
+QM_EARLY_STOP = 0x10
 
 # every symbol include/qcmet.h declares
 EXPORTED = [
     "qm_abi_version", "qm_last_error", "qm_code_create", "qm_code_destroy", "qm_code_get_info",
     "qm_code_set_schedule", "qm_code_get_schedule", "qm_decoder_create", "qm_decoder_destroy",
     "qm_decoder_workspace_bytes", "qm_decoder_bind_workspace", "qm_decoder_set_tuning",
-    "qm_decoder_get_tuning", "qm_decode", "qm_autotune", "qm_decoder_set_profiling",
+    "qm_decoder_get_tuning", "qm_decode", "qm_decode_early", "qm_autotune", "qm_decoder_set_profiling",
     "qm_decoder_get_profile", "qm_nms_workspace_bytes", "qm_nms_bind_workspace", "qm_nms_decode",
     "qm_nms_loss_grad", "qm_adam_step", "qm_generate_frames",
 ]
@@ -96,6 +97,7 @@ def lib():
         L.qm_decoder_set_tuning.argtypes = [p, ctypes.POINTER(qm_tuning)]
         L.qm_decoder_get_tuning.argtypes = [p, ctypes.POINTER(qm_tuning)]
         L.qm_decode.argtypes = [p, p, p, i32, p, p, p, p]
+        L.qm_decode_early.argtypes = [p, p, p, i32, p, p, p, p, p]
         L.qm_autotune.argtypes = [p, p, p, i32, p, p, p, ctypes.c_char_p, p]
         L.qm_decoder_set_profiling.argtypes = [p, i32]
         L.qm_decoder_get_profile.argtypes = [p, ctypes.POINTER(qm_profile), i32]
@@ -218,6 +220,11 @@ def qm_decoder_get_tuning(dec) -> dict:
 def qm_decode(dec, llr, syndrome, iters: int, hard, app, flags, stream=None) -> None:
     _check(lib().qm_decode(dec, _dptr(llr), _dptr(syndrome), int(iters), _dptr(hard), _dptr(app),
                            _dptr(flags), _stream_handle(stream)))
+
+
+def qm_decode_early(dec, llr, syndrome, max_iters: int, hard, app, flags, iters_used=None, stream=None) -> None:
+    _check(lib().qm_decode_early(dec, _dptr(llr), _dptr(syndrome), int(max_iters), _dptr(hard), _dptr(app),
+                                 _dptr(flags), _dptr(iters_used), _stream_handle(stream)))
 
 
 def qm_autotune(dec, llr, syndrome, iters: int, hard, app, flags, cache_path: str | None = None,
@@ -358,6 +365,17 @@ class Decoder:
         hard, app, flags = out if out is not None else self.alloc_outputs(want_app)
         qm_decode(self.handle, llr.reshape(-1), syndrome.reshape(-1), iters, hard, app, flags, stream)
         return hard, app, flags
+
+    def decode_early(self, llr, syndrome, max_iters: int, out=None, want_app: bool = True, stream=None):
+        """Early-terminating decode (decoder created with QM_EARLY_STOP).
+        Returns (hard, app, flags, iters_used) device tensors."""
+        import torch
+        if llr.numel() != self.n_total or syndrome.numel() != self.m_total:
+            raise ValueError("llr/syndrome size does not match the decoder's frames")
+        hard, app, flags = out if out is not None else self.alloc_outputs(want_app)
+        iters = torch.empty(self.F_total, dtype=torch.int32, device=self.device)
+        qm_decode_early(self.handle, llr.reshape(-1), syndrome.reshape(-1), max_iters, hard, app, flags, iters, stream)
+        return hard, app, flags, iters
 
     def set_profiling(self, enable: bool):
         qm_decoder_set_profiling(self.handle, enable)

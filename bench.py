@@ -40,13 +40,14 @@ WORKLOADS = {
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("kernels.hip", "device_common.h", "qcmet_internal.h"):
+    for f in ("layer.h", "phi.h", "device_common.h", "qcmet_internal.h", "layer_f32.hip", "layer_f16.hip",
+              "layer_f8.hip"):
         with open(os.path.join(ROOT, "paper_2004_09084_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload_key: str, fp16: bool):
+def load_traffic(workload_key: str, msg: str):
     """Off-chip bytes per layer launch from the committed rocprofv3 counter
     runs (FETCH_SIZE, WRITE_SIZE, calibrated), if they were taken on the
     current kernel sources; else None."""
@@ -57,7 +58,7 @@ def load_traffic(workload_key: str, fp16: bool):
         data = json.load(open(path))
     except Exception:
         return None
-    key = f"{workload_key}{'_fp16' if fp16 else ''}"
+    key = f"{workload_key}{'_' + msg if msg else ''}"
     ent = data.get(key)
     if not ent or ent.get("kernel_hash") != kernel_source_hash():
         return None
@@ -94,6 +95,7 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="run qm_autotune before timing")
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--fp16", action="store_true", help="store messages as binary16")
+    ap.add_argument("--fp8", action="store_true", help="store messages as 8-bit floats (e4m3)")
     ap.add_argument("--tuning", default=None, help="JSON dict of qm_tuning fields")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
@@ -133,7 +135,9 @@ def main():
     syn = torch.from_numpy(np.concatenate([w.s.reshape(-1) for w in wls])).cuda()
     codes = [Q.Code(w.shifts, spec.Z) for w, spec in zip(wls, specs)]
     tuning = json.loads(args.tuning) if args.tuning else None
-    flags = (Q.QM_MSG_FP16 if args.fp16 else 0) | (Q.QM_EARLY_STOP if args.early_stop else 0)
+    flags = (Q.QM_MSG_FP16 if args.fp16 else 0) | (Q.QM_MSG_FP8 if args.fp8 else 0) \
+        | (Q.QM_EARLY_STOP if args.early_stop else 0)
+    msg_name = "FP16" if args.fp16 else "FP8 (e4m3)" if args.fp8 else "FP32"
     dec = Q.Decoder(codes, Fs, flags=flags, tuning=tuning)
     out = dec.alloc_outputs(want_app=True)
     iters_used = None
@@ -195,11 +199,24 @@ def main():
     syn_fail = float(1.0 - flags.mean())
 
     roofline = None
-    if prof["launches"] > 0:
+    lds_total = prof.get("lds_ms", 0.0)
+    if prof.get("lds_launches", 0) > 0 and prof["launches"] == 0:
+        # the LDS-resident decode dominates: one launch per decode, all sweeps;
+        # its algorithmic HBM bytes leave out the APPs held in LDS
+        avg_ms = lds_total / prof["lds_launches"]
+        achieved = prof["lds_bytes"] / prof["lds_launches"] / (avg_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "kernel": "k_sweeps_lds", "avg_launch_us": round(avg_ms * 1e3, 3),
+                    "algorithmic_bytes_per_launch": round(prof["lds_bytes"] / prof["lds_launches"]),
+                    "launches_timed": prof["lds_launches"],
+                    "timing": "HIP events around each LDS-resident decode launch (all sweeps) on the decode stream",
+                    "bytes": "messages read+written and degree-1 terms per check and sweep; APPs once per frame"}
+    elif prof["launches"] > 0:
         avg_ms = prof["layer_ms"] / prof["launches"]
         bytes_per_launch = prof["layer_bytes"] / prof["launches"]
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-        traffic = load_traffic(args.workload, args.fp16)
+        traffic = load_traffic(args.workload, "fp16" if args.fp16 else "fp8" if args.fp8 else "")
         if args.early_stop:
             traffic = None
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -230,12 +247,12 @@ def main():
         "value": round(mbit_s, 3), "unit": "Mbit/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if not args.fp16 else "f32 (binary16 messages)", "data": "synthetic",
+        "dtype": "f32" if msg_name == "FP32" else f"f32 ({msg_name} messages)", "data": "synthetic",
         "config": {"workload": " + ".join(
                        f"{Fc} x {spec.name} (rate {spec.rate:.2f} QC-MET-LDPC, {spec.mb}x{spec.nb} base, Z={spec.Z}, "
                        f"n={spec.n}, SNR {w.meta['snr']})" for w, spec, Fc in zip(wls, specs, Fs))
                    + (f", at most {iters} iterations with early termination" if args.early_stop
-                      else f", {iters} iterations") + f", layered sum-product, {'FP16' if args.fp16 else 'FP32'} messages",
+                      else f", {iters} iterations") + f", layered sum-product, {msg_name} messages",
                    "frames": F, "iterations": iters, "layers": [int(c.info.G) for c in codes], "tuning": tun,
                    "per_code": per_code},
         "fer": fer, "syndrome_fail_rate": syn_fail, "early_stop": early,

@@ -51,11 +51,15 @@ enum qm_status {
 #define QM_MSG_FP32   0x0  /* check-to-variable messages stored as float32 */
 #define QM_MSG_FP16   0x1  /* messages stored as IEEE binary16 (round to nearest even);
                               all arithmetic and the APP LLRs stay float32 */
+#define QM_MSG_FP8    0x2  /* messages stored as 8-bit floats (1 sign, 4 exponent, 3 mantissa
+                              bits; round to nearest even by the hardware conversion); all
+                              arithmetic and the APP LLRs stay float32.  Excludes QM_MSG_FP16 */
 #define QM_VALIDATE   0x4  /* qm_decode checks inputs first (synchronises the stream) */
 #define QM_GRAPH      0x8  /* replay the whole decode (every code, every sweep) as one captured
                               hipGraph, re-captured when buffers or iters change */
 #define QM_EARLY_STOP 0x10 /* reserve the workspace of qm_decode_early (per code and frame:
-                              4 B per check plus 20 B; at most 8192 frames per code) */
+                              6 B per check, 1 B per variable and 20 B; at most 8192
+                              frames per code) */
 
 typedef struct qm_code qm_code;
 typedef struct qm_decoder qm_decoder;
@@ -87,6 +91,12 @@ typedef struct {
     int32_t stream_hint;      /* 1: messages and per-check terms are read and written with the
                                  non-temporal cache policy (they are used once per sweep), so the
                                  APP columns that the next layers reuse stay cached */
+    int32_t lds_resident;     /* 1: a code whose degree>=2 APPs of one frame fit in one workgroup's
+                                 LDS (at most 8 such entries per row) is decoded by one workgroup
+                                 per frame that keeps those APPs in LDS through every sweep, with
+                                 workgroup barriers between layers (one launch per decode; such a
+                                 code uses one frame per tile).  Bit-identical to the layer
+                                 kernels. */
 } qm_tuning;
 
 int qm_abi_version(void);
@@ -155,6 +165,8 @@ int qm_decode(qm_decoder *dec, const float *llr, const uint8_t *syndrome, int32_
  * qm_decode with iters = t.  Frames that stop free their tile slots: once
  * enough have stopped to empty a tile of frames, the frames still decoding
  * are moved to the leading tiles and later sweeps skip the empty ones.
+ * The per-sweep test reads packed hard decisions (one bit per frame) that
+ * the layer kernel writes as it updates each variable and check. 
  * Needs a decoder created with QM_EARLY_STOP (else QM_ERR_UNSUPPORTED).
  *   max_iters  >= 0: sweeps for frames that never pass
  *   iters_used device int32 [sum_c F_c] out: sweeps each frame ran (or NULL)
@@ -171,8 +183,8 @@ int qm_decode_early(qm_decoder *dec, const float *llr, const uint8_t *syndrome, 
 
 /* Times result-preserving tunings on the given inputs and keeps the fastest:
  * frames per tile {16, 32, 64} x frames per lane {1, 2} x block {128, 256},
- * then, on the best, per-row launches, unfused codes, graph replay and the
- * other stream_hint.  The
+ * then, on the best, per-row launches, unfused codes, graph replay, the
+ * other stream_hint and (if a code fits) the other lds_resident.  The
  * schedule (row order) is never changed, so every trial decodes to the same
  * bits.  Each trial decodes min(iters, 8) sweeps into the caller's output
  * buffers (same shapes as qm_decode); the call synchronises the stream.
@@ -191,7 +203,7 @@ int qm_autotune(qm_decoder *dec, const float *llr, const uint8_t *syndrome, int3
  * them.
  * layer_bytes counts the algorithmic HBM bytes of the timed launches: per
  * check and frame 4 (its degree-1 term) plus, per degree>=2 edge, the message
- * read and written (2 x 4 bytes, or 2 x 2 with QM_MSG_FP16) and the APP read
+ * read and written (2 x 4 bytes; 2 x 2 with QM_MSG_FP16, 2 x 1 with QM_MSG_FP8) and the APP read
  * and written (2 x 4 bytes). */
 typedef struct {
     int32_t launches;     /* layer launches inside the timed windows */
@@ -200,6 +212,11 @@ typedef struct {
     double sweep_ms;      /* unused (0) */
     double layer_bytes;   /* algorithmic bytes of the timed layer launches */
     double checks;        /* check-frame updates in the timed launches */
+    int32_t lds_launches; /* LDS-resident decodes timed (one launch each, every sweep) */
+    double lds_ms;        /* their summed duration */
+    double lds_bytes;     /* their algorithmic HBM bytes: per check and frame and sweep 4 (its
+                             degree-1 term) plus, per degree>=2 edge, the message read and
+                             written; plus each frame's degree>=2 APPs read and written once */
 } qm_profile;
 
 int qm_decoder_set_profiling(qm_decoder *dec, int32_t enable);
@@ -234,7 +251,10 @@ int qm_nms_decode(qm_decoder *dec, const float *weights, const float *llr, const
  * (P(bit = 1) = sigmoid(-APP)), and its exact gradient with respect to the
  * weights by a reverse sweep that restores each sweep's starting state from
  * its checkpoint and recomputes it.  Gradient sums over workgroups are
- * reduced in a fixed order (run-to-run identical).
+ * reduced in a fixed order (run-to-run identical).  Over many sweeps the
+ * reverse-sweep adjoints can grow geometrically; they are bounded at 1e30
+ * (no inf or NaN in float32), which leaves the gradient exact wherever it
+ * stays below that bound.
  *   x: device uint8 [F][n]; loss: device float scalar; grad: device float,
  *   same layout as weights (first T sweeps).  Needs a train workspace. */
 int qm_nms_loss_grad(qm_decoder *dec, const float *weights, const float *llr, const uint8_t *syndrome,
@@ -253,7 +273,8 @@ int qm_generate_frames(qm_decoder *dec, int32_t code_index, uint64_t seed, uint6
 
 /* Adam (Kingma & Ba) on device arrays of `count` floats, step >= 1:
  * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
- * w -= lr * (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps). */
+ * w -= lr * (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps),
+ * with a non-finite g taken as 0 and |g| capped at 1e15 (so g^2 is finite). */
 int qm_adam_step(float *w, const float *g, float *m, float *v, int32_t count, float lr, float b1, float b2,
                  float eps, int32_t step, void *stream);
 

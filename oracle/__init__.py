@@ -38,6 +38,7 @@ def _load(path: str):
     L.qo_clip.restype = d; L.qo_clip.argtypes = [d]
     L.qo_x_lo.restype = d; L.qo_x_hi.restype = d
     L.qo_round_half.restype = d; L.qo_round_half.argtypes = [d]
+    L.qo_round_e4m3.restype = d; L.qo_round_e4m3.argtypes = [d]
     L.qo_greedy_schedule.restype = i32
     L.qo_greedy_schedule.argtypes = [i32, i32, p, p, p, p]
     L.qo_check_schedule.restype = i32
@@ -109,6 +110,10 @@ def round_half(v: float) -> float:
     return lib().qo_round_half(float(v))
 
 
+def round_e4m3(v: float) -> float:
+    return lib().qo_round_e4m3(float(v))
+
+
 def greedy_schedule(shifts: np.ndarray):
     """Greedy layer merge: (group_ptr int32 [G+1], rows int32 [mb])."""
     sh = np.ascontiguousarray(shifts, dtype=np.int32)
@@ -149,7 +154,13 @@ def _prep(shifts, Z, llr, syn, schedule):
     return sh, mb, nb, n, m, L, S, gp, rw
 
 
-def decode_sp(shifts, Z, llr, syn, T, schedule=None, fp16_messages=False, threads=0):
+def _msg_mode(fp16_messages, fp8_messages):
+    if fp16_messages and fp8_messages:
+        raise ValueError("fp16_messages and fp8_messages exclude each other")
+    return 1 if fp16_messages else 2 if fp8_messages else 0
+
+
+def decode_sp(shifts, Z, llr, syn, T, schedule=None, fp16_messages=False, threads=0, fp8_messages=False):
     """Layered sum-product in FP64.  Returns (app f64 [F,n], hard u8 [F,n],
     flags u8 [F], threads_used)."""
     sh, mb, nb, n, m, L, S, gp, rw = _prep(shifts, Z, llr, syn, schedule)
@@ -158,14 +169,14 @@ def decode_sp(shifts, Z, llr, syn, T, schedule=None, fp16_messages=False, thread
     hard = np.empty((F, n), dtype=np.uint8)
     flags = np.empty(F, dtype=np.uint8)
     rc = lib().qo_decode_sp(mb, nb, Z, _ptr(sh), len(gp) - 1, _ptr(gp), _ptr(rw), F, _ptr(L), _ptr(S),
-                            int(T), 1 if fp16_messages else 0, _ptr(app), _ptr(hard), _ptr(flags),
+                            int(T), _msg_mode(fp16_messages, fp8_messages), _ptr(app), _ptr(hard), _ptr(flags),
                             int(threads))
     if rc <= 0:
         raise RuntimeError(f"qo_decode_sp failed: {rc}")
     return app, hard, flags, rc
 
 
-def decode_sp_early(shifts, Z, llr, syn, T, schedule=None, fp16_messages=False, threads=0):
+def decode_sp_early(shifts, Z, llr, syn, T, schedule=None, fp16_messages=False, threads=0, fp8_messages=False):
     """Layered sum-product with early termination: each frame stops at the
     first sweep count in [0, T] whose hard decisions satisfy the syndrome.
     Returns (app, hard, flags, iters_used)."""
@@ -176,7 +187,7 @@ def decode_sp_early(shifts, Z, llr, syn, T, schedule=None, fp16_messages=False, 
     flags = np.empty(F, dtype=np.uint8)
     iters = np.empty(F, dtype=np.int32)
     rc = lib().qo_decode_sp_early(mb, nb, Z, _ptr(sh), len(gp) - 1, _ptr(gp), _ptr(rw), F, _ptr(L), _ptr(S),
-                                  int(T), 1 if fp16_messages else 0, _ptr(app), _ptr(hard), _ptr(flags),
+                                  int(T), _msg_mode(fp16_messages, fp8_messages), _ptr(app), _ptr(hard), _ptr(flags),
                                   _ptr(iters), int(threads))
     if rc <= 0:
         raise RuntimeError(f"qo_decode_sp_early failed: {rc}")

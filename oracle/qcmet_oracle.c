@@ -29,7 +29,9 @@
  *                     (step 4).  Every edge keeps its own message, degree-1
  *                     variables included: the oracle does not defer them.
  *                     msg_mode 1 rounds every new r to IEEE binary16
- *                     (round to nearest even) and keeps all else in FP64.
+ *                     (round to nearest even) and keeps all else in FP64;
+ *                     msg_mode 2 rounds it to an 8-bit float (4 exponent,
+ *                     3 mantissa bits, round to nearest even).
  *   qo_decode_sp_early The same with early termination (Results, Table
  *                     tabearly): a frame stops at the first sweep count
  *                     whose hard decisions satisfy the syndrome.
@@ -82,6 +84,23 @@ double qo_round_half(double v) {
     double quantum = ldexp(1.0, qe);
     double r = nearbyint(a / quantum) * quantum;
     if (r > 65504.0) r = INFINITY;
+    return copysign(r, v);
+}
+
+/* 8-bit float with 1 sign, 4 exponent (bias 7) and 3 mantissa bits, no
+ * infinities, largest finite 448, subnormal spacing 2^-9 (the OCP e4m3
+ * format): round to nearest, ties to even, from the definition; values
+ * beyond 448 saturate. */
+double qo_round_e4m3(double v) {
+    if (v == 0.0 || !isfinite(v)) return v;
+    double a = fabs(v);
+    int e;
+    frexp(a, &e);               /* a in [2^(e-1), 2^e) */
+    int qe = e - 4;             /* spacing of 4-bit significands in that binade */
+    if (qe < -9) qe = -9;       /* subnormal range (exponent -6, 3 fraction bits) */
+    double quantum = ldexp(1.0, qe);
+    double r = nearbyint(a / quantum) * quantum;
+    if (r > 448.0) r = 448.0;
     return copysign(r, v);
 }
 
@@ -305,6 +324,7 @@ static void sp_frame(void *vctx, int f) {
                         double mag = qo_phi(qo_clip(S));
                         double v = neg ? -mag : mag;
                         if (x->mode == 1) v = qo_round_half(v);
+                        else if (x->mode == 2) v = qo_round_e4m3(v);
                         rn[a] = v;
                     }
                     /* step 3, second equation: APP_n = q_nm + r_mn(new) */
@@ -325,13 +345,13 @@ static void sp_frame(void *vctx, int f) {
  *   llr  float [F][n]   channel LLRs (widened exactly to FP64)
  *   syn  uint8 [F][m]   syndrome bits
  *   T    iterations (full sweeps over all groups in schedule order)
- *   mode 0: FP64 messages; 1: messages rounded to binary16
+ *   mode 0: FP64 messages; 1: messages rounded to binary16; 2: to e4m3
  *   app  double [F][n], hard uint8 [F][n], flags uint8 [F] (outputs)
  * Returns the number of threads used (>0) or a negative error. */
 int qo_decode_sp(int mb, int nb, int Z, const int *sh, int G, const int *gptr, const int *rows,
                  int F, const float *llr, const uint8_t *syn, int T, int mode,
                  double *app, uint8_t *hard, uint8_t *flags, int nthreads) {
-    if (mb <= 0 || nb <= 0 || Z <= 0 || F < 0 || T < 0 || (mode != 0 && mode != 1)) return -1;
+    if (mb <= 0 || nb <= 0 || Z <= 0 || F < 0 || T < 0 || mode < 0 || mode > 2) return -1;
     if (qo_check_schedule(mb, nb, sh, G, gptr, rows) != 0) return -3;
     code_t c;
     int rc = code_build(&c, mb, nb, Z, sh);
@@ -349,7 +369,7 @@ int qo_decode_sp(int mb, int nb, int Z, const int *sh, int G, const int *gptr, c
 int qo_decode_sp_early(int mb, int nb, int Z, const int *sh, int G, const int *gptr, const int *rows,
                        int F, const float *llr, const uint8_t *syn, int T, int mode,
                        double *app, uint8_t *hard, uint8_t *flags, int32_t *iters, int nthreads) {
-    if (mb <= 0 || nb <= 0 || Z <= 0 || F < 0 || T < 0 || (mode != 0 && mode != 1)) return -1;
+    if (mb <= 0 || nb <= 0 || Z <= 0 || F < 0 || T < 0 || mode < 0 || mode > 2) return -1;
     if (qo_check_schedule(mb, nb, sh, G, gptr, rows) != 0) return -3;
     code_t c;
     int rc = code_build(&c, mb, nb, Z, sh);

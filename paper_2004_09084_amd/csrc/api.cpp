@@ -118,6 +118,9 @@ RowDesc make_desc(const qm_code &c, int i) {
             d.col[d.d] = j;
             d.shift[d.d] = a;
             d.ent[d.d] = c.ent[i * c.nb + j];
+            int rank = 0;
+            for (int jj = 0; jj < j; ++jj) rank += c.col_deg[jj] >= 2 ? 1 : 0;
+            d.lcol[d.d] = rank;
             d.d++;
         }
     }
@@ -130,9 +133,11 @@ struct Slot {
     int64_t n = 0, m = 0;
     size_t oA = 0, oR = 0, oK = 0, oS = 0, oFail = 0, oRows = 0;
     // early termination (decoders created with QM_EARLY_STOP)
-    size_t oAd = 0, oAct = 0, oMap = 0, oPerm = 0, oIt = 0, oCtl = 0;
+    size_t oAd = 0, oAct = 0, oMap = 0, oPerm = 0, oIt = 0, oCtl = 0, oPA = 0, oPd = 0, oPS = 0;
     std::vector<RowDesc> hrows;  // schedule order
     std::vector<int32_t> gptr;
+    std::vector<int32_t> cols1;  // degree>=2 block columns (LDS order)
+    size_t oGptr = 0, oCols1 = 0;
     int maxd_t = 4;
 };
 
@@ -165,6 +170,13 @@ struct qm_decoder {
     size_t oAd = 0, oAct = 0, oIt = 0, oCols = 0, oLossP = 0, oLoss = 0, oX = 0, ogA = 0, ogAd = 0, ogR = 0, oQ = 0,
            oCkA = 0, oCkR = 0, oPart = 0, nTotal = 0;
     std::vector<int32_t> acols;  // columns whose APP lives in A (degree != 1)
+    int64_t lds_limit = 0;      // LDS bytes one workgroup may use (queried at bind)
+    // LDS-resident codes of a mixed decode run on a side stream, forked from
+    // and joined back to the decode stream with events
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    struct LdsPending { size_t a, b; double bytes; };
+    std::vector<LdsPending> lds_pending;
     // early termination: host polls of the frames still decoding
     int32_t *h_poll = nullptr;   // pinned, 2 words
     hipEvent_t poll_ev[2] = {nullptr, nullptr};
@@ -172,7 +184,23 @@ struct qm_decoder {
 
 namespace {
 
+// message storage kind and bytes per message
+int msg_kind(const qm_decoder &d) {
+    return (d.flags & QM_MSG_FP16) ? QM_MSGK_F16 : (d.flags & QM_MSG_FP8) ? QM_MSGK_F8 : QM_MSGK_F32;
+}
+size_t msg_bytes(const qm_decoder &d) {
+    const int k = msg_kind(d);
+    return k == QM_MSGK_F16 ? 2 : k == QM_MSGK_F8 ? 1 : 4;
+}
+
+// decoded by the LDS-resident kernel (one frame per tile)?
+bool lds_slot(const qm_decoder &d, const Slot &s) {
+    return d.tun.lds_resident && s.F > 0 && s.code->max_d <= 8 && d.lds_limit > 0 &&
+           (int64_t)qm_lds_bytes((int)s.cols1.size(), s.code->Z) <= d.lds_limit;
+}
+
 int slot_ft(const qm_decoder &d, const Slot &s) {
+    if (lds_slot(d, s)) return 1;
     int ft = d.tun.frames_per_tile;
     if (ft > s.Fpad) ft = s.Fpad;
     return ft < 1 ? 1 : ft;
@@ -192,7 +220,7 @@ TileGeom geom(const qm_decoder &d, const Slot &s) {
 
 void layout(qm_decoder &d) {
     size_t off = 0;
-    const size_t msg = (d.flags & QM_MSG_FP16) ? 2 : 4;
+    const size_t msg = msg_bytes(d);
     for (Slot &s : d.slots) {
         const size_t fp = (size_t)s.Fpad;
         s.oA = off; off = align_up(off + fp * (size_t)s.n * 4);
@@ -201,6 +229,8 @@ void layout(qm_decoder &d) {
         s.oS = off; off = align_up(off + fp * (size_t)s.m);
         s.oFail = off; off = align_up(off + fp * 4);
         s.oRows = off; off = align_up(off + s.hrows.size() * sizeof(RowDesc));
+        s.oGptr = off; off = align_up(off + s.gptr.size() * 4);
+        s.oCols1 = off; off = align_up(off + std::max<size_t>(1, s.cols1.size()) * 4);
         if (d.flags & QM_EARLY_STOP) {
             s.oAd = off; off = align_up(off + fp * (size_t)s.m * 4);
             s.oAct = off; off = align_up(off + fp * 4);
@@ -208,6 +238,11 @@ void layout(qm_decoder &d) {
             s.oPerm = off; off = align_up(off + fp * 4);
             s.oIt = off; off = align_up(off + fp * 4);
             s.oCtl = off; off = align_up(off + QM_ET_CTL_WORDS * 4);
+            // packed hard decisions: max(FT, 8) bits per tile and node, at
+            // most one byte per frame and node (FT = 1), whatever the tuning
+            s.oPA = off; off = align_up(off + fp * (size_t)s.n);
+            s.oPd = off; off = align_up(off + fp * (size_t)s.m);
+            s.oPS = off; off = align_up(off + fp * (size_t)s.m);
         }
     }
     d.oErr = off;
@@ -229,9 +264,9 @@ int take_event(qm_decoder &d, hipEvent_t *ev, size_t *index) {
 // algorithmic bytes / check updates of one layer launch over `rows`
 // (early: the early-terminating form, which also reads LLR_d and writes the
 // degree-1 APP of every check that has a degree-1 column, every sweep)
-void layer_work(const Slot &s, const RowDesc *hrows, int nrows, int msg16, double *bytes, double *checks,
+void layer_work(const Slot &s, const RowDesc *hrows, int nrows, size_t msg, double *bytes, double *checks,
                 bool early = false) {
-    const double per_edge = msg16 ? 12.0 : 16.0;
+    const double per_edge = 8.0 + 2.0 * (double)msg;  // APP read + write, message read + write
     double b = 0.0;
     for (int r = 0; r < nrows; ++r) b += per_edge * hrows[r].d + 4.0 + ((early && hrows[r].d1col >= 0) ? 8.0 : 0.0);
     const double fz = (double)s.F * s.code->Z;
@@ -316,7 +351,7 @@ struct ProfScope {
 
 int enqueue_init(qm_decoder &d, const float *llr, const uint8_t *syn, hipStream_t st) {
     size_t on = 0, om = 0;
-    const int msg16 = (d.flags & QM_MSG_FP16) ? 1 : 0;
+    const size_t msg = msg_bytes(d);
     for (Slot &s : d.slots) {
         if (s.F == 0) continue;
         const qm_code &c = *s.code;
@@ -325,7 +360,7 @@ int enqueue_init(qm_decoder &d, const float *llr, const uint8_t *syn, hipStream_
         QM_HIP(qm_launch_to_tiles_f32(llr + on, b.A, s.F, s.n, g.ft_log2, g.ntiles, st));
         QM_HIP(qm_launch_to_tiles_u8(syn + om, b.S, s.F, s.m, g.ft_log2, g.ntiles, st));
         QM_HIP(qm_launch_kappa(b.A, b.S, b.K, b.rows, c.mb, g, st));
-        const size_t rbytes = align_up((size_t)s.Fpad * c.nent1 * c.Z * (msg16 ? 2 : 4));
+        const size_t rbytes = align_up((size_t)s.Fpad * c.nent1 * c.Z * msg);
         QM_HIP(qm_launch_fill_u32(reinterpret_cast<uint32_t *>(b.R), 0u, rbytes / 4, st));
         QM_HIP(qm_launch_fill_u32(b.fail, 0u, (size_t)s.Fpad, st));
         on += (size_t)s.F * s.n;
@@ -350,7 +385,8 @@ int enqueue_finalize(qm_decoder &d, uint8_t *hard, float *app, uint8_t *flags, h
 
 // Sweeps of one code, one launch per layer (or per row with merge = 0).
 int enqueue_sweeps_slot(qm_decoder &d, Slot &s, int32_t iters, hipStream_t st) {
-    const int msg16 = (d.flags & QM_MSG_FP16) ? 1 : 0;
+    const int msgk = msg_kind(d);
+    const size_t msg = msg_bytes(d);
     const RowDesc *rows = slot_bufs(d, s).rows;
     LayerArgs la = layer_args(d, s);
     const int G = (int)s.gptr.size() - 1;
@@ -372,9 +408,9 @@ int enqueue_sweeps_slot(qm_decoder &d, Slot &s, int32_t iters, hipStream_t st) {
             for (int p = p_lo; p < p_hi; p += step) {
                 la.rows = rows + p;
                 la.nrows = step;
-                QM_HIP(qm_launch_layer(la, msg16, s.maxd_t, la.fpl, d.tun.block, d.tun.stream_hint, st));
+                QM_HIP(qm_launch_layer(la, msgk, s.maxd_t, la.fpl, d.tun.block, d.tun.stream_hint, st));
                 double b, ch;
-                layer_work(s, s.hrows.data() + p, step, msg16, &b, &ch);
+                layer_work(s, s.hrows.data() + p, step, msg, &b, &ch);
                 bytes += b;
                 checks += ch;
                 ++launches;
@@ -388,10 +424,11 @@ int enqueue_sweeps_slot(qm_decoder &d, Slot &s, int32_t iters, hipStream_t st) {
 // Sweeps of every code in fused launches: step k runs layer (k mod G_c) of
 // iteration k / G_c of each code c that still has sweeps left.
 int enqueue_sweeps_fused(qm_decoder &d, int32_t iters, hipStream_t st) {
-    const int msg16 = (d.flags & QM_MSG_FP16) ? 1 : 0;
+    const int msgk = msg_kind(d);
+    const size_t msg = msg_bytes(d);
     std::vector<Slot *> act;
     for (Slot &s : d.slots)
-        if (s.F > 0) act.push_back(&s);
+        if (s.F > 0 && !lds_slot(d, s)) act.push_back(&s);
     const int nc = (int)act.size();
     std::vector<LayerArgs> base(nc);
     std::vector<int> G(nc);
@@ -440,7 +477,7 @@ int enqueue_sweeps_fused(qm_decoder &d, int32_t iters, hipStream_t st) {
                 la.nrows = s.gptr[gi + 1] - s.gptr[gi];
                 off += la.ntiles * la.nrows * la.chunks;
                 double b, ch;
-                layer_work(s, s.hrows.data() + s.gptr[gi], la.nrows, msg16, &b, &ch);
+                layer_work(s, s.hrows.data() + s.gptr[gi], la.nrows, msg, &b, &ch);
                 bytes += b;
                 checks += ch;
             } else {
@@ -449,7 +486,7 @@ int enqueue_sweeps_fused(qm_decoder &d, int32_t iters, hipStream_t st) {
             m.code[c] = la;
         }
         m.block_off[nc] = off;
-        QM_HIP(qm_launch_layer_multi(m, msg16, maxd, fpl, d.tun.block, d.tun.stream_hint, st));
+        QM_HIP(qm_launch_layer_multi(m, msgk, maxd, fpl, d.tun.block, d.tun.stream_hint, st));
         if (in_window) {
             wbytes += bytes;
             wchecks += checks;
@@ -462,9 +499,57 @@ int enqueue_sweeps_fused(qm_decoder &d, int32_t iters, hipStream_t st) {
     return QM_OK;
 }
 
+// All sweeps of one code in one launch of the LDS-resident kernel.
+int ensure_side_stream(qm_decoder &d) {
+    if (!d.side) QM_HIP(hipStreamCreateWithFlags(&d.side, hipStreamNonBlocking));
+    if (!d.ev_fork) QM_HIP(hipEventCreateWithFlags(&d.ev_fork, hipEventDisableTiming));
+    if (!d.ev_join) QM_HIP(hipEventCreateWithFlags(&d.ev_join, hipEventDisableTiming));
+    return QM_OK;
+}
+
+int enqueue_sweeps_lds(qm_decoder &d, Slot &s, int32_t iters, hipStream_t st) {
+    const SlotBufs b = slot_bufs(d, s);
+    LdsArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.A = b.A;
+    a.R = b.R;
+    a.K = b.K;
+    a.rows = b.rows;
+    a.gptr = reinterpret_cast<const int32_t *>(d.ws + s.oGptr);
+    a.cols1 = reinterpret_cast<const int32_t *>(d.ws + s.oCols1);
+    a.G = (int)s.gptr.size() - 1;
+    a.Z = s.code->Z;
+    a.T = iters;
+    a.ncols1 = (int)s.cols1.size();
+    a.n = s.n;
+    a.m = s.m;
+    a.nr = (int64_t)s.code->nent1 * s.code->Z;
+    const bool prof = d.profiling && iters > 0;
+    size_t i0 = 0, i1 = 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (prof) {
+        int rc = take_event(d, &e0, &i0);
+        if (rc != QM_OK) return rc;
+        QM_HIP(hipEventRecord(e0, st));
+    }
+    QM_HIP(qm_launch_sweeps_lds(a, s.F, msg_kind(d), s.maxd_t, st));
+    if (prof) {
+        int rc = take_event(d, &e1, &i1);
+        if (rc != QM_OK) return rc;
+        QM_HIP(hipEventRecord(e1, st));
+        // per sweep: messages read + written and K per check; once: the APPs in and out
+        double per_sweep = 0.0;
+        const double msg = (double)msg_bytes(d);
+        for (const RowDesc &r : s.hrows) per_sweep += 2.0 * msg * r.d + 4.0;
+        const double bytes = (double)s.F * s.code->Z * per_sweep * iters + 8.0 * (double)s.F * s.cols1.size() * s.code->Z;
+        d.lds_pending.push_back(qm_decoder::LdsPending{i0, i1, bytes});
+    }
+    return QM_OK;
+}
+
 bool fused_path(const qm_decoder &d) {
     int nc = 0;
-    for (const Slot &s : d.slots) nc += s.F > 0 ? 1 : 0;
+    for (const Slot &s : d.slots) nc += (s.F > 0 && !lds_slot(d, s)) ? 1 : 0;
     return nc >= 2 && nc <= QM_MAX_CODES && d.tun.fuse_codes && d.tun.merge;
 }
 
@@ -473,16 +558,37 @@ int enqueue_decode(qm_decoder &d, const float *llr, const uint8_t *syn, int32_t 
                    uint8_t *flags, hipStream_t st) {
     int rc = enqueue_init(d, llr, syn, st);
     if (rc != QM_OK) return rc;
+    bool any_lds = false, any_tiled = false;
+    for (const Slot &s : d.slots) {
+        if (s.F == 0) continue;
+        (lds_slot(d, s) ? any_lds : any_tiled) = true;
+    }
+    // LDS-resident codes next to tiled ones run concurrently on the side stream
+    const bool fork = any_lds && any_tiled;
+    hipStream_t ls = st;
+    if (fork) {
+        if (!d.side) return fail(QM_ERR_STATE, "side stream missing");
+        QM_HIP(hipEventRecord(d.ev_fork, st));
+        QM_HIP(hipStreamWaitEvent(d.side, d.ev_fork, 0));
+        ls = d.side;
+    }
+    for (Slot &s : d.slots) {
+        if (!lds_slot(d, s)) continue;
+        rc = enqueue_sweeps_lds(d, s, iters, ls);
+        if (rc != QM_OK) return rc;
+    }
+    if (fork) QM_HIP(hipEventRecord(d.ev_join, d.side));
     if (fused_path(d)) {
         rc = enqueue_sweeps_fused(d, iters, st);
     } else {
         for (Slot &s : d.slots) {
-            if (s.F == 0) continue;
+            if (s.F == 0 || lds_slot(d, s)) continue;
             rc = enqueue_sweeps_slot(d, s, iters, st);
             if (rc != QM_OK) break;
         }
     }
     if (rc != QM_OK) return rc;
+    if (fork) QM_HIP(hipStreamWaitEvent(st, d.ev_join, 0));
     return enqueue_finalize(d, hard, app, flags, st);
 }
 
@@ -499,29 +605,41 @@ int enqueue_early_slot(qm_decoder &d, Slot &s, int32_t T, uint8_t *hard, float *
     const qm_code &c = *s.code;
     const TileGeom g = geom(d, s);
     const SlotBufs b = slot_bufs(d, s);
-    const int msg16 = (d.flags & QM_MSG_FP16) ? 1 : 0;
+    const int msgk = msg_kind(d);
+    const size_t msg = msg_bytes(d);
     float *Ad = reinterpret_cast<float *>(d.ws + s.oAd);
     uint32_t *act = reinterpret_cast<uint32_t *>(d.ws + s.oAct);
     int32_t *map = reinterpret_cast<int32_t *>(d.ws + s.oMap);
     int32_t *perm = reinterpret_cast<int32_t *>(d.ws + s.oPerm);
     int32_t *it = reinterpret_cast<int32_t *>(d.ws + s.oIt);
     int32_t *ctl = reinterpret_cast<int32_t *>(d.ws + s.oCtl);
+    uint8_t *PA = reinterpret_cast<uint8_t *>(d.ws + s.oPA);
+    uint8_t *Pd = reinterpret_cast<uint8_t *>(d.ws + s.oPd);
     QM_HIP(qm_launch_et_init(act, map, it, ctl, s.Fpad, g.ntiles, st));
     QM_HIP(qm_launch_commit_d1(b.A, Ad, 0, b.rows, c.mb, g, st));  // Ad = LLR_d
+    uint8_t *PS = reinterpret_cast<uint8_t *>(d.ws + s.oPS);
+    LayerArgs la = layer_args(d, s);
+    // channel hard decisions and syndrome bits, packed; each sweep rewrites
+    // the decisions, a compaction the syndrome bits
+    QM_HIP(qm_launch_pack_signs(b.A, PA, s.n, la.fpl, g, st));
+    QM_HIP(qm_launch_pack_signs(Ad, Pd, s.m, la.fpl, g, st));
+    QM_HIP(qm_launch_pack_syndrome(b.S, PS, nullptr, 0, la.fpl, g, st));
     const CompactArray arr[QM_COMPACT_ARRAYS] = {
-        {b.A, s.n, 4}, {b.R, (int64_t)c.nent1 * c.Z, msg16 ? 2 : 4}, {b.K, s.m, 4}, {b.S, s.m, 1}, {Ad, s.m, 4}};
+        {b.A, s.n, 4}, {b.R, (int64_t)c.nent1 * c.Z, (int32_t)msg}, {b.K, s.m, 4}, {b.S, s.m, 1}, {Ad, s.m, 4}};
     auto test = [&](int t) -> int {
-        QM_HIP(qm_launch_syndrome_et(b.A, Ad, b.S, b.rows, c.mb, b.fail, ctl, g, st));
+        QM_HIP(qm_launch_syndrome_packed(PA, Pd, PS, b.rows, c.mb, b.fail, ctl, la.fpl, g, st));
         QM_HIP(qm_launch_et_plan(b.fail, act, map, perm, it, ctl, s.Fpad, g.ft_log2, t, 0, st));
         QM_HIP(qm_launch_compact(arr, QM_COMPACT_ARRAYS, perm, ctl, s.Fpad, g.ft_log2, st));
+        QM_HIP(qm_launch_pack_syndrome(b.S, PS, ctl, 1, la.fpl, g, st));
         return QM_OK;
     };
     int rc = test(0);
     if (rc != QM_OK) return rc;
-    LayerArgs la = layer_args(d, s);
     la.Ad = Ad;
     la.act = act;
     la.ctl = ctl;
+    la.PA = PA;
+    la.Pd = Pd;
     la.last = 0;
     const RowDesc *rows = b.rows;
     const int G = (int)s.gptr.size() - 1;
@@ -539,9 +657,9 @@ int enqueue_early_slot(qm_decoder &d, Slot &s, int32_t T, uint8_t *hard, float *
             for (int p = p_lo; p < p_hi; p += step) {
                 la.rows = rows + p;
                 la.nrows = step;
-                QM_HIP(qm_launch_layer_et(la, msg16, s.maxd_t, la.fpl, d.tun.block, d.tun.stream_hint, st));
+                QM_HIP(qm_launch_layer_et(la, msgk, s.maxd_t, la.fpl, d.tun.block, d.tun.stream_hint, st));
                 double bb, ch;
-                layer_work(s, s.hrows.data() + p, step, msg16, &bb, &ch, true);
+                layer_work(s, s.hrows.data() + p, step, msg, &bb, &ch, true);
                 bytes += bb;
                 checks += ch;
                 ++launches;
@@ -597,7 +715,8 @@ int nms_slot(qm_decoder &d, Slot **out) {
             ++n;
         }
     if (n != 1) return fail(QM_ERR_UNSUPPORTED, "the min-sum decoder takes a decoder with exactly one code");
-    if (d.flags & QM_MSG_FP16) return fail(QM_ERR_UNSUPPORTED, "the min-sum decoder keeps float32 messages");
+    if (d.flags & (QM_MSG_FP16 | QM_MSG_FP8))
+        return fail(QM_ERR_UNSUPPORTED, "the min-sum decoder keeps float32 messages");
     *out = only;
     return QM_OK;
 }
@@ -787,8 +906,10 @@ int qm_decoder_create(const qm_code *const *codes, int32_t ncodes, const int32_t
     if (!out) return fail(QM_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (!codes || !frames_per_code || ncodes <= 0) return fail(QM_ERR_INVALID_ARG, "need at least one code");
-    if (flags & ~(QM_MSG_FP16 | QM_VALIDATE | QM_GRAPH | QM_EARLY_STOP))
+    if (flags & ~(QM_MSG_FP16 | QM_MSG_FP8 | QM_VALIDATE | QM_GRAPH | QM_EARLY_STOP))
         return fail(QM_ERR_INVALID_ARG, "unknown flag bits");
+    if ((flags & QM_MSG_FP16) && (flags & QM_MSG_FP8))
+        return fail(QM_ERR_INVALID_ARG, "QM_MSG_FP16 and QM_MSG_FP8 exclude each other");
     qm_decoder *d = new (std::nothrow) qm_decoder;
     if (!d) return fail(QM_ERR_OOM, "out of host memory");
     d->flags = flags;
@@ -823,6 +944,8 @@ int qm_decoder_create(const qm_code *const *codes, int32_t ncodes, const int32_t
         }
         for (int i : s.code->rows) s.hrows.push_back(make_desc(*s.code, i));
         s.gptr = s.code->gptr;
+        for (int j = 0; j < s.code->nb; ++j)
+            if (s.code->col_deg[j] >= 2) s.cols1.push_back(j);
         {
             const int md = s.code->max_d;
             s.maxd_t = md <= 2 ? 2 : md <= 6 ? md : md <= 8 ? 8 : 16;
@@ -848,6 +971,9 @@ int qm_decoder_destroy(qm_decoder *d) {
     for (hipEvent_t e : d->ev_pool) (void)hipEventDestroy(e);
     for (hipEvent_t e : d->poll_ev)
         if (e) (void)hipEventDestroy(e);
+    if (d->ev_fork) (void)hipEventDestroy(d->ev_fork);
+    if (d->ev_join) (void)hipEventDestroy(d->ev_join);
+    if (d->side) (void)hipStreamDestroy(d->side);
     if (d->h_poll) (void)hipHostFree(d->h_poll);
     delete d;
     return QM_OK;
@@ -863,8 +989,16 @@ int qm_decoder_bind_workspace(qm_decoder *d, void *dev, size_t bytes) {
     d->ws = static_cast<char *>(dev);
     d->ws_bytes = bytes;
     drop_graph(*d);
-    for (Slot &s : d->slots)
+    for (Slot &s : d->slots) {
         QM_HIP(hipMemcpy(d->ws + s.oRows, s.hrows.data(), s.hrows.size() * sizeof(RowDesc), hipMemcpyHostToDevice));
+        QM_HIP(hipMemcpy(d->ws + s.oGptr, s.gptr.data(), s.gptr.size() * 4, hipMemcpyHostToDevice));
+        if (!s.cols1.empty())
+            QM_HIP(hipMemcpy(d->ws + s.oCols1, s.cols1.data(), s.cols1.size() * 4, hipMemcpyHostToDevice));
+    }
+    int device = 0, lds = 0;
+    QM_HIP(hipGetDevice(&device));
+    QM_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
+    d->lds_limit = lds;
     d->bound = true;
     return QM_OK;
 }
@@ -888,6 +1022,7 @@ int qm_decoder_set_tuning(qm_decoder *d, const qm_tuning *t) {
     n.graph = n.graph ? 1 : 0;
     n.fuse_codes = n.fuse_codes ? 1 : 0;
     n.stream_hint = n.stream_hint ? 1 : 0;
+    n.lds_resident = n.lds_resident ? 1 : 0;
     d->tun = n;
     drop_graph(*d);
     return QM_OK;
@@ -908,6 +1043,10 @@ int qm_decode(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t iters
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (d->flags & QM_VALIDATE) {
         const int rc = validate_inputs(*d, llr, syn, st);
+        if (rc != QM_OK) return rc;
+    }
+    if (d->tun.lds_resident) {
+        const int rc = ensure_side_stream(*d);
         if (rc != QM_OK) return rc;
     }
     if (!d->tun.graph || d->profiling) return enqueue_decode(*d, llr, syn, iters, hard, app, flags, st);
@@ -988,8 +1127,17 @@ int qm_decoder_get_profile(qm_decoder *d, qm_profile *out, int32_t reset) {
         out->layer_bytes += p.bytes;
         out->checks += p.checks;
     }
+    for (const auto &p : d->lds_pending) {
+        QM_HIP(hipEventSynchronize(d->ev_pool[p.b]));
+        float ms = 0.0f;
+        QM_HIP(hipEventElapsedTime(&ms, d->ev_pool[p.a], d->ev_pool[p.b]));
+        out->lds_launches++;
+        out->lds_ms += ms;
+        out->lds_bytes += p.bytes;
+    }
     if (reset) {
         d->pending.clear();
+        d->lds_pending.clear();
         d->ev_used = 0;
     }
     return QM_OK;
@@ -1183,9 +1331,10 @@ int qm_autotune(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t ite
         if (log)
             std::fprintf(log,
                          "{\"frames_per_tile\": %d, \"frames_per_lane\": %d, \"block\": %d, \"merge\": %d, "
-                         "\"fuse_codes\": %d, \"graph\": %d, \"stream_hint\": %d, \"iters\": %d, \"ms\": %.4f}\n",
+                         "\"fuse_codes\": %d, \"graph\": %d, \"stream_hint\": %d, \"lds_resident\": %d, "
+                         "\"iters\": %d, \"ms\": %.4f}\n",
                          t.frames_per_tile, t.frames_per_lane, t.block, t.merge, t.fuse_codes, t.graph,
-                         t.stream_hint, probe, *ms);
+                         t.stream_hint, t.lds_resident, probe, *ms);
         return QM_OK;
     };
 
@@ -1210,9 +1359,21 @@ int qm_autotune(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t ite
                     best = t;
                 }
             }
+    // could a code use the LDS-resident kernel?
+    bool lds_candidate = false;
+    {
+        const qm_tuning keep = d->tun;
+        d->tun.lds_resident = 1;
+        for (const Slot &s : d->slots) lds_candidate = lds_candidate || lds_slot(*d, s);
+        d->tun = keep;
+    }
     // structural variants on top of the best launch shape
-    for (int v = 0; v < 4 && rc == QM_OK; ++v) {
+    for (int v = 0; v < 5 && rc == QM_OK; ++v) {
         qm_tuning t = best;
+        if (v == 4) {
+            if (!lds_candidate) continue;
+            t.lds_resident = !t.lds_resident;
+        }
         if (v == 3) t.stream_hint = !t.stream_hint;
         if (v == 0) t.merge = 0;
         if (v == 1) {

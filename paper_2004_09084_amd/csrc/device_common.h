@@ -124,6 +124,53 @@ template <> struct MsgIO<_Float16> {
     }
 };
 
+// 8-bit float messages (4 exponent bits, 3 mantissa bits), converted by the
+// hardware (round to nearest even); the tag type only selects the storage.
+struct Fp8Msg {};
+template <> struct MsgIO<Fp8Msg> {
+    static constexpr uint32_t bytes = 1;
+    __device__ static __forceinline__ float at(uint32_t w, int i) {
+        switch (i) {
+            case 0: return __builtin_amdgcn_cvt_f32_fp8((int)w, 0);
+            case 1: return __builtin_amdgcn_cvt_f32_fp8((int)w, 1);
+            case 2: return __builtin_amdgcn_cvt_f32_fp8((int)w, 2);
+            default: return __builtin_amdgcn_cvt_f32_fp8((int)w, 3);
+        }
+    }
+    // two values into the low 16 bits of a word
+    __device__ static __forceinline__ uint32_t pack2(float a, float b) {
+        return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false) & 0xffffu;
+    }
+    template <int N, int AUX = 0>
+    __device__ static __forceinline__ void load(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, float (&v)[N]) {
+        if constexpr (N == 1) {
+            v[0] = at((uint32_t)__builtin_amdgcn_raw_buffer_load_b8(r, vo, so, AUX), 0);
+        } else if constexpr (N == 2) {
+            const uint32_t t = (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, vo, so, AUX);
+            v[0] = at(t, 0);
+            v[1] = at(t, 1);
+        } else {
+            const uint32_t t = __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, AUX);
+            v[0] = at(t, 0);
+            v[1] = at(t, 1);
+            v[2] = at(t, 2);
+            v[3] = at(t, 3);
+        }
+    }
+    __device__ static __forceinline__ float round(float x) { return at(pack2(x, 0.0f), 0); }
+    template <int N, int AUX = 0>
+    __device__ static __forceinline__ void store(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, const float (&v)[N]) {
+        if constexpr (N == 1) {
+            __builtin_amdgcn_raw_buffer_store_b8((uint8_t)pack2(v[0], 0.0f), r, vo, so, AUX);
+        } else if constexpr (N == 2) {
+            __builtin_amdgcn_raw_buffer_store_b16((uint16_t)pack2(v[0], v[1]), r, vo, so, AUX);
+        } else {
+            const uint32_t t = pack2(v[0], v[1]) | (pack2(v[2], v[3]) << 16);
+            __builtin_amdgcn_raw_buffer_store_b32(t, r, vo, so, AUX);
+        }
+    }
+};
+
 template <int FPL> struct LogOf;
 template <> struct LogOf<1> { static constexpr int v = 0; };
 template <> struct LogOf<2> { static constexpr int v = 1; };
@@ -134,6 +181,24 @@ typedef const __attribute__((address_space(4))) RowDesc ConstRowDesc;
 __device__ __forceinline__ ConstRowDesc *as_const(const RowDesc *p) { return (ConstRowDesc *)p; }
 
 // Per-lane context of one layer update.
+// packed frame bits: a field of esz bytes (1, 2, 4 or 8) at index i
+__device__ __forceinline__ void store_packed(uint8_t *p, int64_t i, int esz, uint64_t w) {
+    switch (esz) {
+        case 1: p[i] = (uint8_t)w; break;
+        case 2: reinterpret_cast<uint16_t *>(p)[i] = (uint16_t)w; break;
+        case 4: reinterpret_cast<uint32_t *>(p)[i] = (uint32_t)w; break;
+        default: reinterpret_cast<uint64_t *>(p)[i] = w; break;
+    }
+}
+__device__ __forceinline__ uint64_t load_packed(const uint8_t *p, int64_t i, int esz) {
+    switch (esz) {
+        case 1: return p[i];
+        case 2: return reinterpret_cast<const uint16_t *>(p)[i];
+        case 4: return reinterpret_cast<const uint32_t *>(p)[i];
+        default: return reinterpret_cast<const uint64_t *>(p)[i];
+    }
+}
+
 struct LaneCtx {
     __amdgpu_buffer_rsrc_t rA, rR, rK;
     uint32_t node;   // in-column element index of (k, first frame of the lane)

@@ -8,6 +8,8 @@
 // the row's shifts/columns are wave-uniform (scalar registers).
 #include "qcmet_internal.h"
 #include "device_common.h"
+#include "phi.h"
+#include "layer_launch.h"
 
 #include <algorithm>
 #include <cstring>
@@ -15,252 +17,6 @@
 namespace {
 
 using namespace qmdev;
-
-// ---------------------------------------------------------------------------
-// Check-node transform Phi(x) = -ln(tanh(x/2)) (Methods, step 2), float32,
-// for x already clipped to [Phi(30), 30].  Two branch-free regions:
-//   x >= 1: Phi = 2 atanh(u) with u = e^-x <= 1/e, evaluated as u * P(u^2);
-//   x <  1: Phi = ln 2 - ln x - ln(tanh(x/2)/(x/2)), evaluated as
-//           -ln2 * log2(x) + R(x^2).
-// P and R (degree 3) are least-squares fits on Chebyshev nodes of the
-// analytic functions 2 atanh(u)/u and ln 2 - ln(tanh(h)/h) (generated by
-// fit_phi_coeffs.py next to this file); the float32 result stays within
-// 1.5e-6 relative of Phi over the whole interval, most of it from rounding
-// x * log2(e) at large x.  v_exp_f32 / v_log_f32 are the hardware base-2
-// exponential and logarithm.
-// ---------------------------------------------------------------------------
-constexpr float kNegLog2e = -1.44269504088896341f;
-constexpr float kNegLn2 = -0.693147180559945309f;
-constexpr float kP0 = 1.9999992847442627f, kP1 = 0.6668428778648376f, kP2 = 0.39366233348846436f,
-                kP3 = 0.35674116015434265f;
-constexpr float kR0 = 0.6931473612785339f, kR1 = 0.0833277702331543f, kR2 = -0.0048327757976949215f,
-                kR3 = 0.00029465093393810093f;
-
-__device__ __forceinline__ float qm_phi(float x) {
-    const float u = __builtin_amdgcn_exp2f(x * kNegLog2e);
-    const float w = u * u;
-    float p = fmaf(w, kP3, kP2);
-    p = fmaf(w, p, kP1);
-    p = fmaf(w, p, kP0);
-    const float big = u * p;
-    const float y = x * x;
-    float r = fmaf(y, kR3, kR2);
-    r = fmaf(y, r, kR1);
-    r = fmaf(y, r, kR0);
-    const float small = fmaf(kNegLn2, __builtin_amdgcn_logf(x), r);
-    return x < 1.0f ? small : big;
-}
-
-// ---------------------------------------------------------------------------
-// Layer update (Methods, steps 2-3; Results: one fused kernel per layer).
-// A lane owns one check (base row i of the layer, lift k) for FPL adjacent
-// frames of a frame tile.  For each degree>=2 edge j of the row:
-//   q_j = APP[col_j][(k + a_j) mod Z] - r_j(old)                (step 3)
-//   r_j = (-1)^{s ^ xor_{j'!=j}[q_j' < 0]} Phi(clip(sum_{j'!=j} Phi(clip|q_j'|)))
-//                                                                (step 2 + flip)
-//   APP = q_j + r_j(new)                                         (step 3)
-// The degree-1 edge enters through K: its variable has this check only, so
-// its q equals its channel LLR at every visit; |K| = Phi(clip|LLR_d|) and
-// sign(K) = s ^ [LLR_d < 0] are constants.  Exclusive sums are a running
-// prefix plus a precomputed suffix (no total-minus-self).  In the last sweep
-// the degree-1 APP = LLR_d + r_d is formed from the same q's.
-// Rows of one layer share no column and distinct k of a row touch distinct
-// variables, so no two lanes of a launch touch the same APP or message.
-// D is the row's exact number of degree>=2 edges (fully unrolled body).
-// ---------------------------------------------------------------------------
-// Per-lane state of an early-terminating sweep: which of the lane's frames
-// still decode, and where the per-check degree-1 APPs go.
-template <int FPL>
-struct EtLane {
-    bool live[FPL];
-    bool all;                 // every frame of the lane is live
-    __amdgpu_buffer_rsrc_t rAd;
-};
-
-// Store FPL adjacent values, or only the live ones when a frame of the lane
-// has stopped (its state stays as it was when it stopped).
-template <typename IO, int FPL, int AUX, bool ET>
-__device__ __forceinline__ void store_live(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, const float (&v)[FPL],
-                                           const EtLane<FPL> &e) {
-    if (!ET || e.all) {
-        IO::template store<FPL, AUX>(r, vo, so, v);
-    } else {
-#pragma unroll
-        for (int f = 0; f < FPL; ++f)
-            if (e.live[f]) {
-                const float one[1] = {v[f]};
-                IO::template store<1, AUX>(r, vo + (uint32_t)f * IO::bytes, so, one);
-            }
-    }
-}
-
-template <typename MsgT, int D, int FPL, int AUX, bool ET>
-__device__ __forceinline__ void check_update(const LaneCtx &c, ConstRowDesc *rd, int last, const EtLane<FPL> &et) {
-    typedef MsgIO<MsgT> IO;
-    const uint32_t col_bytes = c.colw * 4u;
-    const uint32_t msg_col_bytes = c.colw * IO::bytes;
-    const uint32_t vo4 = c.node * 4u;
-    const uint32_t vom = c.node * IO::bytes;
-    const uint32_t row_so = (uint32_t)rd->row * col_bytes;
-    const int d1col = rd->d1col;
-    const int d1shift = rd->d1shift;
-    int sh[D > 0 ? D : 1];
-    uint32_t col_so[D > 0 ? D : 1], ent_so[D > 0 ? D : 1];
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-        sh[j] = rd->shift[j];
-        col_so[j] = (uint32_t)rd->col[j] * col_bytes;
-        ent_so[j] = (uint32_t)rd->ent[j] * msg_col_bytes;
-    }
-
-    float kap[FPL];
-    bload_f32<FPL, AUX>(c.rK, vo4, row_so, kap);
-    // sign parities are per-lane booleans (lane masks in scalar registers)
-    bool neg[FPL];
-#pragma unroll
-    for (int f = 0; f < FPL; ++f) neg[f] = (int32_t)__float_as_uint(kap[f]) < 0;
-
-    float q[D > 0 ? D : 1][FPL], ph[D > 0 ? D : 1][FPL], suf[D > 0 ? D : 1][FPL];
-    uint32_t aoff[D > 0 ? D : 1];
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-        aoff[j] = shifted_off(c, sh[j]);
-        float av[FPL], rv[FPL];
-        bload_f32<FPL>(c.rA, aoff[j], col_so[j], av);
-        IO::template load<FPL, AUX>(c.rR, vom, ent_so[j], rv);
-#pragma unroll
-        for (int f = 0; f < FPL; ++f) {
-            q[j][f] = av[f] - rv[f];
-            neg[f] = neg[f] != (q[j][f] < 0.0f);
-            ph[j][f] = qm_phi(qm_clip(fabsf(q[j][f])));
-        }
-    }
-    float acc[FPL];
-#pragma unroll
-    for (int f = 0; f < FPL; ++f) acc[f] = 0.0f;
-#pragma unroll
-    for (int j = D - 1; j >= 0; --j) {
-#pragma unroll
-        for (int f = 0; f < FPL; ++f) {
-            suf[j][f] = acc[f];
-            acc[f] += ph[j][f];
-        }
-    }
-    float pre[FPL];
-#pragma unroll
-    for (int f = 0; f < FPL; ++f) pre[f] = fabsf(kap[f]);
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-        float rm[FPL], an[FPL];
-#pragma unroll
-        for (int f = 0; f < FPL; ++f) {
-            const float S = pre[f] + suf[j][f];
-            pre[f] += ph[j][f];
-            const bool nj = neg[f] != (q[j][f] < 0.0f);
-            const float mag = qm_phi(qm_clip(S));
-            rm[f] = IO::round(nj ? -mag : mag);
-            an[f] = q[j][f] + rm[f];
-        }
-        store_live<IO, FPL, AUX, ET>(c.rR, vom, ent_so[j], rm, et);
-        store_live<MsgIO<float>, FPL, 0, ET>(c.rA, aoff[j], col_so[j], an, et);
-    }
-    if ((ET || last) && d1col >= 0) {
-        const uint32_t off = shifted_off(c, d1shift);
-        const uint32_t so = (uint32_t)d1col * col_bytes;
-        float lam[FPL], out[FPL];
-        bload_f32<FPL>(c.rA, off, so, lam);
-#pragma unroll
-        for (int f = 0; f < FPL; ++f) {
-            // neg = s ^ [lam < 0] ^ xor_j [q_j < 0]; the degree-1 target
-            // excludes only its own q (= lam): s ^ xor_j [q_j < 0]
-            const bool nd = neg[f] != (lam[f] < 0.0f);
-            const float mag = qm_phi(qm_clip(acc[f]));
-            out[f] = lam[f] + IO::round(nd ? -mag : mag);
-        }
-        // early termination: every sweep may be a frame's last, so the
-        // degree-1 APPs go to their own per-check array and A keeps LLR_d
-        if constexpr (ET) store_live<MsgIO<float>, FPL, 0, ET>(et.rAd, vo4, row_so, out, et);
-        else bstore_f32<FPL>(c.rA, off, so, out);
-    }
-}
-
-template <typename MsgT, int D, int FPL, int AUX, bool ET>
-__device__ __forceinline__ void dispatch_degree(int d, const LaneCtx &c, ConstRowDesc *rd, int last,
-                                                const EtLane<FPL> &et) {
-    if constexpr (D >= 0) {
-        if (d == D) {
-            check_update<MsgT, D, FPL, AUX, ET>(c, rd, last, et);
-            return;
-        }
-        dispatch_degree<MsgT, D - 1, FPL, AUX, ET>(d, c, rd, last, et);
-    }
-}
-
-// Thread mapping: workgroup -> (frame tile, row of the layer, chunk of
-// lanes); consecutive workgroups cycle through the frame tiles, so with 8
-// tiles each tile's lanes stay on one XCD under round-robin dispatch.
-template <typename MsgT, int MAXD, int FPL, int AUX, bool ET = false>
-__device__ __forceinline__ void layer_body(const LayerArgs &a, int b) {
-    constexpr int FPLL = LogOf<FPL>::v;
-    const int tile = b % a.ntiles;
-    if constexpr (ET) {
-        if (tile >= a.ctl[1]) return;  // every frame of the tile has stopped
-    }
-    const int rest = b / a.ntiles;
-    const int chunk = rest % a.chunks;
-    const int rs = rest / a.chunks;
-    LaneCtx c;
-    c.Z = a.Z;
-    c.ftl = a.ft_log2;
-    const int lpl = c.ftl - FPLL;  // log2(lanes per check)
-    const int idx = chunk * (int)blockDim.x + (int)threadIdx.x;
-    if (idx >= (c.Z << lpl)) return;
-    c.k = idx >> lpl;
-    c.node = ((uint32_t)c.k << c.ftl) + ((uint32_t)(idx & ((1 << lpl) - 1)) << FPLL);
-    c.colw = (uint32_t)c.Z << c.ftl;
-    c.last = a.last;
-    c.rA = make_rsrc(a.A + (int64_t)tile * a.strideA, (uint32_t)(a.strideA * 4));
-    c.rR = make_rsrc(static_cast<char *>(a.R) + (int64_t)tile * a.strideR * MsgIO<MsgT>::bytes,
-                     (uint32_t)(a.strideR * MsgIO<MsgT>::bytes));
-    c.rK = make_rsrc(a.K + (int64_t)tile * a.strideK, (uint32_t)(a.strideK * 4));
-    ConstRowDesc *rd = as_const(a.rows + rs);
-    EtLane<FPL> et;
-    if constexpr (ET) {
-        const int slot0 = (tile << c.ftl) + (int)(c.node & ((1u << c.ftl) - 1u));
-        et.all = true;
-#pragma unroll
-        for (int f = 0; f < FPL; ++f) {
-            et.live[f] = a.act[slot0 + f] != 0u;
-            et.all = et.all && et.live[f];
-        }
-        et.rAd = make_rsrc(a.Ad + (int64_t)tile * a.strideK, (uint32_t)(a.strideK * 4));
-    }
-    dispatch_degree<MsgT, MAXD, FPL, AUX, ET>(rd->d, c, rd, a.last, et);
-}
-
-template <typename MsgT, int MAXD, int FPL, int AUX>
-__global__ void __launch_bounds__(256) k_layer_sp(const LayerArgs a) {
-    layer_body<MsgT, MAXD, FPL, AUX>(a, (int)blockIdx.x);
-}
-
-// The same layer update for an early-terminating decode (see EtLane).
-template <typename MsgT, int MAXD, int FPL, int AUX>
-__global__ void __launch_bounds__(256) k_layer_sp_et(const LayerArgs a) {
-    layer_body<MsgT, MAXD, FPL, AUX, true>(a, (int)blockIdx.x);
-}
-
-// One launch for the current layer of every code of a mixed batch: the
-// workgroups of code c are [block_off[c], block_off[c+1]).  Each code
-// advances through its own layer sequence; codes never share memory.
-template <typename MsgT, int MAXD, int FPL, int AUX>
-__global__ void __launch_bounds__(256) k_layer_multi(const MultiLayerArgs m) {
-    const int b = (int)blockIdx.x;
-    int c = 0;
-#pragma unroll
-    for (int i = 1; i < QM_MAX_CODES; ++i)
-        if (i < m.ncodes && b >= m.block_off[i]) c = i;
-    layer_body<MsgT, MAXD, FPL, AUX>(m.code[c], b - m.block_off[c]);
-}
 
 // K for every check: degree-1 term of the row (or 0 if the row has none)
 // with the syndrome bit folded into its sign.
@@ -397,6 +153,82 @@ __global__ void __launch_bounds__(256) k_syndrome(const float *__restrict__ A, c
     }
     __syncthreads();
     if (tid < FT && lf[tid]) atomicOr(&fail[tile * FT + tid], 1u);
+}
+
+// Syndrome test of an early-terminating decode from packed hard decisions:
+// one lane per check and tile XORs the packed words of the row's variables
+// (PA), of its degree-1 variable (Pd) and of its syndrome bits (PS); failing
+// frames are OR-ed in LDS, then one atomic per failing frame and workgroup.
+__global__ void __launch_bounds__(256) k_syndrome_packed(const uint8_t *__restrict__ PA,
+                                                         const uint8_t *__restrict__ Pd,
+                                                         const uint8_t *__restrict__ PS, const RowDesc *rows,
+                                                         uint32_t *fail, int Z, int ftl, int mb, int chunks,
+                                                         int64_t n, int64_t m, const int32_t *ctl, int fpl) {
+    __shared__ uint32_t lm[2];
+    const int b = blockIdx.x;
+    // blocks map over the tiles that still hold decoding frames (spread over
+    // every XCD); the rest exit
+    const int nt = ctl[1];
+    if (b >= nt * mb * chunks) return;
+    const int tile = b % nt;
+    const int rest = b / nt;
+    const int chunk = rest % chunks;
+    const int rs = rest / chunks;
+    const int tid = threadIdx.x;
+    const int FT = 1 << ftl;
+    if (tid < 2) lm[tid] = 0u;
+    __syncthreads();
+    const RowDesc *rd = rows + rs;
+    const int k = chunk * (int)blockDim.x + tid;
+    if (k < Z) {
+        const int esz = qm_pack_bytes(ftl);
+        const int64_t chk = (int64_t)rd->row * Z + k;
+        uint64_t par = load_packed(PS + (int64_t)tile * m * esz, chk, esz);
+        const uint8_t *pa = PA + (int64_t)tile * n * esz;
+        for (int j = 0; j < rd->d; ++j) {
+            int v = k + rd->shift[j];
+            v = v >= Z ? v - Z : v;
+            par ^= load_packed(pa, (int64_t)rd->col[j] * Z + v, esz);
+        }
+        if (rd->d1col >= 0) par ^= load_packed(Pd + (int64_t)tile * m * esz, chk, esz);
+        if (par) {
+            atomicOr(&lm[0], (uint32_t)par);
+            atomicOr(&lm[1], (uint32_t)(par >> 32));
+        }
+    }
+    __syncthreads();
+    if (tid < FT) {
+        const int bit = qm_pack_bit(tid, ftl, fpl);
+        if ((bit < 32 ? lm[0] >> bit : lm[1] >> (bit - 32)) & 1u) atomicOr(&fail[tile * FT + tid], 1u);
+    }
+}
+
+// Packed hard decisions of every node of the tiles (bit order qm_pack_bit).
+__global__ void __launch_bounds__(256) k_pack_signs(const float *__restrict__ X, uint8_t *__restrict__ P, int64_t N,
+                                                    int ftl, int fpl) {
+    const int tile = blockIdx.y;
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= N) return;
+    const int FT = 1 << ftl;
+    const float *x = X + (((int64_t)tile * N + v) << ftl);
+    uint64_t w = 0;
+    for (int f = 0; f < FT; ++f) w |= (uint64_t)(x[f] < 0.0f) << qm_pack_bit(f, ftl, fpl);
+    store_packed(P, (int64_t)tile * N + v, qm_pack_bytes(ftl), w);
+}
+
+// Packed syndrome bits of the tiles below ctl[1] (all tiles if ctl is null).
+__global__ void __launch_bounds__(256) k_pack_syndrome(const uint8_t *__restrict__ Sil, uint8_t *__restrict__ PS,
+                                                       int64_t m, int ftl, int fpl, const int32_t *ctl,
+                                                       int after_compaction) {
+    const int tile = blockIdx.y;
+    if (ctl && (tile >= ctl[1] || (after_compaction && ctl[2] == 0))) return;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= m) return;
+    const int FT = 1 << ftl;
+    const uint8_t *sp = Sil + (((int64_t)tile * m + c) << ftl);
+    uint64_t w = 0;
+    for (int f = 0; f < FT; ++f) w |= (uint64_t)(sp[f] & 1u) << qm_pack_bit(f, ftl, fpl);
+    store_packed(PS, (int64_t)tile * m + c, qm_pack_bytes(ftl), w);
 }
 
 // ---------------------------------------------------------------------------
@@ -654,106 +486,33 @@ hipError_t qm_launch_fill_u32(uint32_t *p, uint32_t v, size_t count, hipStream_t
     return hipGetLastError();
 }
 
-namespace {
-
-// the two single-code layer kernels, for one dispatch over their variants
-struct LayerSp {
-    template <typename T, int D, int P, int H>
-    static void go(dim3 g, dim3 b, hipStream_t s, const LayerArgs &a) {
-        hipLaunchKernelGGL((k_layer_sp<T, D, P, H>), g, b, 0, s, a);
+hipError_t qm_launch_layer(const LayerArgs &a, int msgk, int maxd, int fpl, int block, int hint, hipStream_t s) {
+    switch (msgk) {
+        case QM_MSGK_F32: return qm_layer_f32(a, 0, maxd, fpl, block, hint, s);
+        case QM_MSGK_F16: return qm_layer_f16(a, 0, maxd, fpl, block, hint, s);
+        case QM_MSGK_F8: return qm_layer_f8(a, 0, maxd, fpl, block, hint, s);
+        default: return hipErrorInvalidValue;
     }
-};
-struct LayerSpEt {
-    template <typename T, int D, int P, int H>
-    static void go(dim3 g, dim3 b, hipStream_t s, const LayerArgs &a) {
-        hipLaunchKernelGGL((k_layer_sp_et<T, D, P, H>), g, b, 0, s, a);
-    }
-};
-
-template <class K, typename T, int D, int P>
-void layer_go(dim3 g, dim3 b, hipStream_t s, const LayerArgs &a, int hint) {
-    if (hint) K::template go<T, D, P, 2>(g, b, s, a);
-    else K::template go<T, D, P, 0>(g, b, s, a);
 }
 
-template <class K, typename T>
-void layer_maxd(dim3 g, dim3 b, hipStream_t s, const LayerArgs &a, int maxd, int fpl, int hint) {
-#define QM_LP(D)                                              \
-    if (fpl == 2) layer_go<K, T, D, 2>(g, b, s, a, hint);     \
-    else layer_go<K, T, D, 1>(g, b, s, a, hint);              \
-    break;
-    switch (maxd) {
-        case 2: { QM_LP(2) }
-        case 3: { QM_LP(3) }
-        case 4: { QM_LP(4) }
-        case 5: { QM_LP(5) }
-        case 6: { QM_LP(6) }
-        case 8: { QM_LP(8) }
-        default: { layer_go<K, T, 16, 1>(g, b, s, a, hint); break; }
-    }
-#undef QM_LP
-}
-
-template <class K>
-hipError_t launch_layer_t(const LayerArgs &a, int msg16, int maxd, int fpl, int block, int hint, hipStream_t s) {
-    const int64_t blocks = (int64_t)a.ntiles * a.nrows * a.chunks;
-    if (blocks == 0) return hipSuccess;
-    if (block < 64 || block > 256 || (fpl != 1 && fpl != 2) || (1 << a.ft_log2) < fpl)
-        return hipErrorInvalidConfiguration;  // the kernels are built for <= 256 lanes
-    dim3 grid((unsigned)blocks), tb((unsigned)block);
-    if (!msg16) layer_maxd<K, float>(grid, tb, s, a, maxd, fpl, hint);
-    else layer_maxd<K, _Float16>(grid, tb, s, a, maxd, fpl, hint);
-    return hipGetLastError();
-}
-
-}  // namespace
-
-hipError_t qm_launch_layer(const LayerArgs &a, int msg16, int maxd, int fpl, int block, int hint, hipStream_t s) {
-    return launch_layer_t<LayerSp>(a, msg16, maxd, fpl, block, hint, s);
-}
-
-hipError_t qm_launch_layer_et(const LayerArgs &a, int msg16, int maxd, int fpl, int block, int hint, hipStream_t s) {
+hipError_t qm_launch_layer_et(const LayerArgs &a, int msgk, int maxd, int fpl, int block, int hint, hipStream_t s) {
     if (!a.Ad || !a.act || !a.ctl) return hipErrorInvalidValue;
-    return launch_layer_t<LayerSpEt>(a, msg16, maxd, fpl, block, hint, s);
+    switch (msgk) {
+        case QM_MSGK_F32: return qm_layer_f32(a, 1, maxd, fpl, block, hint, s);
+        case QM_MSGK_F16: return qm_layer_f16(a, 1, maxd, fpl, block, hint, s);
+        case QM_MSGK_F8: return qm_layer_f8(a, 1, maxd, fpl, block, hint, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
-hipError_t qm_launch_layer_multi(const MultiLayerArgs &m, int msg16, int maxd, int fpl, int block, int hint,
+hipError_t qm_launch_layer_multi(const MultiLayerArgs &m, int msgk, int maxd, int fpl, int block, int hint,
                                  hipStream_t s) {
-    const int64_t blocks = m.block_off[m.ncodes];
-    if (blocks == 0) return hipSuccess;
-    if (block < 64 || block > 256 || (fpl != 1 && fpl != 2) || m.ncodes < 1 || m.ncodes > QM_MAX_CODES)
-        return hipErrorInvalidConfiguration;
-    for (int c = 0; c < m.ncodes; ++c)
-        if (m.block_off[c + 1] > m.block_off[c] && (1 << m.code[c].ft_log2) < fpl) return hipErrorInvalidConfiguration;
-    dim3 grid((unsigned)blocks), tb((unsigned)block);
-#define QM_L(T, D, P)                                                           \
-    do {                                                                        \
-        if (hint) hipLaunchKernelGGL((k_layer_multi<T, D, P, 2>), grid, tb, 0, s, m); \
-        else hipLaunchKernelGGL((k_layer_multi<T, D, P, 0>), grid, tb, 0, s, m);      \
-    } while (0)
-#define QM_LP(T, D)                 \
-    if (fpl == 2) QM_L(T, D, 2);    \
-    else QM_L(T, D, 1);             \
-    break;
-#define QM_LD(T)                                   \
-    switch (maxd) {                                \
-        case 2: { QM_LP(T, 2) }                    \
-        case 3: { QM_LP(T, 3) }                    \
-        case 4: { QM_LP(T, 4) }                    \
-        case 5: { QM_LP(T, 5) }                    \
-        case 6: { QM_LP(T, 6) }                    \
-        case 8: { QM_LP(T, 8) }                    \
-        default: { QM_L(T, 16, 1); break; }        \
+    switch (msgk) {
+        case QM_MSGK_F32: return qm_layer_multi_f32(m, maxd, fpl, block, hint, s);
+        case QM_MSGK_F16: return qm_layer_multi_f16(m, maxd, fpl, block, hint, s);
+        case QM_MSGK_F8: return qm_layer_multi_f8(m, maxd, fpl, block, hint, s);
+        default: return hipErrorInvalidValue;
     }
-    if (!msg16) {
-        QM_LD(float)
-    } else {
-        QM_LD(_Float16)
-    }
-#undef QM_LD
-#undef QM_LP
-#undef QM_L
-    return hipGetLastError();
 }
 
 hipError_t qm_launch_syndrome_et(const float *A, const float *Ad, const uint8_t *Sil, const RowDesc *rows, int mb,
@@ -777,6 +536,35 @@ hipError_t qm_launch_finalize(const float *A, const uint32_t *fail, float *app, 
                               int F, const TileGeom &g, hipStream_t s, const int32_t *map) {
     dim3 grid((unsigned)((g.n + 63) / 64), (unsigned)g.ntiles);
     hipLaunchKernelGGL(k_finalize, grid, dim3(256), 0, s, A, fail, app, hard, flags, F, g.n, g.ft_log2, map);
+    return hipGetLastError();
+}
+
+hipError_t qm_launch_syndrome_packed(const uint8_t *PA, const uint8_t *Pd, const uint8_t *PS, const RowDesc *rows,
+                                     int mb, uint32_t *fail, const int32_t *ctl, int fpl, const TileGeom &g,
+                                     hipStream_t s) {
+    if ((1 << g.ft_log2) > 64 || !ctl || fpl < 1) return hipErrorInvalidValue;
+    const int chunks = (g.Z + 255) / 256;
+    const int64_t blocks = (int64_t)g.ntiles * mb * chunks;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_syndrome_packed, dim3((unsigned)blocks), dim3(256), 0, s, PA, Pd, PS, rows, fail, g.Z,
+                       g.ft_log2, mb, chunks, g.n, g.m, ctl, fpl);
+    return hipGetLastError();
+}
+
+hipError_t qm_launch_pack_signs(const float *X, uint8_t *P, int64_t N, int fpl, const TileGeom &g, hipStream_t s) {
+    if ((1 << g.ft_log2) > 64 || fpl < 1) return hipErrorInvalidValue;
+    if (N == 0 || g.ntiles == 0) return hipSuccess;
+    dim3 grid((unsigned)((N + 255) / 256), (unsigned)g.ntiles);
+    hipLaunchKernelGGL(k_pack_signs, grid, dim3(256), 0, s, X, P, N, g.ft_log2, fpl);
+    return hipGetLastError();
+}
+
+hipError_t qm_launch_pack_syndrome(const uint8_t *Sil, uint8_t *PS, const int32_t *ctl, int after_compaction, int fpl,
+                                   const TileGeom &g, hipStream_t s) {
+    if ((1 << g.ft_log2) > 64 || fpl < 1) return hipErrorInvalidValue;
+    if (g.m == 0 || g.ntiles == 0) return hipSuccess;
+    dim3 grid((unsigned)((g.m + 255) / 256), (unsigned)g.ntiles);
+    hipLaunchKernelGGL(k_pack_syndrome, grid, dim3(256), 0, s, Sil, PS, g.m, g.ft_log2, fpl, ctl, after_compaction);
     return hipGetLastError();
 }
 

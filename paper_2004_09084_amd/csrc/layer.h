@@ -1,0 +1,355 @@
+// Layer kernels of the sum-product decoder (fixed sweeps, early
+// termination, fused codes), templated on the message storage type.  Each
+// layer_<type>.hip instantiates them for one type, so the three build in
+// parallel.
+#pragma once
+
+#include "qcmet_internal.h"
+#include "device_common.h"
+#include "layer_launch.h"
+#include "phi.h"
+
+namespace {
+
+using namespace qmdev;
+
+// ---------------------------------------------------------------------------
+// Layer update (Methods, steps 2-3; Results: one fused kernel per layer).
+// A lane owns one check (base row i of the layer, lift k) for FPL adjacent
+// frames of a frame tile.  For each degree>=2 edge j of the row:
+//   q_j = APP[col_j][(k + a_j) mod Z] - r_j(old)                (step 3)
+//   r_j = (-1)^{s ^ xor_{j'!=j}[q_j' < 0]} Phi(clip(sum_{j'!=j} Phi(clip|q_j'|)))
+//                                                                (step 2 + flip)
+//   APP = q_j + r_j(new)                                         (step 3)
+// The degree-1 edge enters through K: its variable has this check only, so
+// its q equals its channel LLR at every visit; |K| = Phi(clip|LLR_d|) and
+// sign(K) = s ^ [LLR_d < 0] are constants.  Exclusive sums are a running
+// prefix plus a precomputed suffix (no total-minus-self).  In the last sweep
+// the degree-1 APP = LLR_d + r_d is formed from the same q's.
+// Rows of one layer share no column and distinct k of a row touch distinct
+// variables, so no two lanes of a launch touch the same APP or message.
+// D is the row's exact number of degree>=2 edges (fully unrolled body).
+// ---------------------------------------------------------------------------
+// Per-lane state of an early-terminating sweep: which of the lane's frames
+// still decode, and where the per-check degree-1 APPs go.
+template <int FPL>
+struct EtLane {
+    bool live[FPL];
+    bool all;                 // every frame of the lane is live
+    bool leader;              // first lane of its check's lane group
+    __amdgpu_buffer_rsrc_t rAd;
+    uint8_t *PA;              // this tile's packed hard decisions per variable
+    uint8_t *Pd;              // this tile's packed degree-1 hard decisions per check
+    int lpl;                  // log2(lanes per check)
+    int esz;                  // bytes per packed field
+};
+
+// Hard decisions [v < 0] of the FT frames of this lane's check (its lane
+// group of LPC = FT/FPL lanes) as one packed word.  Bit order: frame
+// j*FPL + f of the tile (lane j of the group, its frame f) is bit f*LPC + j,
+// so the word is the group's slice of each frame's wave ballot, side by side
+// (qm_pack_bit gives the same order to every producer and reader).
+template <int FPL>
+__device__ __forceinline__ uint64_t group_signs(const float (&v)[FPL], int lpl) {
+    const int lane = (int)(threadIdx.x & 63u);
+    const int first = (lane >> lpl) << lpl;
+    const int lpc = 1 << lpl;
+    const uint64_t mask = lpc >= 64 ? ~0ull : ((1ull << lpc) - 1ull);
+    uint64_t w = 0;
+#pragma unroll
+    for (int f = 0; f < FPL; ++f) w |= ((__ballot(v[f] < 0.0f) >> first) & mask) << (f * lpc);
+    return w;
+}
+
+// Store FPL adjacent values, or only the live ones when a frame of the lane
+// has stopped (its state stays as it was when it stopped).
+template <typename IO, int FPL, int AUX, bool ET>
+__device__ __forceinline__ void store_live(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, const float (&v)[FPL],
+                                           const EtLane<FPL> &e) {
+    if (!ET || e.all) {
+        IO::template store<FPL, AUX>(r, vo, so, v);
+    } else {
+#pragma unroll
+        for (int f = 0; f < FPL; ++f)
+            if (e.live[f]) {
+                const float one[1] = {v[f]};
+                IO::template store<1, AUX>(r, vo + (uint32_t)f * IO::bytes, so, one);
+            }
+    }
+}
+
+template <typename MsgT, int D, int FPL, int AUX, bool ET>
+__device__ __forceinline__ void check_update(const LaneCtx &c, ConstRowDesc *rd, int last, const EtLane<FPL> &et) {
+    typedef MsgIO<MsgT> IO;
+    const uint32_t col_bytes = c.colw * 4u;
+    const uint32_t msg_col_bytes = c.colw * IO::bytes;
+    const uint32_t vo4 = c.node * 4u;
+    const uint32_t vom = c.node * IO::bytes;
+    const uint32_t row_so = (uint32_t)rd->row * col_bytes;
+    const int d1col = rd->d1col;
+    const int d1shift = rd->d1shift;
+    int sh[D > 0 ? D : 1];
+    uint32_t col_so[D > 0 ? D : 1], ent_so[D > 0 ? D : 1];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        sh[j] = rd->shift[j];
+        col_so[j] = (uint32_t)rd->col[j] * col_bytes;
+        ent_so[j] = (uint32_t)rd->ent[j] * msg_col_bytes;
+    }
+
+    float kap[FPL];
+    bload_f32<FPL, AUX>(c.rK, vo4, row_so, kap);
+    // sign parities are per-lane booleans (lane masks in scalar registers)
+    bool neg[FPL];
+#pragma unroll
+    for (int f = 0; f < FPL; ++f) neg[f] = (int32_t)__float_as_uint(kap[f]) < 0;
+
+    float q[D > 0 ? D : 1][FPL], ph[D > 0 ? D : 1][FPL], suf[D > 0 ? D : 1][FPL];
+    uint32_t aoff[D > 0 ? D : 1];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        aoff[j] = shifted_off(c, sh[j]);
+        float av[FPL], rv[FPL];
+        bload_f32<FPL>(c.rA, aoff[j], col_so[j], av);
+        IO::template load<FPL, AUX>(c.rR, vom, ent_so[j], rv);
+#pragma unroll
+        for (int f = 0; f < FPL; ++f) {
+            q[j][f] = av[f] - rv[f];
+            neg[f] = neg[f] != (q[j][f] < 0.0f);
+            ph[j][f] = qm_phi(qm_clip(fabsf(q[j][f])));
+        }
+    }
+    float acc[FPL];
+#pragma unroll
+    for (int f = 0; f < FPL; ++f) acc[f] = 0.0f;
+#pragma unroll
+    for (int j = D - 1; j >= 0; --j) {
+#pragma unroll
+        for (int f = 0; f < FPL; ++f) {
+            suf[j][f] = acc[f];
+            acc[f] += ph[j][f];
+        }
+    }
+    float pre[FPL];
+#pragma unroll
+    for (int f = 0; f < FPL; ++f) pre[f] = fabsf(kap[f]);
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        float rm[FPL], an[FPL];
+#pragma unroll
+        for (int f = 0; f < FPL; ++f) {
+            const float S = pre[f] + suf[j][f];
+            pre[f] += ph[j][f];
+            const bool nj = neg[f] != (q[j][f] < 0.0f);
+            const float mag = qm_phi(qm_clip(S));
+            rm[f] = IO::round(nj ? -mag : mag);
+            an[f] = q[j][f] + rm[f];
+        }
+        store_live<IO, FPL, AUX, ET>(c.rR, vom, ent_so[j], rm, et);
+        store_live<MsgIO<float>, FPL, 0, ET>(c.rA, aoff[j], col_so[j], an, et);
+        if constexpr (ET) {
+            // the variable's packed hard decisions (the last layer of the
+            // sweep that touches it leaves its end-of-sweep signs)
+            const uint64_t w = group_signs<FPL>(an, et.lpl);
+            if (et.leader) store_packed(et.PA, (int64_t)rd->col[j] * c.Z + ((aoff[j] >> 2) >> c.ftl), et.esz, w);
+        }
+    }
+    if ((ET || last) && d1col >= 0) {
+        const uint32_t off = shifted_off(c, d1shift);
+        const uint32_t so = (uint32_t)d1col * col_bytes;
+        float lam[FPL], out[FPL];
+        bload_f32<FPL>(c.rA, off, so, lam);
+#pragma unroll
+        for (int f = 0; f < FPL; ++f) {
+            // neg = s ^ [lam < 0] ^ xor_j [q_j < 0]; the degree-1 target
+            // excludes only its own q (= lam): s ^ xor_j [q_j < 0]
+            const bool nd = neg[f] != (lam[f] < 0.0f);
+            const float mag = qm_phi(qm_clip(acc[f]));
+            out[f] = lam[f] + IO::round(nd ? -mag : mag);
+        }
+        // early termination: every sweep may be a frame's last, so the
+        // degree-1 APPs go to their own per-check array and A keeps LLR_d
+        if constexpr (ET) {
+            store_live<MsgIO<float>, FPL, 0, ET>(et.rAd, vo4, row_so, out, et);
+            const uint64_t w = group_signs<FPL>(out, et.lpl);
+            if (et.leader) store_packed(et.Pd, (int64_t)rd->row * c.Z + c.k, et.esz, w);
+        } else {
+            bstore_f32<FPL>(c.rA, off, so, out);
+        }
+    }
+}
+
+template <typename MsgT, int D, int FPL, int AUX, bool ET>
+__device__ __forceinline__ void dispatch_degree(int d, const LaneCtx &c, ConstRowDesc *rd, int last,
+                                                const EtLane<FPL> &et) {
+    if constexpr (D >= 0) {
+        if (d == D) {
+            check_update<MsgT, D, FPL, AUX, ET>(c, rd, last, et);
+            return;
+        }
+        dispatch_degree<MsgT, D - 1, FPL, AUX, ET>(d, c, rd, last, et);
+    }
+}
+
+// Thread mapping: workgroup -> (frame tile, row of the layer, chunk of
+// lanes); consecutive workgroups cycle through the frame tiles, so with 8
+// tiles each tile's lanes stay on one XCD under round-robin dispatch.
+template <typename MsgT, int MAXD, int FPL, int AUX, bool ET = false>
+__device__ __forceinline__ void layer_body(const LayerArgs &a, int b) {
+    constexpr int FPLL = LogOf<FPL>::v;
+    int tile, rest;
+    if constexpr (ET) {
+        // only the leading ctl[1] tiles still hold decoding frames: the
+        // blocks map over those alone (spread over every XCD), the rest exit
+        const int nt = a.ctl[1];
+        if (b >= nt * a.nrows * a.chunks) return;
+        tile = b % nt;
+        rest = b / nt;
+    } else {
+        tile = b % a.ntiles;
+        rest = b / a.ntiles;
+    }
+    const int chunk = rest % a.chunks;
+    const int rs = rest / a.chunks;
+    LaneCtx c;
+    c.Z = a.Z;
+    c.ftl = a.ft_log2;
+    const int lpl = c.ftl - FPLL;  // log2(lanes per check)
+    const int idx = chunk * (int)blockDim.x + (int)threadIdx.x;
+    if (idx >= (c.Z << lpl)) return;
+    c.k = idx >> lpl;
+    c.node = ((uint32_t)c.k << c.ftl) + ((uint32_t)(idx & ((1 << lpl) - 1)) << FPLL);
+    c.colw = (uint32_t)c.Z << c.ftl;
+    c.last = a.last;
+    c.rA = make_rsrc(a.A + (int64_t)tile * a.strideA, (uint32_t)(a.strideA * 4));
+    c.rR = make_rsrc(static_cast<char *>(a.R) + (int64_t)tile * a.strideR * MsgIO<MsgT>::bytes,
+                     (uint32_t)(a.strideR * MsgIO<MsgT>::bytes));
+    c.rK = make_rsrc(a.K + (int64_t)tile * a.strideK, (uint32_t)(a.strideK * 4));
+    ConstRowDesc *rd = as_const(a.rows + rs);
+    EtLane<FPL> et;
+    if constexpr (ET) {
+        const int slot0 = (tile << c.ftl) + (int)(c.node & ((1u << c.ftl) - 1u));
+        et.all = true;
+#pragma unroll
+        for (int f = 0; f < FPL; ++f) {
+            et.live[f] = a.act[slot0 + f] != 0u;
+            et.all = et.all && et.live[f];
+        }
+        et.rAd = make_rsrc(a.Ad + (int64_t)tile * a.strideK, (uint32_t)(a.strideK * 4));
+        et.lpl = lpl;
+        et.leader = (idx & ((1 << lpl) - 1)) == 0;
+        et.esz = qm_pack_bytes(c.ftl);
+        et.PA = a.PA + (int64_t)tile * (a.strideA >> c.ftl) * et.esz;
+        et.Pd = a.Pd + (int64_t)tile * (a.strideK >> c.ftl) * et.esz;
+    }
+    dispatch_degree<MsgT, MAXD, FPL, AUX, ET>(rd->d, c, rd, a.last, et);
+}
+
+template <typename MsgT, int MAXD, int FPL, int AUX>
+__global__ void __launch_bounds__(256) k_layer_sp(const LayerArgs a) {
+    layer_body<MsgT, MAXD, FPL, AUX>(a, (int)blockIdx.x);
+}
+
+// The same layer update for an early-terminating decode (see EtLane).
+template <typename MsgT, int MAXD, int FPL, int AUX>
+__global__ void __launch_bounds__(256) k_layer_sp_et(const LayerArgs a) {
+    layer_body<MsgT, MAXD, FPL, AUX, true>(a, (int)blockIdx.x);
+}
+
+// One launch for the current layer of every code of a mixed batch: the
+// workgroups of code c are [block_off[c], block_off[c+1]).  Each code
+// advances through its own layer sequence; codes never share memory.
+template <typename MsgT, int MAXD, int FPL, int AUX>
+__global__ void __launch_bounds__(256) k_layer_multi(const MultiLayerArgs m) {
+    const int b = (int)blockIdx.x;
+    int c = 0;
+#pragma unroll
+    for (int i = 1; i < QM_MAX_CODES; ++i)
+        if (i < m.ncodes && b >= m.block_off[i]) c = i;
+    layer_body<MsgT, MAXD, FPL, AUX>(m.code[c], b - m.block_off[c]);
+}
+
+
+// the two single-code layer kernels, for one dispatch over their variants
+struct LayerSp {
+    template <typename T, int D, int P, int H>
+    static void go(dim3 g, dim3 b, hipStream_t s, const LayerArgs &a) {
+        hipLaunchKernelGGL((k_layer_sp<T, D, P, H>), g, b, 0, s, a);
+    }
+};
+struct LayerSpEt {
+    template <typename T, int D, int P, int H>
+    static void go(dim3 g, dim3 b, hipStream_t s, const LayerArgs &a) {
+        hipLaunchKernelGGL((k_layer_sp_et<T, D, P, H>), g, b, 0, s, a);
+    }
+};
+
+template <class K, typename T, int D, int P>
+void layer_go(dim3 g, dim3 b, hipStream_t s, const LayerArgs &a, int hint) {
+    if (hint) K::template go<T, D, P, 2>(g, b, s, a);
+    else K::template go<T, D, P, 0>(g, b, s, a);
+}
+
+template <class K, typename T>
+void layer_maxd(dim3 g, dim3 b, hipStream_t s, const LayerArgs &a, int maxd, int fpl, int hint) {
+#define QM_LP(D)                                              \
+    if (fpl == 2) layer_go<K, T, D, 2>(g, b, s, a, hint);     \
+    else layer_go<K, T, D, 1>(g, b, s, a, hint);              \
+    break;
+    switch (maxd) {
+        case 2: { QM_LP(2) }
+        case 3: { QM_LP(3) }
+        case 4: { QM_LP(4) }
+        case 5: { QM_LP(5) }
+        case 6: { QM_LP(6) }
+        case 8: { QM_LP(8) }
+        default: { layer_go<K, T, 16, 1>(g, b, s, a, hint); break; }
+    }
+#undef QM_LP
+}
+
+template <typename MsgT>
+hipError_t layer_msg(const LayerArgs &a, int et, int maxd, int fpl, int block, int hint, hipStream_t s) {
+    const int64_t blocks = (int64_t)a.ntiles * a.nrows * a.chunks;
+    if (blocks == 0) return hipSuccess;
+    if (block < 64 || block > 256 || (fpl != 1 && fpl != 2) || (1 << a.ft_log2) < fpl)
+        return hipErrorInvalidConfiguration;  // the kernels are built for <= 256 lanes
+    dim3 grid((unsigned)blocks), tb((unsigned)block);
+    if (et) layer_maxd<LayerSpEt, MsgT>(grid, tb, s, a, maxd, fpl, hint);
+    else layer_maxd<LayerSp, MsgT>(grid, tb, s, a, maxd, fpl, hint);
+    return hipGetLastError();
+}
+
+template <typename MsgT>
+hipError_t layer_multi_msg(const MultiLayerArgs &m, int maxd, int fpl, int block, int hint, hipStream_t s) {
+    const int64_t blocks = m.block_off[m.ncodes];
+    if (blocks == 0) return hipSuccess;
+    if (block < 64 || block > 256 || (fpl != 1 && fpl != 2) || m.ncodes < 1 || m.ncodes > QM_MAX_CODES)
+        return hipErrorInvalidConfiguration;
+    for (int c = 0; c < m.ncodes; ++c)
+        if (m.block_off[c + 1] > m.block_off[c] && (1 << m.code[c].ft_log2) < fpl) return hipErrorInvalidConfiguration;
+    dim3 grid((unsigned)blocks), tb((unsigned)block);
+#define QM_L(D, P)                                                                    \
+    do {                                                                              \
+        if (hint) hipLaunchKernelGGL((k_layer_multi<MsgT, D, P, 2>), grid, tb, 0, s, m); \
+        else hipLaunchKernelGGL((k_layer_multi<MsgT, D, P, 0>), grid, tb, 0, s, m);      \
+    } while (0)
+#define QM_LP(D)                \
+    if (fpl == 2) QM_L(D, 2);   \
+    else QM_L(D, 1);            \
+    break;
+    switch (maxd) {
+        case 2: { QM_LP(2) }
+        case 3: { QM_LP(3) }
+        case 4: { QM_LP(4) }
+        case 5: { QM_LP(5) }
+        case 6: { QM_LP(6) }
+        case 8: { QM_LP(8) }
+        default: { QM_L(16, 1); break; }
+    }
+#undef QM_LP
+#undef QM_L
+    return hipGetLastError();
+}
+
+}  // namespace

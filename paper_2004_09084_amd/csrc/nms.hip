@@ -21,6 +21,9 @@ namespace {
 
 using namespace qmdev;
 
+// bound of the reverse-sweep adjoints (dLoss/dAPP, dLoss/dr)
+constexpr float kAdjointMax = 1e30f;
+
 constexpr float kInf = __builtin_inff();
 
 typedef const __attribute__((address_space(4))) float ConstF;
@@ -460,6 +463,9 @@ __device__ __forceinline__ void check_nms_bwd(const LaneCtx &c, ConstRowDesc *rd
             float g = gq[j][f];
             if (pos[j] == mn[f].p1) g += G1[f] * dabs(q[j][f]);
             if (pos[j] == mn[f].p2) g += G2[f] * dabs(q[j][f]);
+            // adjoints can grow geometrically over many reverse sweeps; bound
+            // them well inside float32 so that no inf (and no inf - inf) arises
+            g = fminf(fmaxf(g, -kAdjointMax), kAdjointMax);
             ga[f] = g;
             gro[f] = -g;
         }
@@ -522,11 +528,14 @@ __global__ void k_grad_reduce(const float *part, float *grad, int T, int mb, int
 
 // Adam (Kingma & Ba): m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
 // w -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)
+// A non-finite gradient component counts as 0 and |g| is capped at 1e15 so
+// that g^2 stays finite (Adam's step depends on g only through m / sqrt(v)).
 __global__ void k_adam(float *w, const float *g, float *m, float *v, int n, float lr, float b1, float b2, float eps,
                        float c1, float c2) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const float gi = g[i];
+    float gi = g[i];
+    gi = __builtin_isfinite(gi) ? fminf(fmaxf(gi, -1e15f), 1e15f) : 0.0f;
     const float mi = b1 * m[i] + (1.0f - b1) * gi;
     const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
     m[i] = mi;

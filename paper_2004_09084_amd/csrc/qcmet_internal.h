@@ -25,6 +25,7 @@ struct RowDesc {
     int32_t col[QM_MAXD];     // degree>=2 columns, ascending
     int32_t shift[QM_MAXD];   // their shifts
     int32_t ent[QM_MAXD];     // index of the entry among all degree>=2 entries (message slot)
+    int32_t lcol[QM_MAXD];    // rank of the column among the degree>=2 columns (LDS-resident decode)
 };
 
 // Device-side layout of one code's frames ("frame tiles"): frames are
@@ -58,7 +59,20 @@ struct LayerArgs {
     float *Ad;                // [ntiles][m][FT]
     const uint32_t *act;      // [Fpad] 1 = frame slot still decoding
     const int32_t *ctl;       // EtCtl
+    uint8_t *PA;              // [ntiles][n] hard decisions of the FT frames of a variable (bit = frame),
+                              // max(FT, 8) bits each
+    uint8_t *Pd;              // [ntiles][m] the same for the degree-1 variable of each check
 };
+
+// bytes of one packed field of FT = 2^ft_log2 frame bits
+__host__ __device__ inline int qm_pack_bytes(int ft_log2) { return ft_log2 <= 3 ? 1 : (1 << (ft_log2 - 3)); }
+// bit of frame fl of a tile in a packed field, with fpl frames per lane:
+// frame j*fpl + f (lane j of the check's lane group, its frame f) sits at
+// bit f*(FT/fpl) + j
+__host__ __device__ inline int qm_pack_bit(int fl, int ft_log2, int fpl) {
+    const int lpc = (1 << ft_log2) / fpl;
+    return (fl % fpl) * lpc + fl / fpl;
+}
 
 // Device-side control words of an early-terminating decode of one code.
 //   [0] nact: slots >= nact hold stopped frames
@@ -69,6 +83,20 @@ struct LayerArgs {
 // Largest padded frame count of one code in an early-terminating decode
 // (the planning kernel keeps per-slot state in LDS).
 #define QM_ET_MAXF 8192
+
+// One code decoded with its degree>=2 APPs resident in LDS: one workgroup
+// per frame runs every sweep, layers separated by workgroup barriers.
+// Frame-major layout (frame tiles of one frame).
+struct LdsArgs {
+    float *A;                 // [F][n]  APP (degree>=2 cols), LLR/APP (degree-1 cols)
+    void *R;                  // [F][nent1*Z] messages
+    const float *K;           // [F][m]  degree-1 terms
+    const RowDesc *rows;      // all rows, schedule order
+    const int32_t *gptr;      // [G+1] layer boundaries
+    const int32_t *cols1;     // [ncols1] degree>=2 block columns, in LDS order
+    int32_t G, Z, T, ncols1;
+    int64_t n, m, nr;         // per-frame elements of A, K, R
+};
 
 // Codes one decoder can mix in a single fused launch.
 #define QM_MAX_CODES 4
@@ -108,17 +136,38 @@ hipError_t qm_launch_to_tiles_u8(const uint8_t *in, uint8_t *out, int F, int64_t
 hipError_t qm_launch_kappa(const float *A, const uint8_t *Sil, float *K, const RowDesc *rows,
                            int mb, const TileGeom &g, hipStream_t s);
 hipError_t qm_launch_fill_u32(uint32_t *p, uint32_t v, size_t count, hipStream_t s);
-hipError_t qm_launch_layer(const LayerArgs &a, int msg16, int maxd, int fpl, int block, int hint, hipStream_t s);
-hipError_t qm_launch_layer_multi(const MultiLayerArgs &m, int msg16, int maxd, int fpl, int block, int hint,
+// message storage kinds (msgk)
+#define QM_MSGK_F32 0
+#define QM_MSGK_F16 1
+#define QM_MSGK_F8 2
+hipError_t qm_launch_layer(const LayerArgs &a, int msgk, int maxd, int fpl, int block, int hint, hipStream_t s);
+hipError_t qm_launch_layer_multi(const MultiLayerArgs &m, int msgk, int maxd, int fpl, int block, int hint,
                                  hipStream_t s);
 hipError_t qm_launch_syndrome(const float *A, const float *Ad, const uint8_t *Sil, const RowDesc *rows, int mb,
                               uint32_t *fail, const TileGeom &g, hipStream_t s);
 hipError_t qm_launch_finalize(const float *A, const uint32_t *fail, float *app, uint8_t *hard,
                               uint8_t *flags, int F, const TileGeom &g, hipStream_t s, const int32_t *map = nullptr);
+// LDS-resident decode (lds_sweeps.hip): all T sweeps of F frames in one
+// launch; bytes of LDS it needs per workgroup, and the launch.
+size_t qm_lds_bytes(int ncols1, int Z);
+hipError_t qm_launch_sweeps_lds(const LdsArgs &a, int F, int msgk, int maxd, hipStream_t s);
 // early termination (kernels.hip)
-hipError_t qm_launch_layer_et(const LayerArgs &a, int msg16, int maxd, int fpl, int block, int hint, hipStream_t s);
+hipError_t qm_launch_layer_et(const LayerArgs &a, int msgk, int maxd, int fpl, int block, int hint, hipStream_t s);
 hipError_t qm_launch_syndrome_et(const float *A, const float *Ad, const uint8_t *Sil, const RowDesc *rows, int mb,
                                  uint32_t *fail, const int32_t *ctl, const TileGeom &g, hipStream_t s);
+// Syndrome test from packed hard decisions (early termination): per check,
+// the row's variables' words of PA, the check's word of Pd and the syndrome
+// bytes; tiles at or past ctl[1] are skipped.
+hipError_t qm_launch_syndrome_packed(const uint8_t *PA, const uint8_t *Pd, const uint8_t *PS, const RowDesc *rows,
+                                     int mb, uint32_t *fail, const int32_t *ctl, int fpl, const TileGeom &g,
+                                     hipStream_t s);
+// Packed hard decisions of every frame tile: bit qm_pack_bit(fl) of
+// P[tile][node] = [X[tile][node][fl] < 0].
+hipError_t qm_launch_pack_signs(const float *X, uint8_t *P, int64_t N, int fpl, const TileGeom &g, hipStream_t s);
+// Packed syndrome bits (same order) of the tiles below ctl[1]; with
+// after_compaction, only when the planning kernel moved frames (ctl[2] != 0).
+hipError_t qm_launch_pack_syndrome(const uint8_t *Sil, uint8_t *PS, const int32_t *ctl, int after_compaction, int fpl,
+                                   const TileGeom &g, hipStream_t s);
 hipError_t qm_launch_et_init(uint32_t *act, int32_t *map, int32_t *iters, int32_t *ctl, int Fpad, int ntiles,
                              hipStream_t s);
 hipError_t qm_launch_et_plan(uint32_t *fail, uint32_t *act, int32_t *map, int32_t *perm, int32_t *iters,

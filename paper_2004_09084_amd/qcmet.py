@@ -29,6 +29,7 @@ QM_ERR_STATE = -9
 
 QM_MSG_FP32 = 0x0
 QM_MSG_FP16 = 0x1
+QM_MSG_FP8 = 0x2
 QM_VALIDATE = 0x4
 QM_GRAPH = 0x8
 QM_EARLY_STOP = 0x10
@@ -62,12 +63,13 @@ class qm_tuning(ctypes.Structure):
     _fields_ = [("frames_per_tile", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("merge", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("frames_per_lane", ctypes.c_int32), ("fuse_codes", ctypes.c_int32),
-                ("stream_hint", ctypes.c_int32)]
+                ("stream_hint", ctypes.c_int32), ("lds_resident", ctypes.c_int32)]
 
 
 class qm_profile(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int32), ("sweeps", ctypes.c_int32), ("layer_ms", ctypes.c_double),
-                ("sweep_ms", ctypes.c_double), ("layer_bytes", ctypes.c_double), ("checks", ctypes.c_double)]
+                ("sweep_ms", ctypes.c_double), ("layer_bytes", ctypes.c_double), ("checks", ctypes.c_double),
+                ("lds_launches", ctypes.c_int32), ("lds_ms", ctypes.c_double), ("lds_bytes", ctypes.c_double)]
 
 
 _lib = None
@@ -206,8 +208,8 @@ def qm_decoder_bind_workspace(dec, ws) -> None:
 
 
 def qm_decoder_set_tuning(dec, frames_per_tile=0, block=0, merge=1, graph=0, frames_per_lane=0, fuse_codes=1,
-                          stream_hint=1) -> None:
-    t = qm_tuning(frames_per_tile, block, merge, graph, frames_per_lane, fuse_codes, stream_hint)
+                          stream_hint=1, lds_resident=0) -> None:
+    t = qm_tuning(frames_per_tile, block, merge, graph, frames_per_lane, fuse_codes, stream_hint, lds_resident)
     _check(lib().qm_decoder_set_tuning(dec, ctypes.byref(t)))
 
 

@@ -41,6 +41,15 @@ def plain_minsum_weights(T, mb, device="cuda"):
     return w
 
 
+def extend_weights(w, T):
+    """Weights for T sweeps: sweeps past the trained ones reuse the last."""
+    import torch
+    if w.shape[0] >= T:
+        return w[:T].contiguous()
+    tail = w[-1:].expand(T - w.shape[0], *w.shape[1:])
+    return torch.cat([w, tail], dim=0).contiguous()
+
+
 def train(spec, shifts, steps=2000, frames=16, T=100, lr=1e-3, snrs=(0.161, 0.15), seed=0, log_every=100,
           weights=None, log=print):
     import torch
@@ -149,7 +158,10 @@ def main():
     ap.add_argument("--spec", default="r0.1_Z20000")
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--frames", type=int, default=16)
-    ap.add_argument("--T", type=int, default=100)
+    ap.add_argument("--T", type=int, default=100, help="min-sum sweeps at evaluation")
+    ap.add_argument("--T-train", type=int, default=None,
+                    help="unrolled sweeps while training (default T); later sweeps reuse the last trained sweep's "
+                         "weights")
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--eval-frames", type=int, default=128)
@@ -164,13 +176,15 @@ def main():
     if args.load:
         w0 = torch.from_numpy(np.load(args.load)).cuda()
     w = w0
+    T_train = args.T_train or args.T
     if args.steps > 0:
-        w, hist, secs = train(spec, shifts, steps=args.steps, frames=args.frames, T=args.T, lr=args.lr,
-                              seed=args.seed, weights=w0)
-        print(json.dumps({"trained_steps": args.steps, "train_seconds": round(secs, 1),
+        w, hist, secs = train(spec, shifts, steps=args.steps, frames=args.frames, T=T_train, lr=args.lr,
+                              seed=args.seed, weights=None if w0 is None else w0[:T_train].contiguous())
+        print(json.dumps({"trained_steps": args.steps, "T_train": T_train, "train_seconds": round(secs, 1),
                           "loss_first": hist[0][1], "loss_last": hist[-1][1]}), flush=True)
     if w is None:
         w = plain_minsum_weights(args.T, spec.mb)
+    w = extend_weights(w, args.T)
     if args.save:
         np.save(args.save, w.cpu().numpy())
     for snr in [float(s) for s in args.eval_snrs.split(",") if s]:

@@ -71,7 +71,7 @@ def test_early_matches_oracle(fp16):
             assert r["bits_diff"] == 0 and r["app_viol"] == 0, r
 
 
-@pytest.mark.parametrize("ft", [4, 16])
+@pytest.mark.parametrize("ft", [1, 4, 16, 32, 64])
 def test_early_frames_equal_fixed_decodes(ft):
     # 64 frames at a waterfall SNR: frames stop after 3 to 6 sweeps or never,
     # so tiles empty at several sweeps and frames are compacted several times

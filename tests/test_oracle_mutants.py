@@ -30,6 +30,8 @@ MUTANTS = {
     "gradient_through_saturation": ("mu = QO_X_HI;\n        best = -1;", "mu = QO_X_HI;"),
     "early_stop_counts_late": ("used = t + 1;\n        for (int g = 0; g < x->G; g++) {", "used = t + 2;\n        for (int g = 0; g < x->G; g++) {"),
     "early_stop_one_sweep_late": ("if (x->early_stop && hard_and_check(c, app, s, hard)) break;", "if (x->early_stop && t > 0 && hard_and_check(c, app, s, hard)) break;"),
+    "e4m3_one_bit_short": ("int qe = e - 4;", "int qe = e - 3;"),
+    "e4m3_no_subnormals": ("if (qe < -9) qe = -9;", "if (qe < -6) qe = -6;"),
     "loss_sign": ("gA[v] = -sg * sigmoid(-sg * app[v]);", "gA[v] = sg * sigmoid(-sg * app[v]);"),
 }
 

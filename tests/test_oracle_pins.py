@@ -59,6 +59,24 @@ def test_round_half_matches_numpy_float16():
     assert np.array_equal(np.signbit(got), np.signbit(ref))
 
 
+def test_round_e4m3_matches_torch_float8():
+    # torch's float8_e4m3fn conversion (round to nearest even) is an
+    # implementation independent of the oracle's
+    import torch
+    rng = np.random.default_rng(7)
+    grid = torch.arange(256, dtype=torch.uint8).view(torch.float8_e4m3fn).to(torch.float64).numpy()
+    g = np.unique(np.abs(grid[np.isfinite(grid)]))
+    mids = (g[1:] + g[:-1]) / 2                      # exact ties
+    v = np.concatenate([g, -g, mids, -mids, rng.normal(0, 8, 3000), rng.uniform(-30, 30, 3000),
+                        rng.normal(0, 1e-2, 1000), np.geomspace(1e-5, 440, 500), [0.0, -0.0, 30.0, 448.0]])
+    v = v.astype(np.float32).astype(np.float64)
+    ref = torch.from_numpy(v.astype(np.float32)).to(torch.float8_e4m3fn).to(torch.float64).numpy()
+    got = np.array([oracle.round_e4m3(a) for a in v])
+    assert np.array_equal(got, ref)
+    assert np.array_equal(np.signbit(got), np.signbit(ref))
+    assert oracle.round_e4m3(1000.0) == 448.0
+
+
 # ------------------------------------------------------------ schedule --
 
 def test_greedy_merge_reproduces_paper_examples():
@@ -113,6 +131,20 @@ def test_single_check_fp16_messages_round_to_binary16():
         r = 2.0 * np.arctanh(np.prod(np.tanh(np.delete(l64, j) / 2.0)))
         r16 = float(np.float64(r).astype(np.float16))
         assert abs(app[0, j] - (l64[j] + r16)) <= 1e-12
+
+
+def test_single_check_fp8_messages_round_to_e4m3():
+    import torch
+    rng = np.random.default_rng(3)
+    d = 5
+    H = np.zeros((1, d), dtype=np.int32)
+    llr = rng.normal(0, 2.0, d).astype(np.float32)
+    app, _, _, _ = oracle.decode_sp(H, 1, llr[None], np.ones((1, 1), np.uint8), 1, fp8_messages=True)
+    l64 = llr.astype(np.float64)
+    for j in range(d):
+        r = -2.0 * np.arctanh(np.prod(np.tanh(np.delete(l64, j) / 2.0)))
+        r8 = float(torch.tensor([r], dtype=torch.float64).to(torch.float8_e4m3fn).to(torch.float64)[0])
+        assert abs(app[0, j] - (l64[j] + r8)) <= 1e-12
 
 
 def _cycle_code(nb, Z, rng):

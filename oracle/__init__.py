@@ -47,6 +47,8 @@ def _load(path: str):
     L.qo_decode_sp.argtypes = [i32, i32, i32, p, i32, p, p, i32, p, p, i32, i32, p, p, p, i32]
     L.qo_decode_sp_early.restype = i32
     L.qo_decode_sp_early.argtypes = [i32, i32, i32, p, i32, p, p, i32, p, p, i32, i32, p, p, p, p, i32]
+    L.qo_decode_flood.restype = i32
+    L.qo_decode_flood.argtypes = [i32, i32, i32, p, i32, p, p, i32, i32, p, p, p, i32]
     L.qo_nms_decode.restype = i32
     L.qo_nms_decode.argtypes = [i32, i32, i32, p, i32, p, p, i32, p, p, i32, p, p, i32,
                                 p, p, p, p, i32]
@@ -192,6 +194,22 @@ def decode_sp_early(shifts, Z, llr, syn, T, schedule=None, fp16_messages=False, 
     if rc <= 0:
         raise RuntimeError(f"qo_decode_sp_early failed: {rc}")
     return app, hard, flags, iters
+
+
+def decode_flood(shifts, Z, llr, syn, T, fp16_messages=False, threads=0, fp8_messages=False):
+    """Flooding-schedule sum-product in FP64.  Returns (app, hard, flags,
+    threads_used)."""
+    sh, mb, nb, n, m, L, S, gp, rw = _prep(shifts, Z, llr, syn, None)
+    F = L.shape[0]
+    app = np.empty((F, n), dtype=np.float64)
+    hard = np.empty((F, n), dtype=np.uint8)
+    flags = np.empty(F, dtype=np.uint8)
+    rc = lib().qo_decode_flood(mb, nb, Z, _ptr(sh), F, _ptr(L), _ptr(S), int(T),
+                               _msg_mode(fp16_messages, fp8_messages), _ptr(app), _ptr(hard), _ptr(flags),
+                               int(threads))
+    if rc <= 0:
+        raise RuntimeError(f"qo_decode_flood failed: {rc}")
+    return app, hard, flags, rc
 
 
 def nms_decode(shifts, Z, llr, syn, T, alpha, beta, early_stop=False, schedule=None, threads=0):

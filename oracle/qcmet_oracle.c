@@ -35,6 +35,9 @@
  *   qo_decode_sp_early The same with early termination (Results, Table
  *                     tabearly): a frame stops at the first sweep count
  *                     whose hard decisions satisfy the syndrome.
+ *   qo_decode_flood   Flooding schedule of the same sum-product update:
+ *                     every check of an iteration reads the previous
+ *                     iteration's APPs; then APP = LLR + sum of messages.
  *   qo_nms_*          Normalised/offset min-sum variant of the same layered
  *                     sweep (a learned decoder that is not in the paper):
  *                     r = sign * alpha[t][row][type] * max(min(min|q|, 30) - beta, 0);
@@ -376,6 +379,81 @@ int qo_decode_sp_early(int mb, int nb, int Z, const int *sh, int G, const int *g
     if (rc) { code_free(&c); return rc; }
     sp_ctx x = {&c, G, gptr, rows, llr, syn, T, mode, 1, app, hard, flags, iters, 0};
     int used = F > 0 ? run_frames(sp_frame, &x, F, nthreads) : 0;
+    code_free(&c);
+    return x.err ? x.err : (used > 0 ? used : 1);
+}
+
+/* ------------------------------------------------ flooding schedule -- */
+
+/* Flooding sum-product (the schedule the paper sets layered decoding
+ * against; Methods, steps 2-4 with every check of an iteration reading the
+ * same APPs): per iteration, every check computes its new messages from
+ * q = APP - r_old with the APPs of the previous iteration (step 2 rule,
+ * syndrome flip, clip), then every variable takes APP = LLR + the sum of its
+ * incoming messages, added in ascending check order.  The result does not
+ * depend on the row order.  Outputs as qo_decode_sp. */
+typedef struct {
+    const code_t *c;
+    const float *llr; const uint8_t *syn;
+    int T, mode;
+    double *app; uint8_t *hard, *flags;
+    int err;
+} flood_ctx;
+
+static void flood_frame(void *vctx, int f) {
+    flood_ctx *x = (flood_ctx *)vctx;
+    const code_t *c = x->c;
+    const int n = c->n, m = c->m;
+    const float *llr = x->llr + (size_t)f * n;
+    const uint8_t *s = x->syn + (size_t)f * m;
+    double *app = x->app + (size_t)f * n;
+    size_t E = (size_t)(c->E > 0 ? c->E : 1);
+    double *r = (double *)calloc(E, sizeof(double));
+    double *rn = (double *)malloc(sizeof(double) * E);
+    double *q = (double *)malloc(sizeof(double) * (size_t)(c->maxdeg + 1));
+    double *ph = (double *)malloc(sizeof(double) * (size_t)(c->maxdeg + 1));
+    if (!r || !rn || !q || !ph) { x->err = -1; free(r); free(rn); free(q); free(ph); return; }
+    for (int v = 0; v < n; v++) app[v] = (double)llr[v];
+    for (int t = 0; t < x->T; t++) {
+        /* every check from the same APPs */
+        for (int chk = 0; chk < m; chk++) {
+            int e0 = c->chk_ptr[chk], d = c->chk_ptr[chk + 1] - e0;
+            for (int a = 0; a < d; a++) {
+                q[a] = app[c->chk_vn[e0 + a]] - r[e0 + a];
+                ph[a] = qo_phi(qo_clip(fabs(q[a])));
+            }
+            for (int a = 0; a < d; a++) {
+                double S = 0.0;
+                int neg = s[chk] & 1;
+                for (int b = 0; b < d; b++) {
+                    if (b == a) continue;
+                    S += ph[b];
+                    neg ^= (q[b] < 0.0);
+                }
+                double mag = qo_phi(qo_clip(S));
+                double v = neg ? -mag : mag;
+                if (x->mode == 1) v = qo_round_half(v);
+                else if (x->mode == 2) v = qo_round_e4m3(v);
+                rn[e0 + a] = v;
+            }
+        }
+        /* every variable: LLR plus its messages, ascending check order */
+        for (size_t e = 0; e < (size_t)c->E; e++) r[e] = rn[e];
+        for (int v = 0; v < n; v++) app[v] = (double)llr[v];
+        for (size_t e = 0; e < (size_t)c->E; e++) app[c->chk_vn[e]] += r[e];
+    }
+    x->flags[f] = (uint8_t)hard_and_check(c, app, s, x->hard + (size_t)f * n);
+    free(r); free(rn); free(q); free(ph);
+}
+
+int qo_decode_flood(int mb, int nb, int Z, const int *sh, int F, const float *llr, const uint8_t *syn, int T,
+                    int mode, double *app, uint8_t *hard, uint8_t *flags, int nthreads) {
+    if (mb <= 0 || nb <= 0 || Z <= 0 || F < 0 || T < 0 || mode < 0 || mode > 2) return -1;
+    code_t c;
+    int rc = code_build(&c, mb, nb, Z, sh);
+    if (rc) { code_free(&c); return rc; }
+    flood_ctx x = {&c, llr, syn, T, mode, app, hard, flags, 0};
+    int used = F > 0 ? run_frames(flood_frame, &x, F, nthreads) : 0;
     code_free(&c);
     return x.err ? x.err : (used > 0 ? used : 1);
 }

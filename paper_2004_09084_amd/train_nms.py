@@ -77,7 +77,9 @@ def train(spec, shifts, steps=2000, frames=16, T=100, lr=1e-3, snrs=(0.161, 0.15
         if step % log_every == 0 or step == 1 or step == steps:
             lv = float(loss.item())
             history.append((step, lv))
-            log(json.dumps({"step": step, "loss": round(lv, 6), "elapsed_s": round(time.perf_counter() - t0, 1)}))
+            log(json.dumps({"step": step, "loss": round(lv, 6), "grad_norm": float(grad.norm().item()),
+                            "alpha_mean": float(w[..., 0].mean().item()), "beta_mean": float(w[..., 1].mean().item()),
+                            "elapsed_s": round(time.perf_counter() - t0, 1)}))
     torch.cuda.synchronize()
     return w, history, time.perf_counter() - t0
 

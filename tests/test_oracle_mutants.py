@@ -32,6 +32,10 @@ MUTANTS = {
     "early_stop_one_sweep_late": ("if (x->early_stop && hard_and_check(c, app, s, hard)) break;", "if (x->early_stop && t > 0 && hard_and_check(c, app, s, hard)) break;"),
     "e4m3_one_bit_short": ("int qe = e - 4;", "int qe = e - 3;"),
     "e4m3_no_subnormals": ("if (qe < -9) qe = -9;", "if (qe < -6) qe = -6;"),
+    "flood_fresh_app": ("for (size_t e = 0; e < (size_t)c->E; e++) r[e] = rn[e];\n        for (int v = 0; v < n; v++) app[v] = (double)llr[v];",
+                        "for (size_t e = 0; e < (size_t)c->E; e++) r[e] = rn[e];\n        for (int v = 0; v < n; v++) app[v] = 0.0;"),
+    "flood_drops_old_message": ("q[a] = app[c->chk_vn[e0 + a]] - r[e0 + a];\n                ph[a] = qo_phi(qo_clip(fabs(q[a])));\n            }\n            for (int a = 0; a < d; a++) {\n                double S = 0.0;\n                int neg = s[chk] & 1;",
+                                "q[a] = app[c->chk_vn[e0 + a]];\n                ph[a] = qo_phi(qo_clip(fabs(q[a])));\n            }\n            for (int a = 0; a < d; a++) {\n                double S = 0.0;\n                int neg = s[chk] & 1;"),
     "loss_sign": ("gA[v] = -sg * sigmoid(-sg * app[v]);", "gA[v] = sg * sigmoid(-sg * app[v]);"),
 }
 

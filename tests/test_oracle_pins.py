@@ -367,6 +367,82 @@ def test_sp_early_stop_zero_noise_stops_at_zero():
     assert np.all(iters == 0) and np.all(flags == 1) and np.array_equal(hard, X)
 
 
+def test_flood_single_check_is_the_tanh_rule():
+    rng = np.random.default_rng(31)
+    d = 4
+    H = np.zeros((1, d), dtype=np.int32)
+    llr = rng.normal(0, 2.0, d).astype(np.float32)
+    app, _, _, _ = oracle.decode_flood(H, 1, llr[None], np.array([[1]], np.uint8), 1)
+    l64 = llr.astype(np.float64)
+    for j in range(d):
+        r = -2.0 * np.arctanh(np.prod(np.tanh(np.delete(l64, j) / 2.0)))
+        assert abs(app[0, j] - (l64[j] + r)) <= 1e-12 * max(1.0, abs(r))
+
+
+def test_flood_tree_lift_gives_exact_map():
+    rng = np.random.default_rng(32)
+    done = 0
+    for trial in range(8):
+        base = random_tree_base(rng, n_rows=int(rng.integers(2, 5)), max_new=2)
+        Z = 2
+        H = lift(base, Z, rng)
+        if H.shape[1] * Z > 16:
+            continue
+        Hd = dense_H(H, Z)
+        x = rng.integers(0, 2, Hd.shape[1]).astype(np.uint8)
+        llr, s = frame_for(Hd, x, 0.5, rng)
+        ref = map_llr(Hd, s, llr)
+        app, _, _, _ = oracle.decode_flood(H, Z, llr[None], s[None], 12)
+        assert np.max(np.abs(app[0] - ref)) < 1e-9, trial
+        done += 1
+    assert done >= 3
+
+
+def test_flood_does_not_depend_on_row_order():
+    # every check of an iteration reads the same APPs, so permuting the base
+    # rows changes only the order of the final additions (layered decoding,
+    # by contrast, depends on the row order)
+    H = W.make_code(W.RATE01_SMALL, 0)
+    Z = W.RATE01_SMALL.Z
+    X, L, S = W.make_frames(H, Z, 0.161, 2, seed=33)
+    perm = np.random.default_rng(34).permutation(H.shape[0])
+    Hp = H[perm]
+    Sp = S.reshape(2, H.shape[0], Z)[:, perm].reshape(2, -1)
+    a1, h1, f1, _ = oracle.decode_flood(H, Z, L, S, 6)
+    a2, h2, f2, _ = oracle.decode_flood(Hp, Z, L, Sp, 6)
+    assert np.max(np.abs(a1 - a2) / np.maximum(np.abs(a1), 1.0)) < 1e-12
+    assert np.array_equal(h1, h2) and np.array_equal(f1, f2)
+    l1, _, _, _ = oracle.decode_sp(H, Z, L, S, 6)
+    l2, _, _, _ = oracle.decode_sp(Hp, Z, L, Sp, 6)
+    assert np.max(np.abs(l1 - l2)) > 1.0
+
+
+def test_flood_equals_layered_when_rows_share_no_variable():
+    # each variable in a single check: one flooding iteration and one
+    # layered sweep perform the same updates
+    rng = np.random.default_rng(35)
+    Z = 8
+    H = np.full((3, 7), -1, dtype=np.int32)
+    H[0, 0:3] = rng.integers(0, Z, 3)
+    H[1, 3:5] = rng.integers(0, Z, 2)
+    H[2, 5:7] = rng.integers(0, Z, 2)
+    Hd = dense_H(H, Z)
+    x = rng.integers(0, 2, 7 * Z).astype(np.uint8)
+    llr, s = frame_for(Hd, x, 1.0, rng)
+    for T in (1, 3):
+        af, hf, ff, _ = oracle.decode_flood(H, Z, llr[None], s[None], T)
+        al, hl, fl, _ = oracle.decode_sp(H, Z, llr[None], s[None], T)
+        assert np.max(np.abs(af - al)) < 1e-12 and np.array_equal(hf, hl)
+
+
+def test_flood_zero_noise_decodes_to_truth():
+    H = W.make_code(W.RATE01_SMALL, 0)
+    Z = W.RATE01_SMALL.Z
+    X, L, S = W.make_frames(H, Z, 0.161, 2, seed=36, zero_noise=True)
+    _, hard, flags, _ = oracle.decode_flood(H, Z, L, S, 3)
+    assert flags.all() and np.array_equal(hard, X)
+
+
 def _fd_setup():
     spec = W.RATE01_SMALL.with_Z(8)
     H = W.make_code(spec, 0)

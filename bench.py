@@ -99,6 +99,7 @@ def main():
     ap.add_argument("--tuning", default=None, help="JSON dict of qm_tuning fields")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--flooding", action="store_true", help="flooding schedule instead of layers")
     ap.add_argument("--early-stop", action="store_true",
                     help="qm_decode_early: frames stop once H c = s (iterations = the maximum)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -136,7 +137,7 @@ def main():
     codes = [Q.Code(w.shifts, spec.Z) for w, spec in zip(wls, specs)]
     tuning = json.loads(args.tuning) if args.tuning else None
     flags = (Q.QM_MSG_FP16 if args.fp16 else 0) | (Q.QM_MSG_FP8 if args.fp8 else 0) \
-        | (Q.QM_EARLY_STOP if args.early_stop else 0)
+        | (Q.QM_EARLY_STOP if args.early_stop else 0) | (Q.QM_FLOODING if args.flooding else 0)
     msg_name = "FP16" if args.fp16 else "FP8 (e4m3)" if args.fp8 else "FP32"
     dec = Q.Decoder(codes, Fs, flags=flags, tuning=tuning)
     out = dec.alloc_outputs(want_app=True)
@@ -221,7 +222,8 @@ def main():
             traffic = None
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                    "kernel": "k_layer_sp_et" if args.early_stop else "k_layer_sp",
+                    "kernel": "k_layer_sp_et" if args.early_stop
+                              else "k_layer_flood + k_flood_vars (one iteration)" if args.flooding else "k_layer_sp",
                     "avg_launch_us": round(avg_ms * 1e3, 3),
                     "algorithmic_bytes_per_launch": round(bytes_per_launch),
                     "launches_timed": prof["launches"],
@@ -252,7 +254,8 @@ def main():
                        f"{Fc} x {spec.name} (rate {spec.rate:.2f} QC-MET-LDPC, {spec.mb}x{spec.nb} base, Z={spec.Z}, "
                        f"n={spec.n}, SNR {w.meta['snr']})" for w, spec, Fc in zip(wls, specs, Fs))
                    + (f", at most {iters} iterations with early termination" if args.early_stop
-                      else f", {iters} iterations") + f", layered sum-product, {msg_name} messages",
+                      else f", {iters} iterations") + f", {'flooding' if args.flooding else 'layered'} sum-product, "
+                   f"{msg_name} messages",
                    "frames": F, "iterations": iters, "layers": [int(c.info.G) for c in codes], "tuning": tun,
                    "per_code": per_code},
         "fer": fer, "syndrome_fail_rate": syn_fail, "early_stop": early,

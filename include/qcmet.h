@@ -57,6 +57,12 @@ enum qm_status {
 #define QM_VALIDATE   0x4  /* qm_decode checks inputs first (synchronises the stream) */
 #define QM_GRAPH      0x8  /* replay the whole decode (every code, every sweep) as one captured
                               hipGraph, re-captured when buffers or iters change */
+#define QM_FLOODING   0x20 /* qm_decode runs the flooding schedule instead of layers: per
+                              iteration every check updates from the previous iteration's
+                              APPs (one launch over all rows), then every variable takes
+                              APP = LLR + its messages added in ascending row order.  Not with
+                              QM_EARLY_STOP or the min-sum decoder; columns of at most 128
+                              entries.  Workspace per frame: 4 B per degree>=2 variable. */
 #define QM_EARLY_STOP 0x10 /* reserve the workspace of qm_decode_early (per code and frame:
                               6 B per check, 1 B per variable and 20 B; at most 8192
                               frames per code) */

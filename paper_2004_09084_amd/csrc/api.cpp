@@ -138,6 +138,8 @@ struct Slot {
     std::vector<int32_t> gptr;
     std::vector<int32_t> cols1;  // degree>=2 block columns (LDS order)
     size_t oGptr = 0, oCols1 = 0;
+    std::vector<ColDesc> hcols;  // flooding: column descriptors of cols1
+    size_t oColD = 0, oLam = 0;
     int maxd_t = 4;
 };
 
@@ -195,7 +197,7 @@ size_t msg_bytes(const qm_decoder &d) {
 
 // decoded by the LDS-resident kernel (one frame per tile)?
 bool lds_slot(const qm_decoder &d, const Slot &s) {
-    return d.tun.lds_resident && s.F > 0 && s.code->max_d <= 8 && d.lds_limit > 0 &&
+    return d.tun.lds_resident && !(d.flags & QM_FLOODING) && s.F > 0 && s.code->max_d <= 8 && d.lds_limit > 0 &&
            (int64_t)qm_lds_bytes((int)s.cols1.size(), s.code->Z) <= d.lds_limit;
 }
 
@@ -231,6 +233,10 @@ void layout(qm_decoder &d) {
         s.oRows = off; off = align_up(off + s.hrows.size() * sizeof(RowDesc));
         s.oGptr = off; off = align_up(off + s.gptr.size() * 4);
         s.oCols1 = off; off = align_up(off + std::max<size_t>(1, s.cols1.size()) * 4);
+        if (d.flags & QM_FLOODING) {
+            s.oColD = off; off = align_up(off + std::max<size_t>(1, s.hcols.size()) * sizeof(ColDesc));
+            s.oLam = off; off = align_up(off + fp * s.cols1.size() * (size_t)s.code->Z * 4);
+        }
         if (d.flags & QM_EARLY_STOP) {
             s.oAd = off; off = align_up(off + fp * (size_t)s.m * 4);
             s.oAct = off; off = align_up(off + fp * 4);
@@ -499,6 +505,42 @@ int enqueue_sweeps_fused(qm_decoder &d, int32_t iters, hipStream_t st) {
     return QM_OK;
 }
 
+// Flooding schedule: per iteration, every check from the previous
+// iteration's APPs (one launch over all rows), then every degree>=2
+// variable: APP = LLR + its messages in ascending row order.
+int enqueue_flood_slot(qm_decoder &d, Slot &s, int32_t iters, hipStream_t st) {
+    const TileGeom g = geom(d, s);
+    const SlotBufs b = slot_bufs(d, s);
+    const int msgk = msg_kind(d);
+    const size_t msg = msg_bytes(d);
+    float *Lam = reinterpret_cast<float *>(d.ws + s.oLam);
+    const ColDesc *cols = reinterpret_cast<const ColDesc *>(d.ws + s.oColD);
+    const int ncols1 = (int)s.cols1.size();
+    QM_HIP(qm_launch_copy_cols(b.A, Lam, reinterpret_cast<const int32_t *>(d.ws + s.oCols1), ncols1, g, st));
+    LayerArgs la = layer_args(d, s);
+    la.rows = b.rows;
+    la.nrows = s.code->mb;
+    // algorithmic bytes of one iteration: checks read APP and message and
+    // write the message per edge, read K per check; variables read the
+    // message per edge, read the LLR and write the APP per variable
+    double it_bytes = 0.0, checks = 0.0;
+    for (const RowDesc &r : s.hrows) it_bytes += (4.0 + 2.0 * msg) * r.d + 4.0;
+    for (const ColDesc &cd : s.hcols) it_bytes += (double)msg * cd.deg + 8.0;
+    it_bytes *= (double)s.F * s.code->Z;
+    checks = (double)s.code->mb * s.F * s.code->Z;
+    const int t0p = (iters - 1) / 2, t1p = d.profiling ? std::min(t0p + 4, iters - 1) : -1;
+    for (int t = 0; t < iters; ++t) {
+        la.last = (t == iters - 1) ? 1 : 0;
+        ProfScope it(d, st, t >= t0p && t < t1p);
+        int rc = it.begin();
+        if (rc != QM_OK) return rc;
+        QM_HIP(qm_launch_layer_flood(la, msgk, s.maxd_t, la.fpl, d.tun.block, d.tun.stream_hint, st));
+        QM_HIP(qm_launch_flood_vars(b.A, Lam, b.R, cols, ncols1, msgk, la.fpl, d.tun.block, g, st));
+        if ((rc = it.end(it_bytes, checks, 1)) != QM_OK) return rc;  // one timed unit = one iteration
+    }
+    return QM_OK;
+}
+
 // All sweeps of one code in one launch of the LDS-resident kernel.
 int ensure_side_stream(qm_decoder &d) {
     if (!d.side) QM_HIP(hipStreamCreateWithFlags(&d.side, hipStreamNonBlocking));
@@ -558,6 +600,13 @@ int enqueue_decode(qm_decoder &d, const float *llr, const uint8_t *syn, int32_t 
                    uint8_t *flags, hipStream_t st) {
     int rc = enqueue_init(d, llr, syn, st);
     if (rc != QM_OK) return rc;
+    if (d.flags & QM_FLOODING) {
+        for (Slot &s : d.slots) {
+            if (s.F == 0) continue;
+            if ((rc = enqueue_flood_slot(d, s, iters, st)) != QM_OK) return rc;
+        }
+        return enqueue_finalize(d, hard, app, flags, st);
+    }
     bool any_lds = false, any_tiled = false;
     for (const Slot &s : d.slots) {
         if (s.F == 0) continue;
@@ -717,6 +766,7 @@ int nms_slot(qm_decoder &d, Slot **out) {
     if (n != 1) return fail(QM_ERR_UNSUPPORTED, "the min-sum decoder takes a decoder with exactly one code");
     if (d.flags & (QM_MSG_FP16 | QM_MSG_FP8))
         return fail(QM_ERR_UNSUPPORTED, "the min-sum decoder keeps float32 messages");
+    if (d.flags & QM_FLOODING) return fail(QM_ERR_UNSUPPORTED, "the min-sum decoder is built for the layered schedule");
     *out = only;
     return QM_OK;
 }
@@ -906,8 +956,10 @@ int qm_decoder_create(const qm_code *const *codes, int32_t ncodes, const int32_t
     if (!out) return fail(QM_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (!codes || !frames_per_code || ncodes <= 0) return fail(QM_ERR_INVALID_ARG, "need at least one code");
-    if (flags & ~(QM_MSG_FP16 | QM_MSG_FP8 | QM_VALIDATE | QM_GRAPH | QM_EARLY_STOP))
+    if (flags & ~(QM_MSG_FP16 | QM_MSG_FP8 | QM_VALIDATE | QM_GRAPH | QM_EARLY_STOP | QM_FLOODING))
         return fail(QM_ERR_INVALID_ARG, "unknown flag bits");
+    if ((flags & QM_FLOODING) && (flags & QM_EARLY_STOP))
+        return fail(QM_ERR_UNSUPPORTED, "early termination is built for the layered schedule only");
     if ((flags & QM_MSG_FP16) && (flags & QM_MSG_FP8))
         return fail(QM_ERR_INVALID_ARG, "QM_MSG_FP16 and QM_MSG_FP8 exclude each other");
     qm_decoder *d = new (std::nothrow) qm_decoder;
@@ -946,6 +998,26 @@ int qm_decoder_create(const qm_code *const *codes, int32_t ncodes, const int32_t
         s.gptr = s.code->gptr;
         for (int j = 0; j < s.code->nb; ++j)
             if (s.code->col_deg[j] >= 2) s.cols1.push_back(j);
+        if (flags & QM_FLOODING) {
+            for (int j : s.cols1) {
+                ColDesc cd;
+                std::memset(&cd, 0, sizeof(cd));
+                cd.col = j;
+                for (int i = 0; i < s.code->mb; ++i) {
+                    const int a = s.code->sh[i * s.code->nb + j];
+                    if (a < 0) continue;
+                    if (cd.deg == QM_MAXCD) {
+                        delete d;
+                        return fail(QM_ERR_UNSUPPORTED, "flooding: a column has more than " +
+                                                            std::to_string(QM_MAXCD) + " entries");
+                    }
+                    cd.ent[cd.deg] = s.code->ent[i * s.code->nb + j];
+                    cd.shift[cd.deg] = a;
+                    cd.deg++;
+                }
+                s.hcols.push_back(cd);
+            }
+        }
         {
             const int md = s.code->max_d;
             s.maxd_t = md <= 2 ? 2 : md <= 6 ? md : md <= 8 ? 8 : 16;
@@ -994,6 +1066,8 @@ int qm_decoder_bind_workspace(qm_decoder *d, void *dev, size_t bytes) {
         QM_HIP(hipMemcpy(d->ws + s.oGptr, s.gptr.data(), s.gptr.size() * 4, hipMemcpyHostToDevice));
         if (!s.cols1.empty())
             QM_HIP(hipMemcpy(d->ws + s.oCols1, s.cols1.data(), s.cols1.size() * 4, hipMemcpyHostToDevice));
+        if (!s.hcols.empty())
+            QM_HIP(hipMemcpy(d->ws + s.oColD, s.hcols.data(), s.hcols.size() * sizeof(ColDesc), hipMemcpyHostToDevice));
     }
     int device = 0, lds = 0;
     QM_HIP(hipGetDevice(&device));

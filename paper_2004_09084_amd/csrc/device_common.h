@@ -179,8 +179,9 @@ template <> struct LogOf<2> { static constexpr int v = 1; };
 // never written while a kernel runs, so every field becomes a scalar load.
 typedef const __attribute__((address_space(4))) RowDesc ConstRowDesc;
 __device__ __forceinline__ ConstRowDesc *as_const(const RowDesc *p) { return (ConstRowDesc *)p; }
+typedef const __attribute__((address_space(4))) ColDesc ConstColDesc;
+__device__ __forceinline__ ConstColDesc *as_const_col(const ColDesc *p) { return (ConstColDesc *)p; }
 
-// Per-lane context of one layer update.
 // packed frame bits: a field of esz bytes (1, 2, 4 or 8) at index i
 __device__ __forceinline__ void store_packed(uint8_t *p, int64_t i, int esz, uint64_t w) {
     switch (esz) {
@@ -199,6 +200,7 @@ __device__ __forceinline__ uint64_t load_packed(const uint8_t *p, int64_t i, int
     }
 }
 
+// Per-lane context of one layer update.
 struct LaneCtx {
     __amdgpu_buffer_rsrc_t rA, rR, rK;
     uint32_t node;   // in-column element index of (k, first frame of the lane)

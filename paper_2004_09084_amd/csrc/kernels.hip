@@ -155,6 +155,59 @@ __global__ void __launch_bounds__(256) k_syndrome(const float *__restrict__ A, c
     if (tid < FT && lf[tid]) atomicOr(&fail[tile * FT + tid], 1u);
 }
 
+// Variable half of a flooding iteration: APP = LLR + the messages of the
+// variable's checks, added in ascending row order (ColDesc), for the FPL
+// frames of a lane.  Workgroup -> (tile, degree>=2 column, chunk of lanes).
+template <typename MsgT, int FPL>
+__global__ void __launch_bounds__(256) k_flood_vars(float *__restrict__ A, const float *__restrict__ Lam,
+                                                    const void *__restrict__ R, const ColDesc *cols, int Z, int ftl,
+                                                    int ntiles, int chunks, int64_t strideA, int64_t strideR,
+                                                    int64_t strideL) {
+    typedef MsgIO<MsgT> IO;
+    constexpr int FPLL = LogOf<FPL>::v;
+    const int b = blockIdx.x;
+    const int tile = b % ntiles;
+    const int rest = b / ntiles;
+    const int chunk = rest % chunks;
+    const int c = rest / chunks;
+    const int lpl = ftl - FPLL;
+    const int idx = chunk * (int)blockDim.x + (int)threadIdx.x;
+    if (idx >= (Z << lpl)) return;
+    const int z = idx >> lpl;
+    const uint32_t node = (uint32_t)idx << FPLL;           // z * FT + first frame of the lane
+    const uint32_t fl = node & ((1u << ftl) - 1u);
+    const uint32_t colw = (uint32_t)Z << ftl;
+    ConstColDesc *cd = as_const_col(cols + c);
+    const __amdgpu_buffer_rsrc_t rL = make_rsrc(Lam + (int64_t)tile * strideL, (uint32_t)(strideL * 4));
+    const __amdgpu_buffer_rsrc_t rR =
+        make_rsrc(static_cast<const char *>(R) + (int64_t)tile * strideR * IO::bytes, (uint32_t)(strideR * IO::bytes));
+    const __amdgpu_buffer_rsrc_t rA = make_rsrc(A + (int64_t)tile * strideA, (uint32_t)(strideA * 4));
+    float sum[FPL];
+    bload_f32<FPL>(rL, node * 4u, (uint32_t)c * colw * 4u, sum);
+    const int deg = cd->deg;
+    for (int e = 0; e < deg; ++e) {
+        int k = z - cd->shift[e];
+        k = k < 0 ? k + Z : k;
+        float r[FPL];
+        IO::template load<FPL>(rR, (((uint32_t)k << ftl) + fl) * IO::bytes, (uint32_t)cd->ent[e] * colw * IO::bytes, r);
+#pragma unroll
+        for (int f = 0; f < FPL; ++f) sum[f] += r[f];
+    }
+    bstore_f32<FPL>(rA, node * 4u, (uint32_t)cd->col * colw * 4u, sum);
+}
+
+// Lam[tile][c*Z*FT + e] = A[tile][cols1[c]*Z*FT + e]: the channel LLRs of the
+// degree>=2 columns, kept for the flooding variable update.
+__global__ void __launch_bounds__(256) k_copy_cols(const float *__restrict__ A, float *__restrict__ Lam,
+                                                   const int32_t *cols1, int64_t colw, int64_t strideA,
+                                                   int64_t strideL) {
+    const int tile = blockIdx.z;
+    const int c = blockIdx.y;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= colw) return;
+    Lam[(int64_t)tile * strideL + (int64_t)c * colw + e] = A[(int64_t)tile * strideA + (int64_t)cols1[c] * colw + e];
+}
+
 // Syndrome test of an early-terminating decode from packed hard decisions:
 // one lane per check and tile XORs the packed words of the row's variables
 // (PA), of its degree-1 variable (Pd) and of its syndrome bits (PS); failing
@@ -536,6 +589,54 @@ hipError_t qm_launch_finalize(const float *A, const uint32_t *fail, float *app, 
                               int F, const TileGeom &g, hipStream_t s, const int32_t *map) {
     dim3 grid((unsigned)((g.n + 63) / 64), (unsigned)g.ntiles);
     hipLaunchKernelGGL(k_finalize, grid, dim3(256), 0, s, A, fail, app, hard, flags, F, g.n, g.ft_log2, map);
+    return hipGetLastError();
+}
+
+hipError_t qm_launch_layer_flood(const LayerArgs &a, int msgk, int maxd, int fpl, int block, int hint, hipStream_t s) {
+    switch (msgk) {
+        case QM_MSGK_F32: return qm_layer_f32(a, 2, maxd, fpl, block, hint, s);
+        case QM_MSGK_F16: return qm_layer_f16(a, 2, maxd, fpl, block, hint, s);
+        case QM_MSGK_F8: return qm_layer_f8(a, 2, maxd, fpl, block, hint, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t qm_launch_flood_vars(float *A, const float *Lam, const void *R, const ColDesc *cols, int ncols1, int msgk,
+                                int fpl, int block, const TileGeom &g, hipStream_t s) {
+    if (ncols1 == 0 || g.ntiles == 0) return hipSuccess;
+    if (block < 64 || block > 256 || (fpl != 1 && fpl != 2) || (1 << g.ft_log2) < fpl)
+        return hipErrorInvalidConfiguration;
+    const int lanes = (g.Z << g.ft_log2) / fpl;
+    const int chunks = (lanes + block - 1) / block;
+    const int64_t blocks = (int64_t)g.ntiles * ncols1 * chunks;
+    const int64_t sA = g.n << g.ft_log2, sR = (g.nent1 * g.Z) << g.ft_log2, sL = ((int64_t)ncols1 * g.Z) << g.ft_log2;
+    dim3 grid((unsigned)blocks), tb((unsigned)block);
+#define QM_FV(T)                                                                                                   \
+    do {                                                                                                           \
+        if (fpl == 2)                                                                                              \
+            hipLaunchKernelGGL((k_flood_vars<T, 2>), grid, tb, 0, s, A, Lam, R, cols, g.Z, g.ft_log2, g.ntiles,     \
+                               chunks, sA, sR, sL);                                                                \
+        else                                                                                                       \
+            hipLaunchKernelGGL((k_flood_vars<T, 1>), grid, tb, 0, s, A, Lam, R, cols, g.Z, g.ft_log2, g.ntiles,     \
+                               chunks, sA, sR, sL);                                                                \
+    } while (0)
+    switch (msgk) {
+        case QM_MSGK_F32: QM_FV(float); break;
+        case QM_MSGK_F16: QM_FV(_Float16); break;
+        case QM_MSGK_F8: QM_FV(Fp8Msg); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef QM_FV
+    return hipGetLastError();
+}
+
+hipError_t qm_launch_copy_cols(const float *A, float *Lam, const int32_t *cols1, int ncols1, const TileGeom &g,
+                               hipStream_t s) {
+    if (ncols1 == 0 || g.ntiles == 0) return hipSuccess;
+    const int64_t colw = (int64_t)g.Z << g.ft_log2;
+    dim3 grid((unsigned)((colw + 255) / 256), (unsigned)ncols1, (unsigned)g.ntiles);
+    hipLaunchKernelGGL(k_copy_cols, grid, dim3(256), 0, s, A, Lam, cols1, colw, g.n << g.ft_log2,
+                       ((int64_t)ncols1 * g.Z) << g.ft_log2);
     return hipGetLastError();
 }
 

@@ -78,8 +78,14 @@ __device__ __forceinline__ void store_live(__amdgpu_buffer_rsrc_t r, uint32_t vo
     }
 }
 
-template <typename MsgT, int D, int FPL, int AUX, bool ET>
+// Update modes of the check kernel.
+constexpr int kLayered = 0;  // layered sweep (fixed iterations)
+constexpr int kEarly = 1;    // layered sweep with early termination (EtLane)
+constexpr int kFlood = 2;    // flooding: messages only, the APPs of the previous iteration stay
+
+template <typename MsgT, int D, int FPL, int AUX, int MODE>
 __device__ __forceinline__ void check_update(const LaneCtx &c, ConstRowDesc *rd, int last, const EtLane<FPL> &et) {
+    constexpr bool ET = MODE == kEarly;
     typedef MsgIO<MsgT> IO;
     const uint32_t col_bytes = c.colw * 4u;
     const uint32_t msg_col_bytes = c.colw * IO::bytes;
@@ -146,7 +152,7 @@ __device__ __forceinline__ void check_update(const LaneCtx &c, ConstRowDesc *rd,
             an[f] = q[j][f] + rm[f];
         }
         store_live<IO, FPL, AUX, ET>(c.rR, vom, ent_so[j], rm, et);
-        store_live<MsgIO<float>, FPL, 0, ET>(c.rA, aoff[j], col_so[j], an, et);
+        if constexpr (MODE != kFlood) store_live<MsgIO<float>, FPL, 0, ET>(c.rA, aoff[j], col_so[j], an, et);
         if constexpr (ET) {
             // the variable's packed hard decisions (the last layer of the
             // sweep that touches it leaves its end-of-sweep signs)
@@ -179,23 +185,24 @@ __device__ __forceinline__ void check_update(const LaneCtx &c, ConstRowDesc *rd,
     }
 }
 
-template <typename MsgT, int D, int FPL, int AUX, bool ET>
+template <typename MsgT, int D, int FPL, int AUX, int MODE>
 __device__ __forceinline__ void dispatch_degree(int d, const LaneCtx &c, ConstRowDesc *rd, int last,
                                                 const EtLane<FPL> &et) {
     if constexpr (D >= 0) {
         if (d == D) {
-            check_update<MsgT, D, FPL, AUX, ET>(c, rd, last, et);
+            check_update<MsgT, D, FPL, AUX, MODE>(c, rd, last, et);
             return;
         }
-        dispatch_degree<MsgT, D - 1, FPL, AUX, ET>(d, c, rd, last, et);
+        dispatch_degree<MsgT, D - 1, FPL, AUX, MODE>(d, c, rd, last, et);
     }
 }
 
 // Thread mapping: workgroup -> (frame tile, row of the layer, chunk of
 // lanes); consecutive workgroups cycle through the frame tiles, so with 8
 // tiles each tile's lanes stay on one XCD under round-robin dispatch.
-template <typename MsgT, int MAXD, int FPL, int AUX, bool ET = false>
+template <typename MsgT, int MAXD, int FPL, int AUX, int MODE = kLayered>
 __device__ __forceinline__ void layer_body(const LayerArgs &a, int b) {
+    constexpr bool ET = MODE == kEarly;
     constexpr int FPLL = LogOf<FPL>::v;
     int tile, rest;
     if constexpr (ET) {
@@ -242,7 +249,7 @@ __device__ __forceinline__ void layer_body(const LayerArgs &a, int b) {
         et.PA = a.PA + (int64_t)tile * (a.strideA >> c.ftl) * et.esz;
         et.Pd = a.Pd + (int64_t)tile * (a.strideK >> c.ftl) * et.esz;
     }
-    dispatch_degree<MsgT, MAXD, FPL, AUX, ET>(rd->d, c, rd, a.last, et);
+    dispatch_degree<MsgT, MAXD, FPL, AUX, MODE>(rd->d, c, rd, a.last, et);
 }
 
 template <typename MsgT, int MAXD, int FPL, int AUX>
@@ -253,7 +260,15 @@ __global__ void __launch_bounds__(256) k_layer_sp(const LayerArgs a) {
 // The same layer update for an early-terminating decode (see EtLane).
 template <typename MsgT, int MAXD, int FPL, int AUX>
 __global__ void __launch_bounds__(256) k_layer_sp_et(const LayerArgs a) {
-    layer_body<MsgT, MAXD, FPL, AUX, true>(a, (int)blockIdx.x);
+    layer_body<MsgT, MAXD, FPL, AUX, kEarly>(a, (int)blockIdx.x);
+}
+
+// The check half of a flooding iteration: every row of the code in one
+// launch, each check reading the APPs of the previous iteration and storing
+// only its new messages (and, in the last iteration, its degree-1 APP).
+template <typename MsgT, int MAXD, int FPL, int AUX>
+__global__ void __launch_bounds__(256) k_layer_flood(const LayerArgs a) {
+    layer_body<MsgT, MAXD, FPL, AUX, kFlood>(a, (int)blockIdx.x);
 }
 
 // One launch for the current layer of every code of a mixed batch: the
@@ -283,6 +298,12 @@ struct LayerSpEt {
         hipLaunchKernelGGL((k_layer_sp_et<T, D, P, H>), g, b, 0, s, a);
     }
 };
+struct LayerFlood {
+    template <typename T, int D, int P, int H>
+    static void go(dim3 g, dim3 b, hipStream_t s, const LayerArgs &a) {
+        hipLaunchKernelGGL((k_layer_flood<T, D, P, H>), g, b, 0, s, a);
+    }
+};
 
 template <class K, typename T, int D, int P>
 void layer_go(dim3 g, dim3 b, hipStream_t s, const LayerArgs &a, int hint) {
@@ -309,13 +330,14 @@ void layer_maxd(dim3 g, dim3 b, hipStream_t s, const LayerArgs &a, int maxd, int
 }
 
 template <typename MsgT>
-hipError_t layer_msg(const LayerArgs &a, int et, int maxd, int fpl, int block, int hint, hipStream_t s) {
+hipError_t layer_msg(const LayerArgs &a, int mode, int maxd, int fpl, int block, int hint, hipStream_t s) {
     const int64_t blocks = (int64_t)a.ntiles * a.nrows * a.chunks;
     if (blocks == 0) return hipSuccess;
     if (block < 64 || block > 256 || (fpl != 1 && fpl != 2) || (1 << a.ft_log2) < fpl)
         return hipErrorInvalidConfiguration;  // the kernels are built for <= 256 lanes
     dim3 grid((unsigned)blocks), tb((unsigned)block);
-    if (et) layer_maxd<LayerSpEt, MsgT>(grid, tb, s, a, maxd, fpl, hint);
+    if (mode == kEarly) layer_maxd<LayerSpEt, MsgT>(grid, tb, s, a, maxd, fpl, hint);
+    else if (mode == kFlood) layer_maxd<LayerFlood, MsgT>(grid, tb, s, a, maxd, fpl, hint);
     else layer_maxd<LayerSp, MsgT>(grid, tb, s, a, maxd, fpl, hint);
     return hipGetLastError();
 }

@@ -98,6 +98,16 @@ struct LdsArgs {
     int64_t n, m, nr;         // per-frame elements of A, K, R
 };
 
+// Flooding schedule: one degree>=2 column and its entries in ascending row
+// order (the order its messages are added in).
+#define QM_MAXCD 128
+struct ColDesc {
+    int32_t col;              // block column
+    int32_t deg;              // entries (rows) in the column
+    int32_t ent[QM_MAXCD];    // message slot of each entry
+    int32_t shift[QM_MAXCD];  // its shift: row check k meets variable (k + shift) mod Z
+};
+
 // Codes one decoder can mix in a single fused launch.
 #define QM_MAX_CODES 4
 
@@ -151,6 +161,14 @@ hipError_t qm_launch_finalize(const float *A, const uint32_t *fail, float *app, 
 // launch; bytes of LDS it needs per workgroup, and the launch.
 size_t qm_lds_bytes(int ncols1, int Z);
 hipError_t qm_launch_sweeps_lds(const LdsArgs &a, int F, int msgk, int maxd, hipStream_t s);
+// flooding schedule (kernels.hip): the check half of an iteration, then the
+// variable half APP = LLR + sum of the column's messages (ascending rows);
+// Lam holds the channel LLRs of the ncols1 degree>=2 columns, [tile][c*Z][FT].
+hipError_t qm_launch_layer_flood(const LayerArgs &a, int msgk, int maxd, int fpl, int block, int hint, hipStream_t s);
+hipError_t qm_launch_flood_vars(float *A, const float *Lam, const void *R, const ColDesc *cols, int ncols1, int msgk,
+                                int fpl, int block, const TileGeom &g, hipStream_t s);
+hipError_t qm_launch_copy_cols(const float *A, float *Lam, const int32_t *cols1, int ncols1, const TileGeom &g,
+                               hipStream_t s);
 // early termination (kernels.hip)
 hipError_t qm_launch_layer_et(const LayerArgs &a, int msgk, int maxd, int fpl, int block, int hint, hipStream_t s);
 hipError_t qm_launch_syndrome_et(const float *A, const float *Ad, const uint8_t *Sil, const RowDesc *rows, int mb,

@@ -33,6 +33,7 @@ QM_MSG_FP8 = 0x2
 QM_VALIDATE = 0x4
 QM_GRAPH = 0x8
 QM_EARLY_STOP = 0x10
+QM_FLOODING = 0x20
 
 # every symbol include/qcmet.h declares
 EXPORTED = [

@@ -103,6 +103,13 @@ typedef struct {
                                  workgroup barriers between layers (one launch per decode; such a
                                  code uses one frame per tile).  Bit-identical to the layer
                                  kernels. */
+    int32_t tile_groups;      /* 1, 2, 4 or 8 (0 = 1): a layered decode of one code splits its frame
+                                 tiles into this many groups (fewer if it does not divide the
+                                 tile count), each running its own layer sequence on its own
+                                 stream, forked from and joined to the decode stream; one
+                                 group's launch fills the ramp-down of another's.  Frames never
+                                 depend on other frames, so results are bit-identical.  Not used
+                                 by fused mixed batches, flooding or early termination. */
 } qm_tuning;
 
 int qm_abi_version(void);
@@ -190,7 +197,8 @@ int qm_decode_early(qm_decoder *dec, const float *llr, const uint8_t *syndrome, 
 /* Times result-preserving tunings on the given inputs and keeps the fastest:
  * frames per tile {16, 32, 64} x frames per lane {1, 2} x block {128, 256},
  * then, on the best, per-row launches, unfused codes, graph replay, the
- * other stream_hint and (if a code fits) the other lds_resident.  The
+ * other stream_hint, (if a code fits) the other lds_resident and (one code)
+ * 2 and 4 tile groups.  The
  * schedule (row order) is never changed, so every trial decodes to the same
  * bits.  Each trial decodes min(iters, 8) sweeps into the caller's output
  * buffers (same shapes as qm_decode); the call synchronises the stream.

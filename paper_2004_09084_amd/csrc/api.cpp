@@ -177,6 +177,10 @@ struct qm_decoder {
     // and joined back to the decode stream with events
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // tile groups of a layered decode: one stream per group after the first
+    std::vector<hipStream_t> gstreams;
+    std::vector<hipEvent_t> gjoin;
+    hipEvent_t gfork = nullptr;
     struct LdsPending { size_t a, b; double bytes; };
     std::vector<LdsPending> lds_pending;
     // early termination: host polls of the frames still decoding
@@ -390,19 +394,62 @@ int enqueue_finalize(qm_decoder &d, uint8_t *hard, float *app, uint8_t *flags, h
 }
 
 // Sweeps of one code, one launch per layer (or per row with merge = 0).
+// Tile groups of a layered decode (tuning tile_groups): usable count for a
+// code (it must divide the number of tiles).
+int tile_groups(const qm_decoder &d, const Slot &s) {
+    const int nt = geom(d, s).ntiles;
+    int g = std::max(1, std::min<int>(d.tun.tile_groups, nt));
+    while (g > 1 && nt % g) --g;
+    return g;
+}
+
+int ensure_group_streams(qm_decoder &d, int groups) {
+    while ((int)d.gstreams.size() < groups - 1) {
+        hipStream_t st = nullptr;
+        QM_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        d.gstreams.push_back(st);
+        hipEvent_t e = nullptr;
+        QM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        d.gjoin.push_back(e);
+    }
+    if (!d.gfork) QM_HIP(hipEventCreateWithFlags(&d.gfork, hipEventDisableTiming));
+    return QM_OK;
+}
+
+// Sweeps of one code, one launch per layer (or per row with merge = 0).
+// With tile groups, each group of consecutive frame tiles runs its own layer
+// sequence on its own stream (frames never depend on other frames), so one
+// group's launch can fill the ramp-down of another's.
 int enqueue_sweeps_slot(qm_decoder &d, Slot &s, int32_t iters, hipStream_t st) {
     const int msgk = msg_kind(d);
     const size_t msg = msg_bytes(d);
     const RowDesc *rows = slot_bufs(d, s).rows;
     LayerArgs la = layer_args(d, s);
     const int G = (int)s.gptr.size() - 1;
+    const int ng = tile_groups(d, s);
+    std::vector<LayerArgs> lg(ng, la);
+    std::vector<hipStream_t> gs(ng, st);
+    if (ng > 1) {
+        if ((int)d.gstreams.size() < ng - 1 || !d.gfork) return fail(QM_ERR_STATE, "tile-group streams missing");
+        const int tpg = la.ntiles / ng;
+        for (int g = 0; g < ng; ++g) {
+            lg[g].A = la.A + (int64_t)g * tpg * la.strideA;
+            lg[g].R = static_cast<char *>(la.R) + (int64_t)g * tpg * la.strideR * (int64_t)msg;
+            lg[g].K = la.K + (int64_t)g * tpg * la.strideK;
+            lg[g].ntiles = tpg;
+            if (g > 0) gs[g] = d.gstreams[g - 1];
+        }
+        QM_HIP(hipEventRecord(d.gfork, st));
+        for (int g = 1; g < ng; ++g) QM_HIP(hipStreamWaitEvent(gs[g], d.gfork, 0));
+    }
     // profiled: up to 4 sweeps from the middle of the decode, never the last
     // (which also forms the degree-1 APPs); one event pair per sweep, so no
     // event sits between two layer launches
     const int t0p = (iters - 1) / 2, t1p = d.profiling ? std::min(t0p + 4, iters - 1) : -1;
     for (int t = 0; t < iters; ++t) {
-        la.last = (t == iters - 1) ? 1 : 0;
         const bool prof = t >= t0p && t < t1p;
+        // with tile groups the window is timed on the decode stream, where
+        // group 0 runs; the groups proceed concurrently with the same work
         ProfScope sweep(d, st, prof);
         int rc = sweep.begin();
         if (rc != QM_OK) return rc;
@@ -412,9 +459,12 @@ int enqueue_sweeps_slot(qm_decoder &d, Slot &s, int32_t iters, hipStream_t st) {
             const int p_lo = s.gptr[gi], p_hi = s.gptr[gi + 1];
             const int step = d.tun.merge ? (p_hi - p_lo) : 1;
             for (int p = p_lo; p < p_hi; p += step) {
-                la.rows = rows + p;
-                la.nrows = step;
-                QM_HIP(qm_launch_layer(la, msgk, s.maxd_t, la.fpl, d.tun.block, d.tun.stream_hint, st));
+                for (int g = 0; g < ng; ++g) {
+                    lg[g].last = (t == iters - 1) ? 1 : 0;
+                    lg[g].rows = rows + p;
+                    lg[g].nrows = step;
+                    QM_HIP(qm_launch_layer(lg[g], msgk, s.maxd_t, la.fpl, d.tun.block, d.tun.stream_hint, gs[g]));
+                }
                 double b, ch;
                 layer_work(s, s.hrows.data() + p, step, msg, &b, &ch);
                 bytes += b;
@@ -423,6 +473,10 @@ int enqueue_sweeps_slot(qm_decoder &d, Slot &s, int32_t iters, hipStream_t st) {
             }
         }
         if ((rc = sweep.end(bytes, checks, launches)) != QM_OK) return rc;
+    }
+    for (int g = 1; g < ng; ++g) {
+        QM_HIP(hipEventRecord(d.gjoin[g - 1], gs[g]));
+        QM_HIP(hipStreamWaitEvent(st, d.gjoin[g - 1], 0));
     }
     return QM_OK;
 }
@@ -1031,6 +1085,7 @@ int qm_decoder_create(const qm_code *const *codes, int32_t ncodes, const int32_t
     d->tun.frames_per_lane = 2;
     d->tun.fuse_codes = 1;
     d->tun.stream_hint = 1;
+    d->tun.tile_groups = 1;
     layout(*d);
     *out = d;
     return QM_OK;
@@ -1043,6 +1098,9 @@ int qm_decoder_destroy(qm_decoder *d) {
     for (hipEvent_t e : d->ev_pool) (void)hipEventDestroy(e);
     for (hipEvent_t e : d->poll_ev)
         if (e) (void)hipEventDestroy(e);
+    for (hipStream_t g : d->gstreams) (void)hipStreamDestroy(g);
+    for (hipEvent_t e : d->gjoin) (void)hipEventDestroy(e);
+    if (d->gfork) (void)hipEventDestroy(d->gfork);
     if (d->ev_fork) (void)hipEventDestroy(d->ev_fork);
     if (d->ev_join) (void)hipEventDestroy(d->ev_join);
     if (d->side) (void)hipStreamDestroy(d->side);
@@ -1097,6 +1155,9 @@ int qm_decoder_set_tuning(qm_decoder *d, const qm_tuning *t) {
     n.fuse_codes = n.fuse_codes ? 1 : 0;
     n.stream_hint = n.stream_hint ? 1 : 0;
     n.lds_resident = n.lds_resident ? 1 : 0;
+    if (n.tile_groups == 0) n.tile_groups = 1;
+    if (n.tile_groups != 1 && n.tile_groups != 2 && n.tile_groups != 4 && n.tile_groups != 8)
+        return fail(QM_ERR_INVALID_ARG, "tile_groups must be 1, 2, 4 or 8");
     d->tun = n;
     drop_graph(*d);
     return QM_OK;
@@ -1121,6 +1182,10 @@ int qm_decode(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t iters
     }
     if (d->tun.lds_resident) {
         const int rc = ensure_side_stream(*d);
+        if (rc != QM_OK) return rc;
+    }
+    if (d->tun.tile_groups > 1) {
+        const int rc = ensure_group_streams(*d, d->tun.tile_groups);
         if (rc != QM_OK) return rc;
     }
     if (!d->tun.graph || d->profiling) return enqueue_decode(*d, llr, syn, iters, hard, app, flags, st);
@@ -1406,9 +1471,9 @@ int qm_autotune(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t ite
             std::fprintf(log,
                          "{\"frames_per_tile\": %d, \"frames_per_lane\": %d, \"block\": %d, \"merge\": %d, "
                          "\"fuse_codes\": %d, \"graph\": %d, \"stream_hint\": %d, \"lds_resident\": %d, "
-                         "\"iters\": %d, \"ms\": %.4f}\n",
+                         "\"tile_groups\": %d, \"iters\": %d, \"ms\": %.4f}\n",
                          t.frames_per_tile, t.frames_per_lane, t.block, t.merge, t.fuse_codes, t.graph,
-                         t.stream_hint, t.lds_resident, probe, *ms);
+                         t.stream_hint, t.lds_resident, t.tile_groups, probe, *ms);
         return QM_OK;
     };
 
@@ -1442,8 +1507,12 @@ int qm_autotune(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t ite
         d->tun = keep;
     }
     // structural variants on top of the best launch shape
-    for (int v = 0; v < 5 && rc == QM_OK; ++v) {
+    for (int v = 0; v < 7 && rc == QM_OK; ++v) {
         qm_tuning t = best;
+        if (v == 5 || v == 6) {
+            if (ncodes != 1) continue;  // fused mixed batches do not use tile groups
+            t.tile_groups = v == 5 ? 2 : 4;
+        }
         if (v == 4) {
             if (!lds_candidate) continue;
             t.lds_resident = !t.lds_resident;

@@ -291,3 +291,49 @@ def test_autotune_picks_a_result_preserving_tuning(tmp_path):
     torch.cuda.synchronize()
     for x, y in zip(ref, got):
         assert np.array_equal(x, y), tun
+
+
+def test_tile_groups_are_bit_identical():
+    # frame tiles split into groups on their own streams: frames never
+    # depend on other frames, so every output is unchanged
+    import torch
+    wl = _wl(SMALL, 64, snr=0.3, seed=9)
+    ref = gpu_decode(wl.shifts, SMALL.Z, wl.llr, wl.s, 9, tuning=dict(frames_per_tile=8))
+    for tun in (dict(frames_per_tile=8, tile_groups=2), dict(frames_per_tile=8, tile_groups=4),
+                dict(frames_per_tile=8, tile_groups=8), dict(frames_per_tile=4, tile_groups=4, merge=0),
+                dict(frames_per_tile=16, tile_groups=8)):
+        got = gpu_decode(wl.shifts, SMALL.Z, wl.llr, wl.s, 9, tuning=tun)
+        for x, y in zip(got, ref):
+            assert np.array_equal(x, y), tun
+    fp16 = gpu_decode(wl.shifts, SMALL.Z, wl.llr, wl.s, 9, flags=Q.QM_MSG_FP16, tuning=dict(frames_per_tile=8))
+    got = gpu_decode(wl.shifts, SMALL.Z, wl.llr, wl.s, 9, flags=Q.QM_MSG_FP16,
+                     tuning=dict(frames_per_tile=8, tile_groups=4))
+    for x, y in zip(got, fp16):
+        assert np.array_equal(x, y)
+    # captured graph with forked group streams, replayed with eager work between
+    code = Q.Code(wl.shifts, SMALL.Z)
+    dec = Q.Decoder([code], [64], tuning=dict(frames_per_tile=8, tile_groups=4, graph=1))
+    L, S = to_dev(wl.llr), to_dev(wl.s)
+    for _ in range(3):
+        h, a, f = dec.decode(L, S, 9)
+        torch.cuda.synchronize()
+        assert np.array_equal(h.cpu().numpy().reshape(64, -1), ref[0])
+        assert np.array_equal(a.cpu().numpy().reshape(64, -1), ref[1])
+        torch.ones(8, device="cuda").mul_(2.0)
+
+
+def test_tile_groups_fullsize():
+    import torch
+    spec = W.RATE01
+    wl = W.build(spec, 128, frame_seed=0)
+    code = Q.Code(wl.shifts, spec.Z)
+    outs = []
+    for g in (1, 2):
+        dec = Q.Decoder([code], [128], tuning=dict(tile_groups=g))
+        h, a, f = dec.decode(to_dev(wl.llr), to_dev(wl.s), 3)
+        torch.cuda.synchronize()
+        outs.append((h.cpu().numpy(), a.cpu().numpy(), f.cpu().numpy()))
+        del dec
+        torch.cuda.empty_cache()
+    for x, y in zip(*outs):
+        assert np.array_equal(x, y)

@@ -201,7 +201,7 @@ hipError_t launch_lds(const LdsArgs &a, int F, int maxd, size_t lds, hipStream_t
         case 5: return launch_lds_d<MsgT, 5>(a, F, lds, s);
         case 6: return launch_lds_d<MsgT, 6>(a, F, lds, s);
         case 8: return launch_lds_d<MsgT, 8>(a, F, lds, s);
-        default: return launch_lds_d<MsgT, 16>(a, F, lds, s);
+        default: return hipErrorInvalidValue;  // rows of more than 8 degree>=2 entries use the tiled kernels
     }
 }
 

@@ -133,7 +133,7 @@ struct Slot {
     int64_t n = 0, m = 0;
     size_t oA = 0, oR = 0, oK = 0, oS = 0, oFail = 0, oRows = 0;
     // early termination (decoders created with QM_EARLY_STOP)
-    size_t oAd = 0, oAct = 0, oMap = 0, oPerm = 0, oIt = 0, oCtl = 0, oPA = 0, oPd = 0, oPS = 0;
+    size_t oAd = 0, oAct = 0, oTmask = 0, oMap = 0, oPerm = 0, oIt = 0, oCtl = 0, oEmit = 0, oPA = 0, oPd = 0, oPS = 0;
     std::vector<RowDesc> hrows;  // schedule order
     std::vector<int32_t> gptr;
     std::vector<int32_t> cols1;  // degree>=2 block columns (LDS order)
@@ -244,10 +244,12 @@ void layout(qm_decoder &d) {
         if (d.flags & QM_EARLY_STOP) {
             s.oAd = off; off = align_up(off + fp * (size_t)s.m * 4);
             s.oAct = off; off = align_up(off + fp * 4);
+            s.oTmask = off; off = align_up(off + fp * 8);  // one word per tile (at most Fpad tiles)
             s.oMap = off; off = align_up(off + fp * 4);
             s.oPerm = off; off = align_up(off + fp * 4);
             s.oIt = off; off = align_up(off + fp * 4);
             s.oCtl = off; off = align_up(off + QM_ET_CTL_WORDS * 4);
+            s.oEmit = off; off = align_up(off + fp * 4);
             // packed hard decisions: max(FT, 8) bits per tile and node, at
             // most one byte per frame and node (FT = 1), whatever the tuning
             s.oPA = off; off = align_up(off + fp * (size_t)s.n);
@@ -276,9 +278,13 @@ int take_event(qm_decoder &d, hipEvent_t *ev, size_t *index) {
 // degree-1 APP of every check that has a degree-1 column, every sweep)
 void layer_work(const Slot &s, const RowDesc *hrows, int nrows, size_t msg, double *bytes, double *checks,
                 bool early = false) {
-    const double per_edge = 8.0 + 2.0 * (double)msg;  // APP read + write, message read + write
+    // per check and frame: APP read + write and message read + write per
+    // degree>=2 edge, plus K read (4); early termination reads the degree-1
+    // LLR instead of K (4) and writes the degree-1 APP (4), plus its packed
+    // syndrome bits (one bit per frame)
+    const double per_edge = 8.0 + 2.0 * (double)msg;
     double b = 0.0;
-    for (int r = 0; r < nrows; ++r) b += per_edge * hrows[r].d + 4.0 + ((early && hrows[r].d1col >= 0) ? 8.0 : 0.0);
+    for (int r = 0; r < nrows; ++r) b += per_edge * hrows[r].d + (early ? 8.125 : 4.0);
     const double fz = (double)s.F * s.code->Z;
     *bytes = b * fz;
     *checks = (double)nrows * fz;
@@ -359,7 +365,8 @@ struct ProfScope {
     }
 };
 
-int enqueue_init(qm_decoder &d, const float *llr, const uint8_t *syn, hipStream_t st) {
+// early: an early-terminating decode, whose layer kernel forms K itself
+int enqueue_init(qm_decoder &d, const float *llr, const uint8_t *syn, hipStream_t st, bool early = false) {
     size_t on = 0, om = 0;
     const size_t msg = msg_bytes(d);
     for (Slot &s : d.slots) {
@@ -369,7 +376,7 @@ int enqueue_init(qm_decoder &d, const float *llr, const uint8_t *syn, hipStream_
         const SlotBufs b = slot_bufs(d, s);
         QM_HIP(qm_launch_to_tiles_f32(llr + on, b.A, s.F, s.n, g.ft_log2, g.ntiles, st));
         QM_HIP(qm_launch_to_tiles_u8(syn + om, b.S, s.F, s.m, g.ft_log2, g.ntiles, st));
-        QM_HIP(qm_launch_kappa(b.A, b.S, b.K, b.rows, c.mb, g, st));
+        if (!early) QM_HIP(qm_launch_kappa(b.A, b.S, b.K, b.rows, c.mb, g, st));
         const size_t rbytes = align_up((size_t)s.Fpad * c.nent1 * c.Z * msg);
         QM_HIP(qm_launch_fill_u32(reinterpret_cast<uint32_t *>(b.R), 0u, rbytes / 4, st));
         QM_HIP(qm_launch_fill_u32(b.fail, 0u, (size_t)s.Fpad, st));
@@ -712,37 +719,49 @@ int enqueue_early_slot(qm_decoder &d, Slot &s, int32_t T, uint8_t *hard, float *
     const size_t msg = msg_bytes(d);
     float *Ad = reinterpret_cast<float *>(d.ws + s.oAd);
     uint32_t *act = reinterpret_cast<uint32_t *>(d.ws + s.oAct);
+    uint64_t *tmask = reinterpret_cast<uint64_t *>(d.ws + s.oTmask);
     int32_t *map = reinterpret_cast<int32_t *>(d.ws + s.oMap);
     int32_t *perm = reinterpret_cast<int32_t *>(d.ws + s.oPerm);
     int32_t *it = reinterpret_cast<int32_t *>(d.ws + s.oIt);
     int32_t *ctl = reinterpret_cast<int32_t *>(d.ws + s.oCtl);
+    int32_t *emit = reinterpret_cast<int32_t *>(d.ws + s.oEmit);
     uint8_t *PA = reinterpret_cast<uint8_t *>(d.ws + s.oPA);
     uint8_t *Pd = reinterpret_cast<uint8_t *>(d.ws + s.oPd);
-    QM_HIP(qm_launch_et_init(act, map, it, ctl, s.Fpad, g.ntiles, st));
+    QM_HIP(qm_launch_et_init(act, tmask, map, it, ctl, s.Fpad, g.ntiles, g.ft_log2, st));
     QM_HIP(qm_launch_commit_d1(b.A, Ad, 0, b.rows, c.mb, g, st));  // Ad = LLR_d
     uint8_t *PS = reinterpret_cast<uint8_t *>(d.ws + s.oPS);
     LayerArgs la = layer_args(d, s);
-    // channel hard decisions and syndrome bits, packed; each sweep rewrites
-    // the decisions, a compaction the syndrome bits
-    QM_HIP(qm_launch_pack_signs(b.A, PA, s.n, la.fpl, g, st));
+    // packed hard decisions (the degree>=2 variables' before every test, the
+    // degree-1 ones here and then by every sweep) and syndrome bits (here and
+    // after every compaction)
     QM_HIP(qm_launch_pack_signs(Ad, Pd, s.m, la.fpl, g, st));
     QM_HIP(qm_launch_pack_syndrome(b.S, PS, nullptr, 0, la.fpl, g, st));
-    const CompactArray arr[QM_COMPACT_ARRAYS] = {
-        {b.A, s.n, 4}, {b.R, (int64_t)c.nent1 * c.Z, (int32_t)msg}, {b.K, s.m, 4}, {b.S, s.m, 1}, {Ad, s.m, 4}};
+    // the per-node state of a decoding frame (K is not used: the layer
+    // kernel forms it from Ad and the syndrome bits)
+    const CompactArray arr[] = {
+        {b.A, s.n, 4}, {b.R, (int64_t)c.nent1 * c.Z, (int32_t)msg}, {b.S, s.m, 1}, {Ad, s.m, 4}};
+    const int narr = (int)(sizeof(arr) / sizeof(arr[0]));
+    const int32_t *cols1 = reinterpret_cast<const int32_t *>(d.ws + s.oCols1);
+    // gl: the geometry with ntiles = an upper bound of ctl[1] known to the
+    // host (the live-tile count only falls, so any count read back earlier
+    // in stream order bounds it); grids cover those tiles alone
+    TileGeom gl = g;
     auto test = [&](int t) -> int {
-        QM_HIP(qm_launch_syndrome_packed(PA, Pd, PS, b.rows, c.mb, b.fail, ctl, la.fpl, g, st));
-        QM_HIP(qm_launch_et_plan(b.fail, act, map, perm, it, ctl, s.Fpad, g.ft_log2, t, 0, st));
-        QM_HIP(qm_launch_compact(arr, QM_COMPACT_ARRAYS, perm, ctl, s.Fpad, g.ft_log2, st));
-        QM_HIP(qm_launch_pack_syndrome(b.S, PS, ctl, 1, la.fpl, g, st));
+        QM_HIP(qm_launch_pack_cols(b.A, PA, cols1, (int)s.cols1.size(), ctl, la.fpl, gl, st));
+        QM_HIP(qm_launch_syndrome_packed(PA, Pd, PS, b.rows, c.mb, b.fail, ctl, la.fpl, gl, st));
+        QM_HIP(qm_launch_et_plan(b.fail, act, tmask, map, perm, it, emit, flags, s.F, ctl, s.Fpad, g.ft_log2, t, 0, st));
+        QM_HIP(qm_launch_emit(b.A, emit, ctl, app, hard, gl, st));
+        QM_HIP(qm_launch_compact(arr, narr, perm, ctl, g.ft_log2, st));
+        QM_HIP(qm_launch_pack_syndrome(b.S, PS, ctl, 1, la.fpl, gl, st));
         return QM_OK;
     };
     int rc = test(0);
     if (rc != QM_OK) return rc;
     la.Ad = Ad;
-    la.act = act;
+    la.tmask = tmask;
     la.ctl = ctl;
-    la.PA = PA;
     la.Pd = Pd;
+    la.PS = PS;
     la.last = 0;
     const RowDesc *rows = b.rows;
     const int G = (int)s.gptr.size() - 1;
@@ -760,6 +779,7 @@ int enqueue_early_slot(qm_decoder &d, Slot &s, int32_t T, uint8_t *hard, float *
             for (int p = p_lo; p < p_hi; p += step) {
                 la.rows = rows + p;
                 la.nrows = step;
+                la.ntiles = gl.ntiles;
                 QM_HIP(qm_launch_layer_et(la, msgk, s.maxd_t, la.fpl, d.tun.block, d.tun.stream_hint, st));
                 double bb, ch;
                 layer_work(s, s.hrows.data() + p, step, msg, &bb, &ch, true);
@@ -774,17 +794,18 @@ int enqueue_early_slot(qm_decoder &d, Slot &s, int32_t T, uint8_t *hard, float *
             if (pending >= 0) {
                 QM_HIP(hipEventSynchronize(d.poll_ev[pending]));
                 if (d.h_poll[pending] == 0) break;
+                // the poll holds ctl[0] (frames still decoding); ctl[1] = ceil(ctl[0] / FT)
+                const int32_t live = (d.h_poll[pending] + (1 << g.ft_log2) - 1) >> g.ft_log2;
+                gl.ntiles = std::min(gl.ntiles, live);
             }
             pending = pending < 0 ? 0 : 1 - pending;
             QM_HIP(hipMemcpyAsync(&d.h_poll[pending], ctl, 4, hipMemcpyDeviceToHost, st));
             QM_HIP(hipEventRecord(d.poll_ev[pending], st));
         }
     }
-    // frames still decoding ran all T sweeps
-    QM_HIP(qm_launch_et_plan(b.fail, act, map, perm, it, ctl, s.Fpad, g.ft_log2, T, 1, st));
-    QM_HIP(qm_launch_commit_d1(b.A, Ad, 1, b.rows, c.mb, g, st));  // degree-1 APPs into A
-    QM_HIP(qm_launch_syndrome(b.A, nullptr, b.S, b.rows, c.mb, b.fail, g, st));
-    QM_HIP(qm_launch_finalize(b.A, b.fail, app, hard, flags, s.F, g, st, map));
+    // frames still decoding ran all T sweeps and failed the last test
+    QM_HIP(qm_launch_et_plan(b.fail, act, tmask, map, perm, it, emit, flags, s.F, ctl, s.Fpad, g.ft_log2, T, 1, st));
+    QM_HIP(qm_launch_emit(b.A, emit, ctl, app, hard, gl, st));
     if (iters_out && s.F > 0)
         QM_HIP(hipMemcpyAsync(iters_out, it, (size_t)s.F * 4, hipMemcpyDeviceToDevice, st));
     return QM_OK;
@@ -1233,7 +1254,7 @@ int qm_decode_early(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t
         QM_HIP(hipEventCreateWithFlags(&d->poll_ev[0], hipEventDisableTiming));
         QM_HIP(hipEventCreateWithFlags(&d->poll_ev[1], hipEventDisableTiming));
     }
-    int rc = enqueue_init(*d, llr, syn, st);
+    int rc = enqueue_init(*d, llr, syn, st, true);
     if (rc != QM_OK) return rc;
     size_t on = 0, of = 0;
     for (Slot &s : d->slots) {

@@ -70,13 +70,11 @@ __global__ void __launch_bounds__(256) k_to_tiles(const T *__restrict__ in, T *_
 }
 
 // Frame tiles -> frame-major APP and hard decisions (step 4: c = [APP < 0]);
-// also the per-frame flags from the syndrome pass.
-// map (may be null): frame held by each slot (early termination reorders
-// slots); slots whose frame is >= F are padding.
+// also the per-frame flags from the syndrome pass.  Slots whose frame is
+// >= F are padding.
 __global__ void __launch_bounds__(256) k_finalize(const float *__restrict__ A, const uint32_t *__restrict__ fail,
                                                   float *__restrict__ app, uint8_t *__restrict__ hard,
-                                                  uint8_t *__restrict__ flags, int F, int64_t N, int ftl,
-                                                  const int32_t *__restrict__ map) {
+                                                  uint8_t *__restrict__ flags, int F, int64_t N, int ftl) {
     __shared__ float lds[64][65];
     const int tile = blockIdx.y;
     const int64_t v0 = (int64_t)blockIdx.x * 64;
@@ -89,7 +87,7 @@ __global__ void __launch_bounds__(256) k_finalize(const float *__restrict__ A, c
     }
     __syncthreads();
     for (int fl = tid >> 6; fl < FT; fl += 4) {
-        const int f = map ? map[tile * FT + fl] : tile * FT + fl;
+        const int f = tile * FT + fl;
         const int64_t v = v0 + (tid & 63);
         if (f < F && v < N) {
             const float x = lds[fl][tid & 63];
@@ -100,8 +98,7 @@ __global__ void __launch_bounds__(256) k_finalize(const float *__restrict__ A, c
     if (blockIdx.x == 0 && blockIdx.y == 0) {
         const int Fpad = (int)gridDim.y * FT;
         for (int sl = tid; sl < Fpad; sl += 256) {
-            const int f = map ? map[sl] : sl;
-            if (f < F) flags[f] = fail[sl] == 0u ? 1 : 0;
+            if (sl < F) flags[sl] = fail[sl] == 0u ? 1 : 0;
         }
     }
 }
@@ -256,32 +253,84 @@ __global__ void __launch_bounds__(256) k_syndrome_packed(const uint8_t *__restri
     }
 }
 
-// Packed hard decisions of every node of the tiles (bit order qm_pack_bit).
-__global__ void __launch_bounds__(256) k_pack_signs(const float *__restrict__ X, uint8_t *__restrict__ P, int64_t N,
-                                                    int ftl, int fpl) {
-    const int tile = blockIdx.y;
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= N) return;
+// Wave-cooperative packing of frame bits (order qm_pack_bit).  One pass of
+// a wave covers 64 / FT consecutive nodes: lane L reads the frame that owns
+// bit L mod FT of node L / FT, so the wave's reads span one contiguous
+// segment of 64 elements; one ballot then holds the packed fields of all
+// those nodes side by side, and the first lane of each field stores it.
+// U passes per wave keep U loads in flight.
+struct NegBit {
+    __device__ bool operator()(float x) const { return x < 0.0f; }
+};
+struct LowBit {
+    __device__ bool operator()(uint8_t x) const { return (x & 1u) != 0u; }
+};
+constexpr int kPackU = 4;
+
+template <int U, typename T, typename Bit>
+__device__ __forceinline__ void pack_wave(const T *__restrict__ X, uint8_t *__restrict__ P, int64_t node0,
+                                          int64_t nend, int ftl, int fpl) {
+    const int lane = (int)(threadIdx.x & 63u);
     const int FT = 1 << ftl;
-    const float *x = X + (((int64_t)tile * N + v) << ftl);
-    uint64_t w = 0;
-    for (int f = 0; f < FT; ++f) w |= (uint64_t)(x[f] < 0.0f) << qm_pack_bit(f, ftl, fpl);
-    store_packed(P, (int64_t)tile * N + v, qm_pack_bytes(ftl), w);
+    const int b = lane & (FT - 1);
+    const int lpc = FT / fpl;
+    const int fl = (b % lpc) * fpl + b / lpc;  // the frame whose decision is bit b
+    const int esz = qm_pack_bytes(ftl);
+    const uint64_t mask = FT >= 64 ? ~0ull : (1ull << FT) - 1ull;
+    const int npw = 64 >> ftl;
+    if (node0 >= nend) return;  // wave-uniform
+    // all U loads first, so they are in flight together; a node past the end
+    // reads the last node (node0 < nend here) and its bit is dropped
+    T x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        int64_t node = node0 + (int64_t)u * npw + (lane >> ftl);
+        node = node < nend ? node : nend - 1;
+        x[u] = X[(node << ftl) + fl];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t node = node0 + (int64_t)u * npw + (lane >> ftl);
+        const uint64_t w = __ballot(node < nend && Bit()(x[u]));
+        if (b == 0 && node < nend) store_packed(P, node, esz, (w >> (lane - b)) & mask);
+    }
 }
 
-// Packed syndrome bits of the tiles below ctl[1] (all tiles if ctl is null).
+// first node of this wave's kPackU passes
+__device__ __forceinline__ int64_t pack_node0(int ftl) {
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    return wave * kPackU * (64 >> ftl);
+}
+
+// Packed hard decisions of every node of the tiles.
+__global__ void __launch_bounds__(256) k_pack_signs(const float *__restrict__ X, uint8_t *__restrict__ P, int64_t N,
+                                                    int ftl, int fpl) {
+    const int64_t tile = blockIdx.y;
+    pack_wave<kPackU, float, NegBit>(X + ((tile * N) << ftl), P + tile * N * qm_pack_bytes(ftl), pack_node0(ftl), N,
+                                     ftl, fpl);
+}
+
+// Packed hard decisions of the degree>=2 columns (cols1) of the tiles that
+// still decode (below ctl[1]), after a sweep.
+__global__ void __launch_bounds__(256) k_pack_cols(const float *__restrict__ A, uint8_t *__restrict__ P,
+                                                   const int32_t *cols1, int Z, int64_t n, int ftl, int fpl,
+                                                   const int32_t *ctl) {
+    const int64_t tile = blockIdx.z;
+    if (tile >= ctl[1]) return;
+    const int64_t base = (int64_t)cols1[blockIdx.y] * Z;
+    pack_wave<kPackU, float, NegBit>(A + ((tile * n) << ftl), P + tile * n * qm_pack_bytes(ftl),
+                                     base + pack_node0(ftl), base + Z, ftl, fpl);
+}
+
+// Packed syndrome bits (same order) of the tiles below ctl[1] (all tiles if
+// ctl is null).
 __global__ void __launch_bounds__(256) k_pack_syndrome(const uint8_t *__restrict__ Sil, uint8_t *__restrict__ PS,
                                                        int64_t m, int ftl, int fpl, const int32_t *ctl,
                                                        int after_compaction) {
-    const int tile = blockIdx.y;
+    const int64_t tile = blockIdx.y;
     if (ctl && (tile >= ctl[1] || (after_compaction && ctl[2] == 0))) return;
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= m) return;
-    const int FT = 1 << ftl;
-    const uint8_t *sp = Sil + (((int64_t)tile * m + c) << ftl);
-    uint64_t w = 0;
-    for (int f = 0; f < FT; ++f) w |= (uint64_t)(sp[f] & 1u) << qm_pack_bit(f, ftl, fpl);
-    store_packed(PS, (int64_t)tile * m + c, qm_pack_bytes(ftl), w);
+    pack_wave<kPackU, uint8_t, LowBit>(Sil + ((tile * m) << ftl), PS + tile * m * qm_pack_bytes(ftl), pack_node0(ftl),
+                                       m, ftl, fpl);
 }
 
 // ---------------------------------------------------------------------------
@@ -292,18 +341,19 @@ __global__ void __launch_bounds__(256) k_pack_syndrome(const uint8_t *__restrict
 // still decoding are moved to the leading slots (stable order) and the
 // stopped ones behind them, so the layer launches skip the trailing tiles.
 // ---------------------------------------------------------------------------
-__global__ void k_et_init(uint32_t *act, int32_t *map, int32_t *iters, int32_t *ctl, int Fpad, int ntiles) {
+__global__ void k_et_init(uint32_t *act, uint64_t *tmask, int32_t *map, int32_t *iters, int32_t *ctl, int Fpad,
+                          int ntiles, int ftl) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < Fpad) {
         act[i] = 1u;
         map[i] = i;
         iters[i] = 0;
     }
+    if (i < ntiles) tmask[i] = ftl >= 6 ? ~0ull : (1ull << (1 << ftl)) - 1ull;
     if (i == 0) {
         ctl[0] = Fpad;
         ctl[1] = ntiles;
-        ctl[2] = 0;
-        ctl[3] = 0;
+        for (int w = 2; w < QM_ET_CTL_WORDS; ++w) ctl[w] = 0;
     }
 }
 
@@ -324,37 +374,63 @@ __device__ __forceinline__ int block_rank(bool pred, int *total, int *wcnt) {
     return off + lane_rank;
 }
 
-// One workgroup of 256 lanes.  t = sweeps done.  final_pass: record t for
-// every frame still decoding.  Otherwise stop the frames whose syndrome
-// passed and, when that empties at least one tile, plan a compaction: the
-// k-th stopped slot below nact_new (in slot order) trades places with the
-// k-th decoding slot at or above it, every other slot stays.  Clears fail
-// for the next test.
-__global__ void __launch_bounds__(256) k_et_plan(uint32_t *fail, uint32_t *act, int32_t *map, int32_t *perm,
-                                                 int32_t *iters, int32_t *ctl, int Fpad, int ftl, int t,
-                                                 int final_pass) {
+// One workgroup of 256 lanes.  t = sweeps done.  Frames whose syndrome
+// passed stop: iterations t, flag 1.  final_pass (after the test of the last
+// sweep): every frame still decoding stops too, with flag 0.  emit[slot] =
+// the frame (< F) that stopped at that slot in this call, else -1, and
+// ctl[4] = how many: their outputs are written from those slots before any
+// data moves.  When the stopped frames free at least one tile, plan a
+// compaction: the k-th stopped slot below alive (in slot order) receives the
+// k-th decoding slot at or above alive (perm[dst] = src, and perm[s] = s for
+// the other slots in [ctl[3], alive)).  Clears fail for the next test.
+// act[slot] and tmask[tile] (bit fl = slot tile*FT + fl) take the new live
+// state on every path.
+__device__ __forceinline__ void plan_commit(const uint8_t *s_act, uint32_t *act, uint64_t *tmask, int Fpad, int ftl) {
+    __syncthreads();
+    const int tid = threadIdx.x;
+    for (int sl = tid; sl < Fpad; sl += 256) act[sl] = s_act[sl];
+    const int FT = 1 << ftl;
+    for (int tl = tid; tl < (Fpad >> ftl); tl += 256) {
+        uint64_t m = 0;
+        for (int fl = 0; fl < FT; ++fl) m |= (uint64_t)s_act[(tl << ftl) + fl] << fl;
+        tmask[tl] = m;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_et_plan(uint32_t *fail, uint32_t *act, uint64_t *tmask, int32_t *map,
+                                                 int32_t *perm, int32_t *iters, int32_t *emit, uint8_t *flags, int F,
+                                                 int32_t *ctl, int Fpad, int ftl, int t, int final_pass) {
     __shared__ uint8_t s_act[QM_ET_MAXF];
     __shared__ int16_t s_map[QM_ET_MAXF];
     __shared__ int16_t s_hole[QM_ET_MAXF];
     __shared__ int wcnt[4];
+    __shared__ int s_emitted;
     const int tid = threadIdx.x;
     const int nold = ctl[0];
+    if (tid == 0) s_emitted = 0;
+    __syncthreads();
+    int emitted = 0;
     for (int sl = tid; sl < Fpad; sl += 256) {
         bool a = act[sl] != 0u;
         const int fr = map[sl];
-        if (a && sl < nold) {
-            if (final_pass) {
-                iters[fr] = t;
-            } else if (fail[sl] == 0u) {
-                a = false;
-                iters[fr] = t;
+        int e = -1;
+        if (a && sl < nold && (final_pass || fail[sl] == 0u)) {
+            a = false;
+            iters[fr] = t;
+            if (fr < F) {
+                flags[fr] = final_pass ? 0 : 1;
+                e = fr;
+                ++emitted;
             }
         }
         s_act[sl] = a ? 1 : 0;
         s_map[sl] = (int16_t)fr;
+        emit[sl] = e;
         fail[sl] = 0u;
     }
+    if (emitted) atomicAdd(&s_emitted, emitted);
     __syncthreads();
+    if (tid == 0) ctl[4] = s_emitted;
     int alive = 0;
     for (int base = 0; base < nold; base += 256) {
         const int sl = base + tid;
@@ -364,17 +440,14 @@ __global__ void __launch_bounds__(256) k_et_plan(uint32_t *fail, uint32_t *act, 
     }
     const int FT = 1 << ftl;
     const int tiles_old = (nold + FT - 1) >> ftl, tiles_new = (alive + FT - 1) >> ftl;
-    if (final_pass || tiles_new == tiles_old) {
-        for (int sl = tid; sl < Fpad; sl += 256) act[sl] = s_act[sl];
-        if (tid == 0) ctl[2] = 0;
-        return;
-    }
-    if (alive == 0) {
-        // nothing left to decode: no data moves
-        for (int sl = tid; sl < Fpad; sl += 256) act[sl] = 0u;
+    if (alive == 0 || (!final_pass && tiles_new == tiles_old)) {
+        // no data moves (alive == 0: nothing left to decode)
+        plan_commit(s_act, act, tmask, Fpad, ftl);
         if (tid == 0) {
-            ctl[0] = 0;
-            ctl[1] = 0;
+            if (alive == 0) {
+                ctl[0] = 0;
+                ctl[1] = 0;
+            }
             ctl[2] = 0;
         }
         return;
@@ -392,7 +465,7 @@ __global__ void __launch_bounds__(256) k_et_plan(uint32_t *fail, uint32_t *act, 
     __syncthreads();
     if (nh == 0) {
         // the stopped frames already sit behind every decoding one
-        for (int sl = tid; sl < Fpad; sl += 256) act[sl] = s_act[sl];
+        plan_commit(s_act, act, tmask, Fpad, ftl);
         if (tid == 0) {
             ctl[0] = alive;
             ctl[1] = tiles_new;
@@ -400,7 +473,10 @@ __global__ void __launch_bounds__(256) k_et_plan(uint32_t *fail, uint32_t *act, 
         }
         return;
     }
-    // decoding slots at or above alive trade places with them
+    const int lo = ((int)s_hole[0] >> ftl) << ftl;
+    for (int sl = lo + tid; sl < alive; sl += 256) perm[sl] = sl;
+    __syncthreads();
+    // decoding slots at or above alive fill the holes, in order
     int nm = 0;
     for (int base = alive; base < nold; base += 256) {
         const int sl = base + tid;
@@ -410,82 +486,109 @@ __global__ void __launch_bounds__(256) k_et_plan(uint32_t *fail, uint32_t *act, 
         if (mv) {
             const int h = s_hole[nm + r];
             perm[h] = sl;
-            perm[sl] = h;
             map[h] = s_map[sl];
-            map[sl] = s_map[h];
         }
         nm += tot;
     }
-    const int lo = ((int)s_hole[0] >> ftl) << ftl;
-    for (int sl = tid; sl < Fpad; sl += 256) {
-        const bool moved = sl < nold && (sl < alive ? !s_act[sl] : (bool)s_act[sl]);
-        if (sl >= lo && sl < nold && !moved) perm[sl] = sl;
-        act[sl] = sl < alive ? 1u : 0u;
-    }
+    __syncthreads();  // every mover has read s_act
+    for (int sl = tid; sl < Fpad; sl += 256) s_act[sl] = sl < alive ? 1 : 0;
+    plan_commit(s_act, act, tmask, Fpad, ftl);
     if (tid == 0) {
         ctl[0] = alive;
         ctl[1] = tiles_new;
-        ctl[2] = nold;
+        ctl[2] = 1;
         ctl[3] = lo;
     }
 }
 
-// Move slot perm[s] to slot s for ctl[3] <= s < ctl[2] in every array, in place: a
-// workgroup owns a run of nb nodes of one array across all slots, stages it
-// in LDS and writes it back permuted (both sides contiguous per tile).
+// Outputs of the frames that stopped in the last planning call, read from
+// their slots before any data moves: frame-major APPs and hard decisions
+// (step 4: c = [APP < 0]), as k_finalize writes them.  Grid-stride over
+// (run of 64 nodes, tile) items of the first ntiles tiles; a tile without
+// an emitted slot is skipped.
+__global__ void __launch_bounds__(256) k_emit(const float *__restrict__ A, const int32_t *__restrict__ emit,
+                                              const int32_t *ctl, float *__restrict__ app,
+                                              uint8_t *__restrict__ hard, int64_t N, int ftl, int ntiles) {
+    if (ctl[4] == 0) return;
+    __shared__ float lds[64][65];
+    __shared__ int32_t s_fr[64];
+    const int FT = 1 << ftl;
+    const int tid = threadIdx.x;
+    const int64_t items = ((N + 63) >> 6) * ntiles;
+    for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+        const int tile = (int)(it % ntiles);
+        const int64_t v0 = (it / ntiles) << 6;
+        __syncthreads();  // the previous item is done with s_fr and lds
+        if (tid < FT) s_fr[tid] = emit[tile * FT + tid];
+        __syncthreads();
+        bool any = false;
+        for (int fl = 0; fl < FT; ++fl) any = any || s_fr[fl] >= 0;
+        if (!any) continue;
+        const float *a = A + ((int64_t)tile * N + v0) * FT;
+        for (int e = tid; e < (64 << ftl); e += 256) {
+            const int vv = e >> ftl;
+            lds[e & (FT - 1)][vv] = (v0 + vv < N) ? a[e] : 0.0f;
+        }
+        __syncthreads();
+        for (int fl = tid >> 6; fl < FT; fl += 4) {
+            const int f = s_fr[fl];
+            const int64_t v = v0 + (tid & 63);
+            if (f >= 0 && v < N) {
+                const float x = lds[fl][tid & 63];
+                if (app) app[(int64_t)f * N + v] = x;
+                hard[(int64_t)f * N + v] = x < 0.0f ? 1 : 0;
+            }
+        }
+    }
+}
+
+// Gather the frames still decoding into the holes below alive = ctl[0]: for
+// every slot s in [ctl[3], alive) with perm[s] != s, element s of every
+// array takes element perm[s] (a slot >= alive, so no element is both read
+// and written).  The stopped frames' elements are not kept: their outputs
+// were written when they stopped.  Grid-stride over chunks of 256 elements
+// of one tile's range; each lane walks the destination tiles.
 struct CompactArgs {
     CompactArray arr[QM_COMPACT_ARRAYS];
-    int64_t chunk_end[QM_COMPACT_ARRAYS];  // cumulative node-run counts
-    int32_t narr, nb, ftl, Fpad;
+    int64_t chunk_end[QM_COMPACT_ARRAYS];  // cumulative chunk counts
+    int32_t narr, ftl;
     const int32_t *perm;
     const int32_t *ctl;
 };
 
 template <typename T>
-__device__ __forceinline__ void compact_run(T *p, int64_t N, int64_t n0, int nb, int ftl, int Fpad, int lo, int hi,
-                                            const int32_t *sperm, uint32_t *lds) {
+__device__ __forceinline__ void gather_elem(T *p, int64_t N, int64_t e, int ftl, int lo, int alive,
+                                            const int32_t *perm) {
+    if (e >= (N << ftl)) return;
     const int FT = 1 << ftl;
-    const int t0 = lo >> ftl, ntl = ((hi + FT - 1) >> ftl) - t0;
-    const int per_tile = nb << ftl;
-    const int tot = ntl * per_tile;
-    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-        const int tile = t0 + e / per_tile, w = e % per_tile;
-        const int nl = w >> ftl, sl = (tile << ftl) + (w & (FT - 1));
-        const int64_t node = n0 + nl;
-        if (node < N && sl < hi) lds[nl * Fpad + sl] = (uint32_t)p[(((int64_t)tile * N + node) << ftl) + (w & (FT - 1))];
+    const int fl = (int)(e & (FT - 1));
+    const int64_t node = e >> ftl;
+    const int t1 = (alive + FT - 1) >> ftl;
+    for (int tile = lo >> ftl; tile < t1; ++tile) {
+        const int sl = (tile << ftl) + fl;
+        if (sl < lo || sl >= alive) continue;
+        const int src = perm[sl];
+        if (src == sl) continue;
+        p[((int64_t)tile * N << ftl) + e] = p[((((int64_t)(src >> ftl)) * N + node) << ftl) + (src & (FT - 1))];
     }
-    __syncthreads();
-    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-        const int tile = t0 + e / per_tile, w = e % per_tile;
-        const int nl = w >> ftl, sl = (tile << ftl) + (w & (FT - 1));
-        const int64_t node = n0 + nl;
-        if (node < N && sl < hi) p[(((int64_t)tile * N + node) << ftl) + (w & (FT - 1))] = (T)lds[nl * Fpad + sperm[sl]];
-    }
-    __syncthreads();
 }
 
 __global__ void __launch_bounds__(256) k_compact(const CompactArgs c) {
-    const int hi = c.ctl[2];
-    if (hi == 0) return;
-    const int lo = c.ctl[3];
-    extern __shared__ uint32_t dyn[];
-    int32_t *sperm = reinterpret_cast<int32_t *>(dyn);
-    uint32_t *lds = dyn + c.Fpad;
-    for (int i = lo + (int)threadIdx.x; i < hi; i += blockDim.x) sperm[i] = c.perm[i];
-    __syncthreads();
+    if (c.ctl[2] == 0) return;
+    const int alive = c.ctl[0], lo = c.ctl[3];
     const int64_t total = c.chunk_end[c.narr - 1];
     for (int64_t ch = blockIdx.x; ch < total; ch += gridDim.x) {
         int a = 0;
         while (ch >= c.chunk_end[a]) ++a;
         const int64_t first = a ? c.chunk_end[a - 1] : 0;
-        const int64_t n0 = (ch - first) * c.nb;
+        const int64_t e = (ch - first) * 256 + threadIdx.x;
         const CompactArray &A = c.arr[a];
         if (A.esz == 4)
-            compact_run(static_cast<uint32_t *>(A.p), A.N, n0, c.nb, c.ftl, c.Fpad, lo, hi, sperm, lds);
+            gather_elem(static_cast<uint32_t *>(A.p), A.N, e, c.ftl, lo, alive, c.perm);
         else if (A.esz == 2)
-            compact_run(static_cast<uint16_t *>(A.p), A.N, n0, c.nb, c.ftl, c.Fpad, lo, hi, sperm, lds);
+            gather_elem(static_cast<uint16_t *>(A.p), A.N, e, c.ftl, lo, alive, c.perm);
         else
-            compact_run(static_cast<uint8_t *>(A.p), A.N, n0, c.nb, c.ftl, c.Fpad, lo, hi, sperm, lds);
+            gather_elem(static_cast<uint8_t *>(A.p), A.N, e, c.ftl, lo, alive, c.perm);
     }
 }
 
@@ -549,7 +652,7 @@ hipError_t qm_launch_layer(const LayerArgs &a, int msgk, int maxd, int fpl, int 
 }
 
 hipError_t qm_launch_layer_et(const LayerArgs &a, int msgk, int maxd, int fpl, int block, int hint, hipStream_t s) {
-    if (!a.Ad || !a.act || !a.ctl) return hipErrorInvalidValue;
+    if (!a.Ad || !a.tmask || !a.ctl) return hipErrorInvalidValue;
     switch (msgk) {
         case QM_MSGK_F32: return qm_layer_f32(a, 1, maxd, fpl, block, hint, s);
         case QM_MSGK_F16: return qm_layer_f16(a, 1, maxd, fpl, block, hint, s);
@@ -586,9 +689,9 @@ hipError_t qm_launch_syndrome(const float *A, const float *Ad, const uint8_t *Si
 }
 
 hipError_t qm_launch_finalize(const float *A, const uint32_t *fail, float *app, uint8_t *hard, uint8_t *flags,
-                              int F, const TileGeom &g, hipStream_t s, const int32_t *map) {
+                              int F, const TileGeom &g, hipStream_t s) {
     dim3 grid((unsigned)((g.n + 63) / 64), (unsigned)g.ntiles);
-    hipLaunchKernelGGL(k_finalize, grid, dim3(256), 0, s, A, fail, app, hard, flags, F, g.n, g.ft_log2, map);
+    hipLaunchKernelGGL(k_finalize, grid, dim3(256), 0, s, A, fail, app, hard, flags, F, g.n, g.ft_log2);
     return hipGetLastError();
 }
 
@@ -652,60 +755,84 @@ hipError_t qm_launch_syndrome_packed(const uint8_t *PA, const uint8_t *Pd, const
     return hipGetLastError();
 }
 
+// blocks of 256 lanes for a packing pass over N nodes
+static unsigned pack_blocks(int64_t N, int ftl) {
+    const int64_t per_block = 4LL * kPackU * (64 >> ftl);
+    return (unsigned)((N + per_block - 1) / per_block);
+}
+
 hipError_t qm_launch_pack_signs(const float *X, uint8_t *P, int64_t N, int fpl, const TileGeom &g, hipStream_t s) {
-    if ((1 << g.ft_log2) > 64 || fpl < 1) return hipErrorInvalidValue;
+    if ((1 << g.ft_log2) > 64 || fpl < 1 || fpl > (1 << g.ft_log2)) return hipErrorInvalidValue;
     if (N == 0 || g.ntiles == 0) return hipSuccess;
-    dim3 grid((unsigned)((N + 255) / 256), (unsigned)g.ntiles);
+    dim3 grid(pack_blocks(N, g.ft_log2), (unsigned)g.ntiles);
     hipLaunchKernelGGL(k_pack_signs, grid, dim3(256), 0, s, X, P, N, g.ft_log2, fpl);
+    return hipGetLastError();
+}
+
+hipError_t qm_launch_pack_cols(const float *A, uint8_t *P, const int32_t *cols1, int ncols1, const int32_t *ctl, int fpl,
+                               const TileGeom &g, hipStream_t s) {
+    if ((1 << g.ft_log2) > 64 || fpl < 1 || fpl > (1 << g.ft_log2) || !ctl) return hipErrorInvalidValue;
+    if (ncols1 == 0 || g.ntiles == 0) return hipSuccess;
+    dim3 grid(pack_blocks(g.Z, g.ft_log2), (unsigned)ncols1, (unsigned)g.ntiles);
+    hipLaunchKernelGGL(k_pack_cols, grid, dim3(256), 0, s, A, P, cols1, g.Z, g.n, g.ft_log2, fpl, ctl);
     return hipGetLastError();
 }
 
 hipError_t qm_launch_pack_syndrome(const uint8_t *Sil, uint8_t *PS, const int32_t *ctl, int after_compaction, int fpl,
                                    const TileGeom &g, hipStream_t s) {
-    if ((1 << g.ft_log2) > 64 || fpl < 1) return hipErrorInvalidValue;
+    if ((1 << g.ft_log2) > 64 || fpl < 1 || fpl > (1 << g.ft_log2)) return hipErrorInvalidValue;
     if (g.m == 0 || g.ntiles == 0) return hipSuccess;
-    dim3 grid((unsigned)((g.m + 255) / 256), (unsigned)g.ntiles);
+    dim3 grid(pack_blocks(g.m, g.ft_log2), (unsigned)g.ntiles);
     hipLaunchKernelGGL(k_pack_syndrome, grid, dim3(256), 0, s, Sil, PS, g.m, g.ft_log2, fpl, ctl, after_compaction);
     return hipGetLastError();
 }
 
-hipError_t qm_launch_et_init(uint32_t *act, int32_t *map, int32_t *iters, int32_t *ctl, int Fpad, int ntiles,
-                             hipStream_t s) {
-    hipLaunchKernelGGL(k_et_init, dim3((unsigned)((Fpad + 255) / 256)), dim3(256), 0, s, act, map, iters, ctl, Fpad,
-                       ntiles);
+hipError_t qm_launch_et_init(uint32_t *act, uint64_t *tmask, int32_t *map, int32_t *iters, int32_t *ctl, int Fpad,
+                             int ntiles, int ft_log2, hipStream_t s) {
+    if (ft_log2 < 0 || ft_log2 > 6 || (ntiles << ft_log2) != Fpad) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_et_init, dim3((unsigned)((Fpad + 255) / 256)), dim3(256), 0, s, act, tmask, map, iters, ctl,
+                       Fpad, ntiles, ft_log2);
     return hipGetLastError();
 }
 
-hipError_t qm_launch_et_plan(uint32_t *fail, uint32_t *act, int32_t *map, int32_t *perm, int32_t *iters,
-                             int32_t *ctl, int Fpad, int ft_log2, int t, int final_pass, hipStream_t s) {
-    if (Fpad < 1 || Fpad > QM_ET_MAXF) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_et_plan, dim3(1), dim3(256), 0, s, fail, act, map, perm, iters, ctl, Fpad, ft_log2, t,
-                       final_pass);
+hipError_t qm_launch_et_plan(uint32_t *fail, uint32_t *act, uint64_t *tmask, int32_t *map, int32_t *perm,
+                             int32_t *iters, int32_t *emit, uint8_t *flags, int F, int32_t *ctl, int Fpad, int ft_log2,
+                             int t, int final_pass, hipStream_t s) {
+    if (Fpad < 1 || Fpad > QM_ET_MAXF || F > Fpad || ft_log2 < 0 || ft_log2 > 6 || (Fpad & ((1 << ft_log2) - 1)))
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_et_plan, dim3(1), dim3(256), 0, s, fail, act, tmask, map, perm, iters, emit, flags, F, ctl,
+                       Fpad, ft_log2, t, final_pass);
     return hipGetLastError();
 }
 
-hipError_t qm_launch_compact(const CompactArray *arr, int narr, const int32_t *perm, const int32_t *ctl, int Fpad,
+hipError_t qm_launch_emit(const float *A, const int32_t *emit, const int32_t *ctl, float *app, uint8_t *hard,
+                          const TileGeom &g, hipStream_t s) {
+    if ((1 << g.ft_log2) > 64) return hipErrorInvalidValue;
+    const int64_t items = ((g.n + 63) >> 6) * g.ntiles;
+    if (items == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)std::min<int64_t>(items, 4096);
+    hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(256), 0, s, A, emit, ctl, app, hard, g.n, g.ft_log2, g.ntiles);
+    return hipGetLastError();
+}
+
+hipError_t qm_launch_compact(const CompactArray *arr, int narr, const int32_t *perm, const int32_t *ctl,
                              int ft_log2, hipStream_t s) {
-    if (narr < 1 || narr > QM_COMPACT_ARRAYS || Fpad < 1 || Fpad > QM_ET_MAXF) return hipErrorInvalidValue;
+    if (narr < 1 || narr > QM_COMPACT_ARRAYS) return hipErrorInvalidValue;
     CompactArgs c;
     std::memset(&c, 0, sizeof(c));
-    // nodes per run: the staged run (nb x Fpad words) plus perm stay <= 48 KB
-    c.nb = std::max(1, std::min(64, (12288 - Fpad) / Fpad));
     c.narr = narr;
     c.ftl = ft_log2;
-    c.Fpad = Fpad;
     c.perm = perm;
     c.ctl = ctl;
     int64_t acc = 0;
     for (int i = 0; i < narr; ++i) {
         c.arr[i] = arr[i];
-        acc += (arr[i].N + c.nb - 1) / c.nb;
+        acc += ((arr[i].N << ft_log2) + 255) / 256;
         c.chunk_end[i] = acc;
     }
     if (acc == 0) return hipSuccess;
-    const size_t lds = ((size_t)Fpad + (size_t)c.nb * Fpad) * 4;
-    const unsigned blocks = (unsigned)std::min<int64_t>(acc, 2048);
-    hipLaunchKernelGGL(k_compact, dim3(blocks), dim3(256), lds, s, c);
+    const unsigned blocks = (unsigned)std::min<int64_t>(acc, 8192);
+    hipLaunchKernelGGL(k_compact, dim3(blocks), dim3(256), 0, s, c);
     return hipGetLastError();
 }
 

@@ -36,10 +36,12 @@ template <int FPL>
 struct EtLane {
     bool live[FPL];
     bool all;                 // every frame of the lane is live
+    bool tile_full;           // every frame of the tile is live (wave-uniform)
     bool leader;              // first lane of its check's lane group
-    __amdgpu_buffer_rsrc_t rAd;
-    uint8_t *PA;              // this tile's packed hard decisions per variable
+    __amdgpu_buffer_rsrc_t rAd;  // this tile's channel LLRs of the degree-1 variables, per check
     uint8_t *Pd;              // this tile's packed degree-1 hard decisions per check
+    const uint8_t *PS;        // this tile's packed syndrome bits per check
+    int jl;                   // lane index in its check's lane group
     int lpl;                  // log2(lanes per check)
     int esz;                  // bytes per packed field
 };
@@ -83,9 +85,12 @@ constexpr int kLayered = 0;  // layered sweep (fixed iterations)
 constexpr int kEarly = 1;    // layered sweep with early termination (EtLane)
 constexpr int kFlood = 2;    // flooding: messages only, the APPs of the previous iteration stay
 
-template <typename MsgT, int D, int FPL, int AUX, int MODE>
+// MASK (early termination only): some frame of the tile has stopped, so
+// stores go through the per-frame live mask; otherwise they are plain.
+template <typename MsgT, int D, int FPL, int AUX, int MODE, bool MASK>
 __device__ __forceinline__ void check_update(const LaneCtx &c, ConstRowDesc *rd, int last, const EtLane<FPL> &et) {
     constexpr bool ET = MODE == kEarly;
+    constexpr bool MASKED = ET && MASK;
     typedef MsgIO<MsgT> IO;
     const uint32_t col_bytes = c.colw * 4u;
     const uint32_t msg_col_bytes = c.colw * IO::bytes;
@@ -103,8 +108,28 @@ __device__ __forceinline__ void check_update(const LaneCtx &c, ConstRowDesc *rd,
         ent_so[j] = (uint32_t)rd->ent[j] * msg_col_bytes;
     }
 
+    // kap = K (|K| = Phi(clip|LLR_d|), sign s ^ [LLR_d < 0]; |K| = 0 and sign
+    // s without a degree-1 variable).  Early termination: every sweep may be
+    // a frame's last, so every sweep forms the degree-1 APPs in A, from the
+    // channel LLRs of the degree-1 variables kept per check in Ad; with
+    // those at hand K is formed here from them and the packed syndrome bits
+    // (the same arithmetic as the kernel that fills K) instead of being read.
+    // The Ad load is unconditional (Ad has an entry for every check), so no
+    // branch on the row waits for its descriptor before the first load.
     float kap[FPL];
-    bload_f32<FPL, AUX>(c.rK, vo4, row_so, kap);
+    float lam[FPL];
+    if constexpr (ET) {
+        bload_f32<FPL>(et.rAd, vo4, row_so, lam);
+        const uint64_t sw = load_packed(et.PS, (int64_t)rd->row * c.Z + c.k, et.esz);
+#pragma unroll
+        for (int f = 0; f < FPL; ++f) {
+            const uint32_t sb = (uint32_t)(sw >> ((f << et.lpl) + et.jl)) & 1u;
+            const float mag = d1col >= 0 ? qm_phi(qm_clip(fabsf(lam[f]))) : 0.0f;
+            kap[f] = with_sign(mag, sb ^ (uint32_t)(d1col >= 0 && lam[f] < 0.0f));
+        }
+    } else {
+        bload_f32<FPL, AUX>(c.rK, vo4, row_so, kap);
+    }
     // sign parities are per-lane booleans (lane masks in scalar registers)
     bool neg[FPL];
 #pragma unroll
@@ -151,20 +176,15 @@ __device__ __forceinline__ void check_update(const LaneCtx &c, ConstRowDesc *rd,
             rm[f] = IO::round(nj ? -mag : mag);
             an[f] = q[j][f] + rm[f];
         }
-        store_live<IO, FPL, AUX, ET>(c.rR, vom, ent_so[j], rm, et);
-        if constexpr (MODE != kFlood) store_live<MsgIO<float>, FPL, 0, ET>(c.rA, aoff[j], col_so[j], an, et);
-        if constexpr (ET) {
-            // the variable's packed hard decisions (the last layer of the
-            // sweep that touches it leaves its end-of-sweep signs)
-            const uint64_t w = group_signs<FPL>(an, et.lpl);
-            if (et.leader) store_packed(et.PA, (int64_t)rd->col[j] * c.Z + ((aoff[j] >> 2) >> c.ftl), et.esz, w);
-        }
+        store_live<IO, FPL, AUX, MASKED>(c.rR, vom, ent_so[j], rm, et);
+        if constexpr (MODE != kFlood) store_live<MsgIO<float>, FPL, 0, MASKED>(c.rA, aoff[j], col_so[j], an, et);
+
     }
     if ((ET || last) && d1col >= 0) {
         const uint32_t off = shifted_off(c, d1shift);
         const uint32_t so = (uint32_t)d1col * col_bytes;
-        float lam[FPL], out[FPL];
-        bload_f32<FPL>(c.rA, off, so, lam);
+        float out[FPL];
+        if constexpr (!ET) bload_f32<FPL>(c.rA, off, so, lam);
 #pragma unroll
         for (int f = 0; f < FPL; ++f) {
             // neg = s ^ [lam < 0] ^ xor_j [q_j < 0]; the degree-1 target
@@ -173,27 +193,23 @@ __device__ __forceinline__ void check_update(const LaneCtx &c, ConstRowDesc *rd,
             const float mag = qm_phi(qm_clip(acc[f]));
             out[f] = lam[f] + IO::round(nd ? -mag : mag);
         }
-        // early termination: every sweep may be a frame's last, so the
-        // degree-1 APPs go to their own per-check array and A keeps LLR_d
+        store_live<MsgIO<float>, FPL, 0, MASKED>(c.rA, off, so, out, et);
         if constexpr (ET) {
-            store_live<MsgIO<float>, FPL, 0, ET>(et.rAd, vo4, row_so, out, et);
             const uint64_t w = group_signs<FPL>(out, et.lpl);
             if (et.leader) store_packed(et.Pd, (int64_t)rd->row * c.Z + c.k, et.esz, w);
-        } else {
-            bstore_f32<FPL>(c.rA, off, so, out);
         }
     }
 }
 
-template <typename MsgT, int D, int FPL, int AUX, int MODE>
+template <typename MsgT, int D, int FPL, int AUX, int MODE, bool MASK = false>
 __device__ __forceinline__ void dispatch_degree(int d, const LaneCtx &c, ConstRowDesc *rd, int last,
                                                 const EtLane<FPL> &et) {
     if constexpr (D >= 0) {
         if (d == D) {
-            check_update<MsgT, D, FPL, AUX, MODE>(c, rd, last, et);
+            check_update<MsgT, D, FPL, AUX, MODE, MASK>(c, rd, last, et);
             return;
         }
-        dispatch_degree<MsgT, D - 1, FPL, AUX, MODE>(d, c, rd, last, et);
+        dispatch_degree<MsgT, D - 1, FPL, AUX, MODE, MASK>(d, c, rd, last, et);
     }
 }
 
@@ -235,21 +251,34 @@ __device__ __forceinline__ void layer_body(const LayerArgs &a, int b) {
     ConstRowDesc *rd = as_const(a.rows + rs);
     EtLane<FPL> et;
     if constexpr (ET) {
-        const int slot0 = (tile << c.ftl) + (int)(c.node & ((1u << c.ftl) - 1u));
+        // the tile's live mask is one scalar load, issued with the row
+        // descriptor's (a per-lane load here would be waited for before the
+        // lane's first data load)
+        const uint64_t tm = a.tmask[tile];
+        et.tile_full = tm == (c.ftl >= 6 ? ~0ull : (1ull << (1 << c.ftl)) - 1ull);
+        const int fl0 = (int)(c.node & ((1u << c.ftl) - 1u));
         et.all = true;
 #pragma unroll
         for (int f = 0; f < FPL; ++f) {
-            et.live[f] = a.act[slot0 + f] != 0u;
+            et.live[f] = ((tm >> (fl0 + f)) & 1ull) != 0ull;
             et.all = et.all && et.live[f];
         }
         et.rAd = make_rsrc(a.Ad + (int64_t)tile * a.strideK, (uint32_t)(a.strideK * 4));
         et.lpl = lpl;
         et.leader = (idx & ((1 << lpl) - 1)) == 0;
         et.esz = qm_pack_bytes(c.ftl);
-        et.PA = a.PA + (int64_t)tile * (a.strideA >> c.ftl) * et.esz;
         et.Pd = a.Pd + (int64_t)tile * (a.strideK >> c.ftl) * et.esz;
+        et.PS = a.PS + (int64_t)tile * (a.strideK >> c.ftl) * et.esz;
+        et.jl = idx & ((1 << lpl) - 1);
     }
-    dispatch_degree<MsgT, MAXD, FPL, AUX, MODE>(rd->d, c, rd, a.last, et);
+    if constexpr (ET) {
+        // a wave-uniform choice: tiles whose frames all decode (the common
+        // case) take the body without per-frame masks
+        if (et.tile_full) dispatch_degree<MsgT, MAXD, FPL, AUX, MODE, false>(rd->d, c, rd, a.last, et);
+        else dispatch_degree<MsgT, MAXD, FPL, AUX, MODE, true>(rd->d, c, rd, a.last, et);
+    } else {
+        dispatch_degree<MsgT, MAXD, FPL, AUX, MODE>(rd->d, c, rd, a.last, et);
+    }
 }
 
 template <typename MsgT, int MAXD, int FPL, int AUX>

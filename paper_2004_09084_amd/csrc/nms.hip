@@ -236,16 +236,19 @@ __global__ void __launch_bounds__(256) k_nms_kappa(const float *__restrict__ A, 
 }
 
 // to_A: A[d1col][(k + a) mod Z] = Ad[row][k] (the degree-1 APPs enter the
-// variable array for the final outputs); else Ad = the channel LLRs.
+// variable array for the final outputs); else Ad = the channel LLRs.  A lane
+// moves V adjacent frames of one check (V divides FT).
+template <int V>
 __global__ void __launch_bounds__(256) k_commit_d1(float *__restrict__ A, float *__restrict__ Ad, int to_A,
                                                    const RowDesc *rows, int Z, int ftl, int ntiles, int chunks,
                                                    int64_t strideA, int64_t strideM) {
+    typedef float vec __attribute__((ext_vector_type(V)));
     const int b = blockIdx.x;
     const int tile = b % ntiles;
     const int rest = b / ntiles;
     const int chunk = rest % chunks;
     const int rs = rest / chunks;
-    const int idx = chunk * (int)blockDim.x + (int)threadIdx.x;
+    const int idx = (chunk * (int)blockDim.x + (int)threadIdx.x) * V;
     if (idx >= (Z << ftl)) return;
     ConstRowDesc *rd = as_const(rows + rs);
     if (rd->d1col < 0) return;
@@ -253,12 +256,12 @@ __global__ void __launch_bounds__(256) k_commit_d1(float *__restrict__ A, float 
     const int fl = idx & ((1 << ftl) - 1);
     int v = k + rd->d1shift;
     v = v >= Z ? v - Z : v;
-    const int64_t oa = (int64_t)tile * strideA + (((rd->d1col * Z + v) << ftl) + fl);
-    const int64_t od = (int64_t)tile * strideM + (((rd->row * Z + k) << ftl) + fl);
+    vec *pa = reinterpret_cast<vec *>(A + (int64_t)tile * strideA + (((rd->d1col * Z + v) << ftl) + fl));
+    vec *pd = reinterpret_cast<vec *>(Ad + (int64_t)tile * strideM + (((rd->row * Z + k) << ftl) + fl));
     if (to_A)
-        A[oa] = Ad[od];
+        *pa = *pd;
     else
-        Ad[od] = A[oa];
+        *pd = *pa;
 }
 
 // after a syndrome pass: frames that became valid stop (iterations = done)
@@ -609,11 +612,17 @@ hipError_t qm_launch_nms_bwd(const NmsBwdArgs &ba, int maxd, int fpl, int block,
 
 hipError_t qm_launch_commit_d1(float *A, float *Ad, int to_A, const RowDesc *rows, int mb, const TileGeom &g,
                                hipStream_t s) {
-    const int chunks = ((g.Z << g.ft_log2) + 255) / 256;
+    const int V = g.ft_log2 >= 2 ? 4 : 1;  // 16-byte moves when a node holds >= 4 frames
+    const int chunks = ((g.Z << g.ft_log2) / V + 255) / 256;
     const int64_t blocks = (int64_t)g.ntiles * mb * chunks;
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_commit_d1, dim3((unsigned)blocks), dim3(256), 0, s, A, Ad, to_A, rows, g.Z, g.ft_log2, g.ntiles,
-                       chunks, (int64_t)g.n << g.ft_log2, (int64_t)g.m << g.ft_log2);
+    const int64_t sA = (int64_t)g.n << g.ft_log2, sM = (int64_t)g.m << g.ft_log2;
+    if (V == 4)
+        hipLaunchKernelGGL(k_commit_d1<4>, dim3((unsigned)blocks), dim3(256), 0, s, A, Ad, to_A, rows, g.Z, g.ft_log2,
+                           g.ntiles, chunks, sA, sM);
+    else
+        hipLaunchKernelGGL(k_commit_d1<1>, dim3((unsigned)blocks), dim3(256), 0, s, A, Ad, to_A, rows, g.Z, g.ft_log2,
+                           g.ntiles, chunks, sA, sM);
     return hipGetLastError();
 }
 

@@ -54,14 +54,17 @@ struct LayerArgs {
     int32_t last;             // 1 in the last sweep: also form the degree-1 APPs
     int64_t strideA, strideR, strideK;  // per-tile strides (elements)
     // early termination (null otherwise): every sweep forms the degree-1
-    // APPs into Ad instead of A; frames with act = 0 are left untouched;
-    // tiles at or past ctl[1] are skipped
-    float *Ad;                // [ntiles][m][FT]
-    const uint32_t *act;      // [Fpad] 1 = frame slot still decoding
+    // APPs in A, reading the channel LLRs of the degree-1 variables from Ad;
+    // frames whose tmask bit is 0 are left untouched; tiles at or past ctl[1] are
+    // skipped, and the grid may cover fewer than ntiles tiles (any count
+    // >= ctl[1])
+    const float *Ad;          // [ntiles][m][FT] LLR of each check's degree-1 variable
+    const uint64_t *tmask;    // [ntiles] frames of each tile still decoding (bit fl)
     const int32_t *ctl;       // EtCtl
-    uint8_t *PA;              // [ntiles][n] hard decisions of the FT frames of a variable (bit = frame),
-                              // max(FT, 8) bits each
-    uint8_t *Pd;              // [ntiles][m] the same for the degree-1 variable of each check
+    uint8_t *Pd;              // [ntiles][m] hard decisions of the FT frames of each check's degree-1
+                              // variable (bit = frame), max(FT, 8) bits each
+    const uint8_t *PS;        // [ntiles][m] syndrome bits, packed the same way (K is formed from
+                              // them and Ad; the K array is not read)
 };
 
 // bytes of one packed field of FT = 2^ft_log2 frame bits
@@ -77,9 +80,10 @@ __host__ __device__ inline int qm_pack_bit(int fl, int ft_log2, int fpl) {
 // Device-side control words of an early-terminating decode of one code.
 //   [0] nact: slots >= nact hold stopped frames
 //   [1] tiles that still hold a decoding frame (ceil(nact / FT))
-//   [2], [3] slots [ctl[3], ctl[2]) to permute by perm before the next
-//        sweep (ctl[2] = 0: none)
-#define QM_ET_CTL_WORDS 4
+//   [2] 1: the planning kernel planned a compaction (perm, from slot ctl[3])
+//   [3] first slot the compaction writes
+//   [4] frames that stopped in the last planning call (outputs to write)
+#define QM_ET_CTL_WORDS 8
 // Largest padded frame count of one code in an early-terminating decode
 // (the planning kernel keeps per-slot state in LDS).
 #define QM_ET_MAXF 8192
@@ -156,7 +160,7 @@ hipError_t qm_launch_layer_multi(const MultiLayerArgs &m, int msgk, int maxd, in
 hipError_t qm_launch_syndrome(const float *A, const float *Ad, const uint8_t *Sil, const RowDesc *rows, int mb,
                               uint32_t *fail, const TileGeom &g, hipStream_t s);
 hipError_t qm_launch_finalize(const float *A, const uint32_t *fail, float *app, uint8_t *hard,
-                              uint8_t *flags, int F, const TileGeom &g, hipStream_t s, const int32_t *map = nullptr);
+                              uint8_t *flags, int F, const TileGeom &g, hipStream_t s);
 // LDS-resident decode (lds_sweeps.hip): all T sweeps of F frames in one
 // launch; bytes of LDS it needs per workgroup, and the launch.
 size_t qm_lds_bytes(int ncols1, int Z);
@@ -174,7 +178,8 @@ hipError_t qm_launch_layer_et(const LayerArgs &a, int msgk, int maxd, int fpl, i
 hipError_t qm_launch_syndrome_et(const float *A, const float *Ad, const uint8_t *Sil, const RowDesc *rows, int mb,
                                  uint32_t *fail, const int32_t *ctl, const TileGeom &g, hipStream_t s);
 // Syndrome test from packed hard decisions (early termination): per check,
-// the row's variables' words of PA, the check's word of Pd and the syndrome
+// the row's variables' words of PA (packed hard decisions per variable), the
+// check's word of Pd and the syndrome
 // bytes; tiles at or past ctl[1] are skipped.
 hipError_t qm_launch_syndrome_packed(const uint8_t *PA, const uint8_t *Pd, const uint8_t *PS, const RowDesc *rows,
                                      int mb, uint32_t *fail, const int32_t *ctl, int fpl, const TileGeom &g,
@@ -182,22 +187,30 @@ hipError_t qm_launch_syndrome_packed(const uint8_t *PA, const uint8_t *Pd, const
 // Packed hard decisions of every frame tile: bit qm_pack_bit(fl) of
 // P[tile][node] = [X[tile][node][fl] < 0].
 hipError_t qm_launch_pack_signs(const float *X, uint8_t *P, int64_t N, int fpl, const TileGeom &g, hipStream_t s);
+// Packed hard decisions of the degree>=2 columns of the tiles below ctl[1].
+hipError_t qm_launch_pack_cols(const float *A, uint8_t *P, const int32_t *cols1, int ncols1, const int32_t *ctl, int fpl,
+                               const TileGeom &g, hipStream_t s);
 // Packed syndrome bits (same order) of the tiles below ctl[1]; with
 // after_compaction, only when the planning kernel moved frames (ctl[2] != 0).
 hipError_t qm_launch_pack_syndrome(const uint8_t *Sil, uint8_t *PS, const int32_t *ctl, int after_compaction, int fpl,
                                    const TileGeom &g, hipStream_t s);
-hipError_t qm_launch_et_init(uint32_t *act, int32_t *map, int32_t *iters, int32_t *ctl, int Fpad, int ntiles,
-                             hipStream_t s);
-hipError_t qm_launch_et_plan(uint32_t *fail, uint32_t *act, int32_t *map, int32_t *perm, int32_t *iters,
-                             int32_t *ctl, int Fpad, int ft_log2, int t, int final_pass, hipStream_t s);
-// permute frame slots [ctl[3], ctl[2]) of every per-node array by perm
+hipError_t qm_launch_et_init(uint32_t *act, uint64_t *tmask, int32_t *map, int32_t *iters, int32_t *ctl, int Fpad,
+                             int ntiles, int ft_log2, hipStream_t s);
+hipError_t qm_launch_et_plan(uint32_t *fail, uint32_t *act, uint64_t *tmask, int32_t *map, int32_t *perm,
+                             int32_t *iters, int32_t *emit, uint8_t *flags, int F, int32_t *ctl, int Fpad, int ft_log2,
+                             int t, int final_pass, hipStream_t s);
+// frame-major APPs and hard decisions of the frames the planning kernel
+// stopped (emit[slot] = frame or -1), from the first g.ntiles tiles
+hipError_t qm_launch_emit(const float *A, const int32_t *emit, const int32_t *ctl, float *app, uint8_t *hard,
+                          const TileGeom &g, hipStream_t s);
+// move the planned frames (slot perm[s] into slot s) in every per-node array
 struct CompactArray {
     void *p;                  // [ntiles][N][FT] elements of esz bytes
     int64_t N;
     int32_t esz;              // 1, 2 or 4
 };
 #define QM_COMPACT_ARRAYS 5
-hipError_t qm_launch_compact(const CompactArray *arr, int narr, const int32_t *perm, const int32_t *ctl, int Fpad,
+hipError_t qm_launch_compact(const CompactArray *arr, int narr, const int32_t *perm, const int32_t *ctl,
                              int ft_log2, hipStream_t s);
 // nms.hip
 hipError_t qm_launch_nms_kappa(const float *A, const uint8_t *Sil, float *K, const RowDesc *rows, int mb,

@@ -91,9 +91,12 @@ typedef struct {
     int32_t graph;            /* 1: replay a captured hipGraph (as QM_GRAPH) */
     int32_t frames_per_lane;  /* 1 or 2 adjacent frames per GPU lane (<= frames_per_tile);
                                  0 = default (2).  4 is rejected (QM_ERR_UNSUPPORTED). */
-    int32_t fuse_codes;       /* 1: with several codes (at most 4) and merge = 1, one launch runs
+    int32_t fuse_codes;       /* with several codes (at most 4) and merge = 1: 1, one launch runs
                                  the current layer of every code (each code walks its own layer
-                                 sequence); 0: the codes are swept one after another */
+                                 sequence); 2, each code runs its own layer sequence on its own
+                                 stream, forked from and joined to the decode stream (launches
+                                 of different codes overlap; the default); 0, the codes are swept
+                                 one after another.  Results are bit-identical in every mode. */
     int32_t stream_hint;      /* 1: messages and per-check terms are read and written with the
                                  non-temporal cache policy (they are used once per sweep), so the
                                  APP columns that the next layers reuse stay cached */
@@ -110,6 +113,12 @@ typedef struct {
                                  group's launch fills the ramp-down of another's.  Frames never
                                  depend on other frames, so results are bit-identical.  Not used
                                  by fused mixed batches, flooding or early termination. */
+    int32_t spread_codes;     /* fused mixed batches: 1 (default) spreads each code's layers evenly
+                                 over the launches (the code with the most layers runs in every
+                                 launch, a code with a third as many in every third), so every
+                                 launch carries a similar share of the traffic; 0 runs every code
+                                 from the first launch until its layers are done.  Each code
+                                 keeps its own layer order, so results are bit-identical. */
 } qm_tuning;
 
 int qm_abi_version(void);

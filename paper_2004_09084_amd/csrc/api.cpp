@@ -496,6 +496,11 @@ int enqueue_sweeps_fused(qm_decoder &d, int32_t iters, hipStream_t st) {
     std::vector<Slot *> act;
     for (Slot &s : d.slots)
         if (s.F > 0 && !lds_slot(d, s)) act.push_back(&s);
+    // the code with the longest chain of layers is placed first in every
+    // launch, so its (latency-bound) blocks are dispatched first and overlap
+    // with the other codes' blocks instead of trailing them
+    std::stable_sort(act.begin(), act.end(),
+                     [](const Slot *a, const Slot *b) { return a->gptr.size() > b->gptr.size(); });
     const int nc = (int)act.size();
     std::vector<LayerArgs> base(nc);
     std::vector<int> G(nc);
@@ -536,8 +541,19 @@ int enqueue_sweeps_fused(qm_decoder &d, int32_t iters, hipStream_t st) {
         for (int c = 0; c < nc; ++c) {
             m.block_off[c] = off;
             LayerArgs la = base[c];
-            if (k < (int64_t)iters * G[c]) {
-                const int t = (int)(k / G[c]), gi = (int)(k % G[c]);
+            // code c runs its layer number j (of N = iters * G[c]) at this
+            // step: spread, at the steps where floor(k N / steps) advances
+            // (every step for the longest code); else at step j itself
+            const int64_t N = (int64_t)iters * G[c];
+            int64_t j = -1;
+            if (d.tun.spread_codes) {
+                const int64_t j0 = k * N / steps, j1 = (k + 1) * N / steps;
+                if (j1 > j0) j = j0;
+            } else if (k < N) {
+                j = k;
+            }
+            if (j >= 0) {
+                const int t = (int)(j / G[c]), gi = (int)(j % G[c]);
                 const Slot &s = *act[c];
                 la.last = (t == iters - 1) ? 1 : 0;
                 la.rows = slot_bufs(d, s).rows + s.gptr[gi];
@@ -650,10 +666,87 @@ int enqueue_sweeps_lds(qm_decoder &d, Slot &s, int32_t iters, hipStream_t st) {
     return QM_OK;
 }
 
-bool fused_path(const qm_decoder &d) {
+int tiled_codes(const qm_decoder &d) {
     int nc = 0;
     for (const Slot &s : d.slots) nc += (s.F > 0 && !lds_slot(d, s)) ? 1 : 0;
-    return nc >= 2 && nc <= QM_MAX_CODES && d.tun.fuse_codes && d.tun.merge;
+    return nc;
+}
+
+bool fused_path(const qm_decoder &d) {
+    const int nc = tiled_codes(d);
+    return nc >= 2 && nc <= QM_MAX_CODES && d.tun.fuse_codes == 1 && d.tun.merge;
+}
+
+bool streams_path(const qm_decoder &d) {
+    const int nc = tiled_codes(d);
+    return nc >= 2 && nc <= QM_MAX_CODES && d.tun.fuse_codes == 2 && d.tun.merge;
+}
+
+// Codes on their own streams (tuning fuse_codes = 2): each tiled code runs
+// its own layer sequence on its own stream, forked from and joined to the
+// decode stream, so the launches of different codes overlap on the device.
+// Launches are enqueued round-robin, each code's layers spread evenly over
+// the steps of the longest code (as spread_codes), so every stream is fed.
+int enqueue_sweeps_streams(qm_decoder &d, int32_t iters, hipStream_t st) {
+    const int msgk = msg_kind(d);
+    const size_t msg = msg_bytes(d);
+    std::vector<Slot *> act;
+    for (Slot &s : d.slots)
+        if (s.F > 0 && !lds_slot(d, s)) act.push_back(&s);
+    std::stable_sort(act.begin(), act.end(),
+                     [](const Slot *a, const Slot *b) { return a->gptr.size() > b->gptr.size(); });
+    const int nc = (int)act.size();
+    if ((int)d.gstreams.size() < nc - 1 || !d.gfork) return fail(QM_ERR_STATE, "code streams missing");
+    std::vector<hipStream_t> cs(nc, st);
+    std::vector<LayerArgs> base(nc);
+    std::vector<int> G(nc);
+    int64_t steps = 0;
+    for (int c = 0; c < nc; ++c) {
+        if (c > 0) cs[c] = d.gstreams[c - 1];
+        base[c] = layer_args(d, *act[c]);
+        G[c] = (int)act[c]->gptr.size() - 1;
+        steps = std::max<int64_t>(steps, (int64_t)iters * G[c]);
+    }
+    QM_HIP(hipEventRecord(d.gfork, st));
+    for (int c = 1; c < nc; ++c) QM_HIP(hipStreamWaitEvent(cs[c], d.gfork, 0));
+    // profiled: one sweep of the longest code (on the decode stream) from
+    // the middle of the decode; its launches overlap the other codes'
+    const int64_t kprof = (d.profiling && iters >= 2) ? (int64_t)((iters - 1) / 2) * G[0] : -1;
+    ProfScope window(d, st, kprof >= 0);
+    double wbytes = 0.0, wchecks = 0.0;
+    for (int64_t k = 0; k < steps; ++k) {
+        if (k == kprof) {
+            const int rc = window.begin();
+            if (rc != QM_OK) return rc;
+        }
+        for (int c = 0; c < nc; ++c) {
+            const int64_t N = (int64_t)iters * G[c];
+            const int64_t j0 = k * N / steps, j1 = (k + 1) * N / steps;
+            if (j1 <= j0) continue;
+            const Slot &s = *act[c];
+            const int t = (int)(j0 / G[c]), gi = (int)(j0 % G[c]);
+            LayerArgs la = base[c];
+            la.last = (t == iters - 1) ? 1 : 0;
+            la.rows = slot_bufs(d, s).rows + s.gptr[gi];
+            la.nrows = s.gptr[gi + 1] - s.gptr[gi];
+            QM_HIP(qm_launch_layer(la, msgk, s.maxd_t, la.fpl, d.tun.block, d.tun.stream_hint, cs[c]));
+            if (c == 0 && kprof >= 0 && k >= kprof && k < kprof + G[0]) {
+                double b, ch;
+                layer_work(s, s.hrows.data() + s.gptr[gi], la.nrows, msg, &b, &ch);
+                wbytes += b;
+                wchecks += ch;
+            }
+        }
+        if (kprof >= 0 && k == kprof + G[0] - 1) {
+            const int rc = window.end(wbytes, wchecks, G[0]);
+            if (rc != QM_OK) return rc;
+        }
+    }
+    for (int c = 1; c < nc; ++c) {
+        QM_HIP(hipEventRecord(d.gjoin[c - 1], cs[c]));
+        QM_HIP(hipStreamWaitEvent(st, d.gjoin[c - 1], 0));
+    }
+    return QM_OK;
 }
 
 // The launch sequence of one decode (no host synchronisation: capturable).
@@ -690,6 +783,8 @@ int enqueue_decode(qm_decoder &d, const float *llr, const uint8_t *syn, int32_t 
     if (fork) QM_HIP(hipEventRecord(d.ev_join, d.side));
     if (fused_path(d)) {
         rc = enqueue_sweeps_fused(d, iters, st);
+    } else if (streams_path(d)) {
+        rc = enqueue_sweeps_streams(d, iters, st);
     } else {
         for (Slot &s : d.slots) {
             if (s.F == 0 || lds_slot(d, s)) continue;
@@ -1104,9 +1199,10 @@ int qm_decoder_create(const qm_code *const *codes, int32_t ncodes, const int32_t
     d->tun.merge = 1;
     d->tun.graph = (flags & QM_GRAPH) ? 1 : 0;
     d->tun.frames_per_lane = 2;
-    d->tun.fuse_codes = 1;
+    d->tun.fuse_codes = 2;
     d->tun.stream_hint = 1;
     d->tun.tile_groups = 1;
+    d->tun.spread_codes = 1;
     layout(*d);
     *out = d;
     return QM_OK;
@@ -1173,9 +1269,10 @@ int qm_decoder_set_tuning(qm_decoder *d, const qm_tuning *t) {
         return fail(QM_ERR_INVALID_ARG, "frames_per_lane must be 1 or 2");
     n.merge = n.merge ? 1 : 0;
     n.graph = n.graph ? 1 : 0;
-    n.fuse_codes = n.fuse_codes ? 1 : 0;
+    if (n.fuse_codes < 0 || n.fuse_codes > 2) return fail(QM_ERR_INVALID_ARG, "fuse_codes must be 0, 1 or 2");
     n.stream_hint = n.stream_hint ? 1 : 0;
     n.lds_resident = n.lds_resident ? 1 : 0;
+    n.spread_codes = n.spread_codes ? 1 : 0;
     if (n.tile_groups == 0) n.tile_groups = 1;
     if (n.tile_groups != 1 && n.tile_groups != 2 && n.tile_groups != 4 && n.tile_groups != 8)
         return fail(QM_ERR_INVALID_ARG, "tile_groups must be 1, 2, 4 or 8");
@@ -1205,8 +1302,9 @@ int qm_decode(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t iters
         const int rc = ensure_side_stream(*d);
         if (rc != QM_OK) return rc;
     }
-    if (d->tun.tile_groups > 1) {
-        const int rc = ensure_group_streams(*d, d->tun.tile_groups);
+    if (d->tun.tile_groups > 1 || d->tun.fuse_codes == 2) {
+        const int rc = ensure_group_streams(
+            *d, d->tun.fuse_codes == 2 ? std::max<int>(d->tun.tile_groups, QM_MAX_CODES) : d->tun.tile_groups);
         if (rc != QM_OK) return rc;
     }
     if (!d->tun.graph || d->profiling) return enqueue_decode(*d, llr, syn, iters, hard, app, flags, st);
@@ -1492,9 +1590,9 @@ int qm_autotune(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t ite
             std::fprintf(log,
                          "{\"frames_per_tile\": %d, \"frames_per_lane\": %d, \"block\": %d, \"merge\": %d, "
                          "\"fuse_codes\": %d, \"graph\": %d, \"stream_hint\": %d, \"lds_resident\": %d, "
-                         "\"tile_groups\": %d, \"iters\": %d, \"ms\": %.4f}\n",
+                         "\"tile_groups\": %d, \"spread_codes\": %d, \"iters\": %d, \"ms\": %.4f}\n",
                          t.frames_per_tile, t.frames_per_lane, t.block, t.merge, t.fuse_codes, t.graph,
-                         t.stream_hint, t.lds_resident, t.tile_groups, probe, *ms);
+                         t.stream_hint, t.lds_resident, t.tile_groups, t.spread_codes, probe, *ms);
         return QM_OK;
     };
 
@@ -1528,8 +1626,12 @@ int qm_autotune(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t ite
         d->tun = keep;
     }
     // structural variants on top of the best launch shape
-    for (int v = 0; v < 7 && rc == QM_OK; ++v) {
+    for (int v = 0; v < 8 && rc == QM_OK; ++v) {
         qm_tuning t = best;
+        if (v == 7) {
+            if (ncodes < 2 || !t.fuse_codes) continue;
+            t.spread_codes = !t.spread_codes;
+        }
         if (v == 5 || v == 6) {
             if (ncodes != 1) continue;  // fused mixed batches do not use tile groups
             t.tile_groups = v == 5 ? 2 : 4;
@@ -1542,7 +1644,7 @@ int qm_autotune(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t ite
         if (v == 0) t.merge = 0;
         if (v == 1) {
             if (ncodes < 2) continue;
-            t.fuse_codes = 0;
+            t.fuse_codes = t.fuse_codes == 2 ? 1 : 2;
         }
         if (v == 2) t.graph = 1;
         float ms = 0.0f;

@@ -235,23 +235,46 @@ def test_fused_mixed_batch_equals_unfused_and_single_code():
     Fs = [64, 32, 32]
     wls, codes, L, S = _mixed(specs, Fs)
     outs = {}
-    for fuse in (1, 0):
+    # fuse 1 / spread 1: layers spread over the launches; fuse 1 / spread 0:
+    # every code from the first launch on; fuse 2: each code on its own
+    # stream; fuse 0: codes one after another
+    for fuse, spread in ((1, 1), (1, 0), (2, 1), (0, 1)):
         for flags in (0, Q.QM_MSG_FP16):
-            dec = Q.Decoder(codes, Fs, flags=flags, tuning=dict(fuse_codes=fuse))
+            dec = Q.Decoder(codes, Fs, flags=flags, tuning=dict(fuse_codes=fuse, spread_codes=spread))
             h, a, f = dec.decode(L, S, 9)
             torch.cuda.synchronize()
-            outs[(fuse, flags)] = (h.cpu().numpy(), a.cpu().numpy(), f.cpu().numpy())
+            outs[(fuse, spread, flags)] = (h.cpu().numpy(), a.cpu().numpy(), f.cpu().numpy())
     for flags in (0, Q.QM_MSG_FP16):
-        for x, y in zip(outs[(1, flags)], outs[(0, flags)]):
-            assert np.array_equal(x, y)
+        for other in ((1, 0, flags), (2, 1, flags), (0, 1, flags)):
+            for x, y in zip(outs[(1, 1, flags)], outs[other]):
+                assert np.array_equal(x, y), other
     # and against one decoder per code (FP32)
     on = of = 0
     for w, s, F in zip(wls, specs, Fs):
         h1, a1, f1 = gpu_decode(w.shifts, s.Z, w.llr, w.s, 9)
-        assert np.array_equal(outs[(1, 0)][1][on:on + F * s.n], a1.reshape(-1))
-        assert np.array_equal(outs[(1, 0)][2][of:of + F], f1)
+        assert np.array_equal(outs[(1, 1, 0)][1][on:on + F * s.n], a1.reshape(-1))
+        assert np.array_equal(outs[(1, 1, 0)][2][of:of + F], f1)
         on += F * s.n
         of += F
+
+
+def test_code_streams_graph_replays_match_eager():
+    # each code on its own stream (fuse_codes = 2) inside a captured graph,
+    # replayed with eager work between the replays
+    import torch
+    specs = [SMALL, W.RATE005.with_Z(16), W.RATE002.with_Z(16)]
+    Fs = [32, 16, 16]
+    wls, codes, L, S = _mixed(specs, Fs)
+    ref = Q.Decoder(codes, Fs, tuning=dict(fuse_codes=0))
+    rh, ra, rf = (t.cpu().numpy() for t in ref.decode(L, S, 7))
+    dec = Q.Decoder(codes, Fs, tuning=dict(fuse_codes=2, graph=1))
+    for _ in range(3):
+        h, a, f = dec.decode(L, S, 7)
+        torch.cuda.synchronize()
+        assert np.array_equal(h.cpu().numpy(), rh)
+        assert np.array_equal(a.cpu().numpy().view(np.uint32), ra.view(np.uint32))
+        assert np.array_equal(f.cpu().numpy(), rf)
+        torch.ones(8, device="cuda").mul_(2.0)
 
 
 def test_fused_mixed_batch_matches_oracle_per_code():

@@ -240,6 +240,9 @@ typedef struct {
     double lds_bytes;     /* their algorithmic HBM bytes: per check and frame and sweep 4 (its
                              degree-1 term) plus, per degree>=2 edge, the message read and
                              written; plus each frame's degree>=2 APPs read and written once */
+    int32_t et_narrowings; /* early-terminating decodes: times the frames still decoding were
+                              moved into a narrower frame tile (counted whether or not profiling
+                              is enabled) */
 } qm_profile;
 
 int qm_decoder_set_profiling(qm_decoder *dec, int32_t enable);

@@ -184,7 +184,8 @@ struct qm_decoder {
     struct LdsPending { size_t a, b; double bytes; };
     std::vector<LdsPending> lds_pending;
     // early termination: host polls of the frames still decoding
-    int32_t *h_poll = nullptr;   // pinned, 2 words
+    int32_t *h_poll = nullptr;   // pinned, 2 copies of the control words
+    int32_t et_narrowings = 0;   // early termination: narrowing steps since the last profile reset
     hipEvent_t poll_ev[2] = {nullptr, nullptr};
 };
 
@@ -801,18 +802,22 @@ int enqueue_decode(qm_decoder &d, const float *llr, const uint8_t *syn, int32_t 
 
 // Sweeps of one code until every frame has met its syndrome or T sweeps
 // have run (Results, Table tabearly): after each sweep the frames still
-// decoding are tested, those that pass stop with the state they have, and
-// frames are compacted into the leading tiles when that frees a tile.  The
-// host stops enqueueing once a poll (every 4 sweeps, read one poll late so
-// the queue never drains) shows no frame left.
+// decoding are tested, those that pass stop and their outputs are written,
+// and the frames still decoding are gathered into the leading tiles when
+// that frees a tile.  The host stops enqueueing once a poll (every 4 sweeps,
+// read one poll late so the queue never drains) shows no frame left.  When a
+// poll shows that the frames still decoding fit in half a tile, their state
+// is copied into a narrower tile (in a tile region whose frames have all
+// stopped) and the sweeps go on there: a few frames in a wide tile make
+// latency-bound launches that narrow tiles shorten.
 int enqueue_early_slot(qm_decoder &d, Slot &s, int32_t T, uint8_t *hard, float *app, uint8_t *flags,
                        int32_t *iters_out, hipStream_t st) {
     const qm_code &c = *s.code;
-    const TileGeom g = geom(d, s);
+    const TileGeom g0 = geom(d, s);
     const SlotBufs b = slot_bufs(d, s);
     const int msgk = msg_kind(d);
     const size_t msg = msg_bytes(d);
-    float *Ad = reinterpret_cast<float *>(d.ws + s.oAd);
+    float *Ad0 = reinterpret_cast<float *>(d.ws + s.oAd);
     uint32_t *act = reinterpret_cast<uint32_t *>(d.ws + s.oAct);
     uint64_t *tmask = reinterpret_cast<uint64_t *>(d.ws + s.oTmask);
     int32_t *map = reinterpret_cast<int32_t *>(d.ws + s.oMap);
@@ -822,42 +827,84 @@ int enqueue_early_slot(qm_decoder &d, Slot &s, int32_t T, uint8_t *hard, float *
     int32_t *emit = reinterpret_cast<int32_t *>(d.ws + s.oEmit);
     uint8_t *PA = reinterpret_cast<uint8_t *>(d.ws + s.oPA);
     uint8_t *Pd = reinterpret_cast<uint8_t *>(d.ws + s.oPd);
-    QM_HIP(qm_launch_et_init(act, tmask, map, it, ctl, s.Fpad, g.ntiles, g.ft_log2, st));
-    QM_HIP(qm_launch_commit_d1(b.A, Ad, 0, b.rows, c.mb, g, st));  // Ad = LLR_d
     uint8_t *PS = reinterpret_cast<uint8_t *>(d.ws + s.oPS);
-    LayerArgs la = layer_args(d, s);
-    // packed hard decisions (the degree>=2 variables' before every test, the
-    // degree-1 ones here and then by every sweep) and syndrome bits (here and
-    // after every compaction)
-    QM_HIP(qm_launch_pack_signs(Ad, Pd, s.m, la.fpl, g, st));
-    QM_HIP(qm_launch_pack_syndrome(b.S, PS, nullptr, 0, la.fpl, g, st));
-    // the per-node state of a decoding frame (K is not used: the layer
-    // kernel forms it from Ad and the syndrome bits)
-    const CompactArray arr[] = {
-        {b.A, s.n, 4}, {b.R, (int64_t)c.nent1 * c.Z, (int32_t)msg}, {b.S, s.m, 1}, {Ad, s.m, 4}};
-    const int narr = (int)(sizeof(arr) / sizeof(arr[0]));
     const int32_t *cols1 = reinterpret_cast<const int32_t *>(d.ws + s.oCols1);
-    // gl: the geometry with ntiles = an upper bound of ctl[1] known to the
-    // host (the live-tile count only falls, so any count read back earlier
-    // in stream order bounds it); grids cover those tiles alone
-    TileGeom gl = g;
-    auto test = [&](int t) -> int {
-        QM_HIP(qm_launch_pack_cols(b.A, PA, cols1, (int)s.cols1.size(), ctl, la.fpl, gl, st));
-        QM_HIP(qm_launch_syndrome_packed(PA, Pd, PS, b.rows, c.mb, b.fail, ctl, la.fpl, gl, st));
-        QM_HIP(qm_launch_et_plan(b.fail, act, tmask, map, perm, it, emit, flags, s.F, ctl, s.Fpad, g.ft_log2, t, 0, st));
-        QM_HIP(qm_launch_emit(b.A, emit, ctl, app, hard, gl, st));
-        QM_HIP(qm_launch_compact(arr, narr, perm, ctl, g.ft_log2, st));
-        QM_HIP(qm_launch_pack_syndrome(b.S, PS, ctl, 1, la.fpl, gl, st));
-        return QM_OK;
-    };
-    int rc = test(0);
-    if (rc != QM_OK) return rc;
+    const int64_t nR = (int64_t)c.nent1 * c.Z;  // message nodes
+
+    // The current frame-tile geometry and per-node arrays (A, R, S, Ad).
+    // g.ntiles is an upper bound of ctl[1] known to the host (the live-tile
+    // count only falls, so any count read back earlier in stream order
+    // bounds it); grids cover those tiles alone.
+    TileGeom g = g0;
+    int Fpad = s.Fpad;
+    float *A = b.A, *Ad = Ad0;
+    char *R = static_cast<char *>(b.R);
+    uint8_t *S = b.S;
+    int region = 0;  // tile of the original layout that holds the state once narrowed
+    LayerArgs la = layer_args(d, s);
     la.Ad = Ad;
     la.tmask = tmask;
     la.ctl = ctl;
     la.Pd = Pd;
     la.PS = PS;
     la.last = 0;
+
+    QM_HIP(qm_launch_et_init(act, tmask, map, it, ctl, Fpad, g.ntiles, g.ft_log2, st));
+    QM_HIP(qm_launch_commit_d1(A, Ad, 0, b.rows, c.mb, g, st));  // Ad = LLR_d
+    // packed hard decisions (the degree>=2 variables' before every test, the
+    // degree-1 ones here and then by every sweep) and syndrome bits (here,
+    // after every compaction and after narrowing)
+    QM_HIP(qm_launch_pack_signs(Ad, Pd, s.m, la.fpl, g, st));
+    QM_HIP(qm_launch_pack_syndrome(S, PS, nullptr, 0, la.fpl, g, st));
+    auto test = [&](int t) -> int {
+        // the per-node state of a decoding frame (K is not used: the layer
+        // kernel forms it from Ad and the syndrome bits)
+        const CompactArray arr[] = {{A, s.n, 4}, {R, nR, (int32_t)msg}, {S, s.m, 1}, {Ad, s.m, 4}};
+        const int narr = (int)(sizeof(arr) / sizeof(arr[0]));
+        QM_HIP(qm_launch_pack_cols(A, PA, cols1, (int)s.cols1.size(), ctl, la.fpl, g, st));
+        QM_HIP(qm_launch_syndrome_packed(PA, Pd, PS, b.rows, c.mb, b.fail, ctl, la.fpl, g, st));
+        QM_HIP(qm_launch_et_plan(b.fail, act, tmask, map, perm, it, emit, flags, s.F, ctl, Fpad, g.ft_log2, t, 0, st));
+        QM_HIP(qm_launch_emit(A, emit, ctl, app, hard, g, st));
+        QM_HIP(qm_launch_compact(arr, narr, perm, ctl, g.ft_log2, st));
+        QM_HIP(qm_launch_pack_syndrome(S, PS, ctl, 1, la.fpl, g, st));
+        return QM_OK;
+    };
+    // Gather the frames still decoding (all in tile 0 of the current
+    // layout) into the first slots of a one-tile layout of 2^ftl frames in
+    // the other region; the slot -> frame map, flags and masks follow.
+    auto narrow = [&](int ftl) -> int {
+        region ^= 1;
+        float *A2 = b.A + (int64_t)region * (s.n << g0.ft_log2);
+        char *R2 = static_cast<char *>(b.R) + (int64_t)region * (nR << g0.ft_log2) * (int64_t)msg;
+        uint8_t *S2 = b.S + (int64_t)region * (s.m << g0.ft_log2);
+        float *Ad2 = Ad0 + (int64_t)region * (s.m << g0.ft_log2);
+        QM_HIP(qm_launch_et_narrow_plan(act, tmask, map, perm, ctl, g.ft_log2, ftl, st));
+        QM_HIP(qm_launch_narrow(A, A2, perm, s.n, 4, g.ft_log2, ftl, st));
+        QM_HIP(qm_launch_narrow(R, R2, perm, nR, (int)msg, g.ft_log2, ftl, st));
+        QM_HIP(qm_launch_narrow(S, S2, perm, s.m, 1, g.ft_log2, ftl, st));
+        QM_HIP(qm_launch_narrow(Ad, Ad2, perm, s.m, 4, g.ft_log2, ftl, st));
+        A = A2;
+        R = R2;
+        S = S2;
+        Ad = Ad2;
+        g.ft_log2 = ftl;
+        g.ntiles = 1;
+        Fpad = 1 << ftl;
+        la.A = A;
+        la.R = R;
+        la.Ad = Ad;
+        la.ft_log2 = ftl;
+        la.fpl = std::min(la.fpl, Fpad);
+        la.chunks = ((c.Z << ftl) / la.fpl + d.tun.block - 1) / d.tun.block;
+        la.strideA = s.n << ftl;
+        la.strideR = nR << ftl;
+        la.strideK = s.m << ftl;
+        QM_HIP(qm_launch_pack_syndrome(S, PS, nullptr, 0, la.fpl, g, st));
+        ++d.et_narrowings;
+        return QM_OK;
+    };
+    int rc = test(0);
+    if (rc != QM_OK) return rc;
     const RowDesc *rows = b.rows;
     const int G = (int)s.gptr.size() - 1;
     int pending = -1;
@@ -874,7 +921,7 @@ int enqueue_early_slot(qm_decoder &d, Slot &s, int32_t T, uint8_t *hard, float *
             for (int p = p_lo; p < p_hi; p += step) {
                 la.rows = rows + p;
                 la.nrows = step;
-                la.ntiles = gl.ntiles;
+                la.ntiles = g.ntiles;
                 QM_HIP(qm_launch_layer_et(la, msgk, s.maxd_t, la.fpl, d.tun.block, d.tun.stream_hint, st));
                 double bb, ch;
                 layer_work(s, s.hrows.data() + p, step, msg, &bb, &ch, true);
@@ -888,19 +935,25 @@ int enqueue_early_slot(qm_decoder &d, Slot &s, int32_t T, uint8_t *hard, float *
         if ((t + 1) % 4 == 0 && t + 1 < T) {
             if (pending >= 0) {
                 QM_HIP(hipEventSynchronize(d.poll_ev[pending]));
-                if (d.h_poll[pending] == 0) break;
-                // the poll holds ctl[0] (frames still decoding); ctl[1] = ceil(ctl[0] / FT)
-                const int32_t live = (d.h_poll[pending] + (1 << g.ft_log2) - 1) >> g.ft_log2;
-                gl.ntiles = std::min(gl.ntiles, live);
+                const int32_t *pc = d.h_poll + pending * QM_ET_CTL_WORDS;  // ctl as of that poll
+                const int32_t alive = pc[5];
+                if (alive == 0) break;
+                g.ntiles = std::min(g.ntiles, pc[1]);
+                int ftl = 0;
+                while ((1 << ftl) < alive) ++ftl;
+                if (g0.ntiles >= 2 && g.ntiles == 1 && ftl < g.ft_log2) {
+                    if ((rc = narrow(ftl)) != QM_OK) return rc;
+                }
             }
             pending = pending < 0 ? 0 : 1 - pending;
-            QM_HIP(hipMemcpyAsync(&d.h_poll[pending], ctl, 4, hipMemcpyDeviceToHost, st));
+            QM_HIP(hipMemcpyAsync(d.h_poll + pending * QM_ET_CTL_WORDS, ctl, QM_ET_CTL_WORDS * sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, st));
             QM_HIP(hipEventRecord(d.poll_ev[pending], st));
         }
     }
     // frames still decoding ran all T sweeps and failed the last test
-    QM_HIP(qm_launch_et_plan(b.fail, act, tmask, map, perm, it, emit, flags, s.F, ctl, s.Fpad, g.ft_log2, T, 1, st));
-    QM_HIP(qm_launch_emit(b.A, emit, ctl, app, hard, gl, st));
+    QM_HIP(qm_launch_et_plan(b.fail, act, tmask, map, perm, it, emit, flags, s.F, ctl, Fpad, g.ft_log2, T, 1, st));
+    QM_HIP(qm_launch_emit(A, emit, ctl, app, hard, g, st));
     if (iters_out && s.F > 0)
         QM_HIP(hipMemcpyAsync(iters_out, it, (size_t)s.F * 4, hipMemcpyDeviceToDevice, st));
     return QM_OK;
@@ -1347,7 +1400,7 @@ int qm_decode_early(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t
     }
     if (!d->h_poll) {
         void *p = nullptr;
-        QM_HIP(hipHostMalloc(&p, 2 * sizeof(int32_t), hipHostMallocDefault));
+        QM_HIP(hipHostMalloc(&p, 2 * QM_ET_CTL_WORDS * sizeof(int32_t), hipHostMallocDefault));
         d->h_poll = static_cast<int32_t *>(p);
         QM_HIP(hipEventCreateWithFlags(&d->poll_ev[0], hipEventDisableTiming));
         QM_HIP(hipEventCreateWithFlags(&d->poll_ev[1], hipEventDisableTiming));
@@ -1393,10 +1446,12 @@ int qm_decoder_get_profile(qm_decoder *d, qm_profile *out, int32_t reset) {
         out->lds_ms += ms;
         out->lds_bytes += p.bytes;
     }
+    out->et_narrowings = d->et_narrowings;
     if (reset) {
         d->pending.clear();
         d->lds_pending.clear();
         d->ev_used = 0;
+        d->et_narrowings = 0;
     }
     return QM_OK;
 }

@@ -354,6 +354,7 @@ __global__ void k_et_init(uint32_t *act, uint64_t *tmask, int32_t *map, int32_t 
         ctl[0] = Fpad;
         ctl[1] = ntiles;
         for (int w = 2; w < QM_ET_CTL_WORDS; ++w) ctl[w] = 0;
+        ctl[5] = Fpad;
     }
 }
 
@@ -440,6 +441,7 @@ __global__ void __launch_bounds__(256) k_et_plan(uint32_t *fail, uint32_t *act, 
     }
     const int FT = 1 << ftl;
     const int tiles_old = (nold + FT - 1) >> ftl, tiles_new = (alive + FT - 1) >> ftl;
+    if (tid == 0) ctl[5] = alive;
     if (alive == 0 || (!final_pass && tiles_new == tiles_old)) {
         // no data moves (alive == 0: nothing left to decode)
         plan_commit(s_act, act, tmask, Fpad, ftl);
@@ -590,6 +592,49 @@ __global__ void __launch_bounds__(256) k_compact(const CompactArgs c) {
         else
             gather_elem(static_cast<uint8_t *>(A.p), A.N, e, c.ftl, lo, alive, c.perm);
     }
+}
+
+// Before the frames still decoding move into a narrower tile: one wave
+// ranks the live slots of tile 0 (FT_old <= 64 of them) and gives the k-th
+// the new slot k (src[k] = its old slot, -1 for new slots without one);
+// map, act, the tile mask and the control words follow.
+__global__ void __launch_bounds__(64) k_et_narrow_plan(uint32_t *act, uint64_t *tmask, int32_t *map, int32_t *src,
+                                                       int32_t *ctl, int ft_old, int ft_new) {
+    const int l = (int)threadIdx.x;
+    const bool live = l < ft_old && act[l] != 0u;
+    const int fr = l < ft_old ? map[l] : 0;
+    const uint64_t b = __ballot(live);
+    const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+    const int n = __popcll(b);
+    __syncthreads();  // every lane has read act and map
+    if (l < ft_new) {
+        src[l] = -1;
+        act[l] = 0u;
+    }
+    __syncthreads();
+    if (live && rank < ft_new) {
+        src[rank] = l;
+        map[rank] = fr;
+        act[rank] = 1u;
+    }
+    if (l == 0) {
+        tmask[0] = n >= 64 ? ~0ull : (1ull << n) - 1ull;
+        ctl[0] = n;
+        ctl[1] = n > 0 ? 1 : 0;
+        ctl[2] = 0;
+        ctl[5] = n;
+    }
+}
+
+// The narrowed tile: out[node][k] = in[node][src[k]] (tile 0 of the old
+// layout) for the new slots k < FT_out, 0 where src[k] < 0.
+template <typename T>
+__global__ void __launch_bounds__(256) k_narrow(const T *__restrict__ in, T *__restrict__ out, const int32_t *src,
+                                                int64_t N, int ftl_in, int ftl_out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (N << ftl_out)) return;
+    const int sl = src[e & ((1 << ftl_out) - 1)];
+    out[e] = sl >= 0 ? in[((e >> ftl_out) << ftl_in) + sl] : (T)0;
 }
 
 __global__ void k_fill_u32(uint32_t *p, uint32_t v, size_t count) {
@@ -798,7 +843,9 @@ hipError_t qm_launch_et_init(uint32_t *act, uint64_t *tmask, int32_t *map, int32
 hipError_t qm_launch_et_plan(uint32_t *fail, uint32_t *act, uint64_t *tmask, int32_t *map, int32_t *perm,
                              int32_t *iters, int32_t *emit, uint8_t *flags, int F, int32_t *ctl, int Fpad, int ft_log2,
                              int t, int final_pass, hipStream_t s) {
-    if (Fpad < 1 || Fpad > QM_ET_MAXF || F > Fpad || ft_log2 < 0 || ft_log2 > 6 || (Fpad & ((1 << ft_log2) - 1)))
+    // F (the code's frame count) may exceed Fpad once the frames still
+    // decoding sit in a narrowed tile: frame ids come from map
+    if (Fpad < 1 || Fpad > QM_ET_MAXF || F < 0 || ft_log2 < 0 || ft_log2 > 6 || (Fpad & ((1 << ft_log2) - 1)))
         return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_et_plan, dim3(1), dim3(256), 0, s, fail, act, tmask, map, perm, iters, emit, flags, F, ctl,
                        Fpad, ft_log2, t, final_pass);
@@ -833,6 +880,38 @@ hipError_t qm_launch_compact(const CompactArray *arr, int narr, const int32_t *p
     if (acc == 0) return hipSuccess;
     const unsigned blocks = (unsigned)std::min<int64_t>(acc, 8192);
     hipLaunchKernelGGL(k_compact, dim3(blocks), dim3(256), 0, s, c);
+    return hipGetLastError();
+}
+
+hipError_t qm_launch_et_narrow_plan(uint32_t *act, uint64_t *tmask, int32_t *map, int32_t *src, int32_t *ctl,
+                                    int ft_log2_old, int ft_log2_new, hipStream_t s) {
+    if (ft_log2_new < 0 || ft_log2_new >= ft_log2_old || ft_log2_old > 6) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_et_narrow_plan, dim3(1), dim3(64), 0, s, act, tmask, map, src, ctl, 1 << ft_log2_old,
+                       1 << ft_log2_new);
+    return hipGetLastError();
+}
+
+hipError_t qm_launch_narrow(const void *in, void *out, const int32_t *src, int64_t N, int esz, int ft_log2_in,
+                            int ft_log2_out, hipStream_t s) {
+    if (ft_log2_out < 0 || ft_log2_out > ft_log2_in || ft_log2_in > 6) return hipErrorInvalidValue;
+    const int64_t total = N << ft_log2_out;
+    if (total == 0) return hipSuccess;
+    const dim3 grid((unsigned)((total + 255) / 256));
+    switch (esz) {
+        case 4:
+            hipLaunchKernelGGL(k_narrow<uint32_t>, grid, dim3(256), 0, s, static_cast<const uint32_t *>(in),
+                               static_cast<uint32_t *>(out), src, N, ft_log2_in, ft_log2_out);
+            break;
+        case 2:
+            hipLaunchKernelGGL(k_narrow<uint16_t>, grid, dim3(256), 0, s, static_cast<const uint16_t *>(in),
+                               static_cast<uint16_t *>(out), src, N, ft_log2_in, ft_log2_out);
+            break;
+        case 1:
+            hipLaunchKernelGGL(k_narrow<uint8_t>, grid, dim3(256), 0, s, static_cast<const uint8_t *>(in),
+                               static_cast<uint8_t *>(out), src, N, ft_log2_in, ft_log2_out);
+            break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

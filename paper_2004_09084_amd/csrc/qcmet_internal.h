@@ -83,6 +83,7 @@ __host__ __device__ inline int qm_pack_bit(int fl, int ft_log2, int fpl) {
 //   [2] 1: the planning kernel planned a compaction (perm, from slot ctl[3])
 //   [3] first slot the compaction writes
 //   [4] frames that stopped in the last planning call (outputs to write)
+//   [5] frames still decoding
 #define QM_ET_CTL_WORDS 8
 // Largest padded frame count of one code in an early-terminating decode
 // (the planning kernel keeps per-slot state in LDS).
@@ -212,6 +213,16 @@ struct CompactArray {
 #define QM_COMPACT_ARRAYS 5
 hipError_t qm_launch_compact(const CompactArray *arr, int narr, const int32_t *perm, const int32_t *ctl,
                              int ft_log2, hipStream_t s);
+// moving the frames still decoding (all in tile 0) into a tile of
+// 2^ft_log2_new slots: src[k] = the old slot that new slot k takes (-1:
+// none), with map, act, the tile mask and the control words updated
+hipError_t qm_launch_et_narrow_plan(uint32_t *act, uint64_t *tmask, int32_t *map, int32_t *src, int32_t *ctl,
+                                    int ft_log2_old, int ft_log2_new, hipStream_t s);
+// out[node][k] = in[node][src[k]] for k < 2^ft_log2_out (tile 0 of a layout
+// of 2^ft_log2_in frames per tile; N nodes, esz-byte elements; in and out
+// must not overlap)
+hipError_t qm_launch_narrow(const void *in, void *out, const int32_t *src, int64_t N, int esz, int ft_log2_in,
+                            int ft_log2_out, hipStream_t s);
 // nms.hip
 hipError_t qm_launch_nms_kappa(const float *A, const uint8_t *Sil, float *K, const RowDesc *rows, int mb,
                                const TileGeom &g, hipStream_t s);

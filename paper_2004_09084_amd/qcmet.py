@@ -71,7 +71,8 @@ class qm_tuning(ctypes.Structure):
 class qm_profile(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int32), ("sweeps", ctypes.c_int32), ("layer_ms", ctypes.c_double),
                 ("sweep_ms", ctypes.c_double), ("layer_bytes", ctypes.c_double), ("checks", ctypes.c_double),
-                ("lds_launches", ctypes.c_int32), ("lds_ms", ctypes.c_double), ("lds_bytes", ctypes.c_double)]
+                ("lds_launches", ctypes.c_int32), ("lds_ms", ctypes.c_double), ("lds_bytes", ctypes.c_double),
+                ("et_narrowings", ctypes.c_int32)]
 
 
 _lib = None

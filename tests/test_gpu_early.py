@@ -85,6 +85,43 @@ def test_early_frames_equal_fixed_decodes(ft):
     _assert_frozen_equal_fixed(H, SMALL.Z, L, S, res, tuning=tun)
 
 
+# (SNR, frames, seed) groups of a 64-frame batch for the small rate-0.1 code.
+# The SNR-0.25 group (seed 32) stops at sweeps 3-5 except 3 frames that never
+# converge; with the fast frames that leaves 7 frames at the poll after
+# sweep 4 and 3 at the next one: two narrowings (to 8, then 4 frames per
+# tile), into each of the two tile regions in turn.  One never-converging
+# frame among fast ones narrows to a single frame per tile (1 frame per lane).
+NARROW_CASES = {
+    "two_steps": ((0.6, 52, 31), (0.25, 12, 32)),
+    "one_frame": ((0.6, 63, 31), (0.161, 1, 33)),
+}
+
+
+@pytest.mark.parametrize("flags", [0, Q.QM_MSG_FP16], ids=["fp32", "fp16"])
+@pytest.mark.parametrize("case", sorted(NARROW_CASES))
+def test_early_narrowed_tiles_equal_fixed_decodes(case, flags):
+    # the frames still decoding are moved into narrower tiles, and every
+    # frame still equals a fixed decode of the batch at its own count
+    import torch
+    T = 40
+    H = W.make_code(SMALL, 0)
+    parts = [W.make_frames(H, SMALL.Z, snr, F, seed=seed)[1:] for snr, F, seed in NARROW_CASES[case]]
+    L = np.concatenate([p[0] for p in parts])
+    S = np.concatenate([p[1] for p in parts])
+    tun = {"frames_per_tile": 16}
+    code = Q.Code(H, SMALL.Z)
+    dec = Q.Decoder([code], [64], flags=flags | Q.QM_EARLY_STOP, tuning=tun)
+    dec.profile(reset=True)
+    hard, app, fl, it = dec.decode_early(to_dev(L), to_dev(S), T)
+    torch.cuda.synchronize()
+    narrowed = dec.profile(reset=True)["et_narrowings"]
+    res = (hard.cpu().numpy().reshape(64, -1), app.cpu().numpy().reshape(64, -1), fl.cpu().numpy(), it.cpu().numpy())
+    say(case, "narrowed", narrowed, "iters", np.bincount(res[3]).tolist())
+    assert narrowed >= (2 if case == "two_steps" else 1)
+    assert (res[3] == T).sum() >= 1
+    _assert_frozen_equal_fixed(H, SMALL.Z, L, S, res, flags=flags, tuning=tun)
+
+
 def test_early_fp16_frames_equal_fixed_decodes():
     T = 30
     H, L, S = _frames(SMALL, 48, 0.25, 13)

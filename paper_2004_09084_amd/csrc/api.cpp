@@ -804,12 +804,15 @@ int enqueue_decode(qm_decoder &d, const float *llr, const uint8_t *syn, int32_t 
 // have run (Results, Table tabearly): after each sweep the frames still
 // decoding are tested, those that pass stop and their outputs are written,
 // and the frames still decoding are gathered into the leading tiles when
-// that frees a tile.  The host stops enqueueing once a poll (every 4 sweeps,
-// read one poll late so the queue never drains) shows no frame left.  When a
+// that frees a tile.  The host stops enqueueing once a poll (every
+// kPollEvery sweeps, read one poll late so the queue never drains) shows no
+// frame left.  When a
 // poll shows that the frames still decoding fit in half a tile, their state
 // is copied into a narrower tile (in a tile region whose frames have all
 // stopped) and the sweeps go on there: a few frames in a wide tile make
 // latency-bound launches that narrow tiles shorten.
+constexpr int kPollEvery = 2;  // sweeps between host polls of an early-terminating decode
+
 int enqueue_early_slot(qm_decoder &d, Slot &s, int32_t T, uint8_t *hard, float *app, uint8_t *flags,
                        int32_t *iters_out, hipStream_t st) {
     const qm_code &c = *s.code;
@@ -865,8 +868,10 @@ int enqueue_early_slot(qm_decoder &d, Slot &s, int32_t T, uint8_t *hard, float *
         QM_HIP(qm_launch_syndrome_packed(PA, Pd, PS, b.rows, c.mb, b.fail, ctl, la.fpl, g, st));
         QM_HIP(qm_launch_et_plan(b.fail, act, tmask, map, perm, it, emit, flags, s.F, ctl, Fpad, g.ft_log2, t, 0, st));
         QM_HIP(qm_launch_emit(A, emit, ctl, app, hard, g, st));
-        QM_HIP(qm_launch_compact(arr, narr, perm, ctl, g.ft_log2, st));
-        QM_HIP(qm_launch_pack_syndrome(S, PS, ctl, 1, la.fpl, g, st));
+        if (g.ntiles > 1) {  // with one tile left no compaction can be planned
+            QM_HIP(qm_launch_compact(arr, narr, perm, ctl, g.ft_log2, st));
+            QM_HIP(qm_launch_pack_syndrome(S, PS, ctl, 1, la.fpl, g, st));
+        }
         return QM_OK;
     };
     // Gather the frames still decoding (all in tile 0 of the current
@@ -932,7 +937,7 @@ int enqueue_early_slot(qm_decoder &d, Slot &s, int32_t T, uint8_t *hard, float *
         }
         if ((rc = sweep.end(bytes, checks, launches)) != QM_OK) return rc;
         if ((rc = test(t + 1)) != QM_OK) return rc;
-        if ((t + 1) % 4 == 0 && t + 1 < T) {
+        if ((t + 1) % kPollEvery == 0 && t + 1 < T) {
             if (pending >= 0) {
                 QM_HIP(hipEventSynchronize(d.poll_ev[pending]));
                 const int32_t *pc = d.h_poll + pending * QM_ET_CTL_WORDS;  // ctl as of that poll

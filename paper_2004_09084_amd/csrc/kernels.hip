@@ -20,52 +20,66 @@ using namespace qmdev;
 
 // K for every check: degree-1 term of the row (or 0 if the row has none)
 // with the syndrome bit folded into its sign.
+template <int V>
 __global__ void __launch_bounds__(256) k_kappa(const float *__restrict__ A, const uint8_t *__restrict__ Sil,
                                                float *__restrict__ K, const RowDesc *rows, int Z, int ftl,
                                                int ntiles, int chunks, int64_t strideA, int64_t strideM) {
+    // a lane forms K for V adjacent frames of one check (V divides FT)
+    typedef float vf __attribute__((ext_vector_type(V)));
+    typedef uint8_t vb __attribute__((ext_vector_type(V)));
     const int b = blockIdx.x;
     const int tile = b % ntiles;
     const int rest = b / ntiles;
     const int chunk = rest % chunks;
     const int rs = rest / chunks;
-    const int idx = chunk * (int)blockDim.x + (int)threadIdx.x;
+    const int idx = (chunk * (int)blockDim.x + (int)threadIdx.x) * V;
     if (idx >= (Z << ftl)) return;
     const int k = idx >> ftl;
     const int fl = idx & ((1 << ftl) - 1);
-    const RowDesc *rd = rows + rs;
-    const int moff = ((rd->row * Z + k) << ftl) + fl;
-    uint32_t neg = Sil[(int64_t)tile * strideM + moff] & 1u;
-    float mag = 0.0f;
+    ConstRowDesc *rd = as_const(rows + rs);
+    const int64_t moff = (int64_t)tile * strideM + (((rd->row * Z + k) << ftl) + fl);
+    const vb sb = *reinterpret_cast<const vb *>(Sil + moff);
+    vf out;
     if (rd->d1col >= 0) {
         int v = k + rd->d1shift;
         v = v >= Z ? v - Z : v;
-        const float lam = A[(int64_t)tile * strideA + (((rd->d1col * Z + v) << ftl) + fl)];
-        mag = qm_phi(qm_clip(fabsf(lam)));
-        neg ^= (uint32_t)(lam < 0.0f);
+        const vf lam = *reinterpret_cast<const vf *>(A + (int64_t)tile * strideA + (((rd->d1col * Z + v) << ftl) + fl));
+#pragma unroll
+        for (int i = 0; i < V; ++i)
+            out[i] = with_sign(qm_phi(qm_clip(fabsf(lam[i]))), (uint32_t)(sb[i] & 1u) ^ (uint32_t)(lam[i] < 0.0f));
+    } else {
+#pragma unroll
+        for (int i = 0; i < V; ++i) out[i] = with_sign(0.0f, (uint32_t)(sb[i] & 1u));
     }
-    K[(int64_t)tile * strideM + moff] = with_sign(mag, neg);
+    *reinterpret_cast<vf *>(K + moff) = out;
 }
 
+// Nodes per workgroup of the layout transposes: a frame's run of them is
+// 128 bytes or more on the frame-major side.
+constexpr int kRun = 128;
+
 // Frame-major [F][N] -> frame tiles [ntiles][N][FT] (padding frames = 0),
-// through a 64-node x FT-frame LDS tile so both sides are coalesced.
+// through a kRun-node x FT-frame LDS tile so both sides are coalesced.
+// (LDS: FT x (kRun + 1) elements, dynamic.)
 template <typename T>
 __global__ void __launch_bounds__(256) k_to_tiles(const T *__restrict__ in, T *__restrict__ out, int F,
                                                   int64_t N, int ftl) {
-    __shared__ T lds[64][65];
+    extern __shared__ uint32_t dyn_lds[];
+    T *lds = reinterpret_cast<T *>(dyn_lds);
     const int tile = blockIdx.y;
-    const int64_t v0 = (int64_t)blockIdx.x * 64;
+    const int64_t v0 = (int64_t)blockIdx.x * kRun;
     const int FT = 1 << ftl;
     const int tid = threadIdx.x;
-    for (int fl = tid >> 6; fl < FT; fl += 4) {
+    for (int fl = tid / kRun; fl < FT; fl += 256 / kRun) {
         const int f = tile * FT + fl;
-        const int64_t v = v0 + (tid & 63);
-        lds[fl][tid & 63] = (f < F && v < N) ? in[(int64_t)f * N + v] : (T)0;
+        const int64_t v = v0 + (tid % kRun);
+        lds[fl * (kRun + 1) + tid % kRun] = (f < F && v < N) ? in[(int64_t)f * N + v] : (T)0;
     }
     __syncthreads();
     T *o = out + ((int64_t)tile * N + v0) * FT;
-    for (int e = tid; e < (64 << ftl); e += 256) {
+    for (int e = tid; e < (kRun << ftl); e += 256) {
         const int vv = e >> ftl;
-        if (v0 + vv < N) o[e] = lds[e & (FT - 1)][vv];
+        if (v0 + vv < N) o[e] = lds[(e & (FT - 1)) * (kRun + 1) + vv];
     }
 }
 
@@ -75,22 +89,23 @@ __global__ void __launch_bounds__(256) k_to_tiles(const T *__restrict__ in, T *_
 __global__ void __launch_bounds__(256) k_finalize(const float *__restrict__ A, const uint32_t *__restrict__ fail,
                                                   float *__restrict__ app, uint8_t *__restrict__ hard,
                                                   uint8_t *__restrict__ flags, int F, int64_t N, int ftl) {
-    __shared__ float lds[64][65];
+    extern __shared__ uint32_t dyn_lds[];
+    float *lds = reinterpret_cast<float *>(dyn_lds);  // FT x (kRun + 1)
     const int tile = blockIdx.y;
-    const int64_t v0 = (int64_t)blockIdx.x * 64;
+    const int64_t v0 = (int64_t)blockIdx.x * kRun;
     const int FT = 1 << ftl;
     const int tid = threadIdx.x;
     const float *a = A + ((int64_t)tile * N + v0) * FT;
-    for (int e = tid; e < (64 << ftl); e += 256) {
+    for (int e = tid; e < (kRun << ftl); e += 256) {
         const int vv = e >> ftl;
-        lds[e & (FT - 1)][vv] = (v0 + vv < N) ? a[e] : 0.0f;
+        lds[(e & (FT - 1)) * (kRun + 1) + vv] = (v0 + vv < N) ? a[e] : 0.0f;
     }
     __syncthreads();
-    for (int fl = tid >> 6; fl < FT; fl += 4) {
+    for (int fl = tid / kRun; fl < FT; fl += 256 / kRun) {
         const int f = tile * FT + fl;
-        const int64_t v = v0 + (tid & 63);
+        const int64_t v = v0 + (tid % kRun);
         if (f < F && v < N) {
-            const float x = lds[fl][tid & 63];
+            const float x = lds[fl * (kRun + 1) + tid % kRun];
             if (app) app[(int64_t)f * N + v] = x;
             hard[(int64_t)f * N + v] = x < 0.0f ? 1 : 0;
         }
@@ -104,13 +119,17 @@ __global__ void __launch_bounds__(256) k_finalize(const float *__restrict__ A, c
 }
 
 // Syndrome test of the hard decisions (H c = s), per frame: a check fails
-// iff s ^ xor of [APP < 0] over its variables is 1.  Failures are OR-ed in
-// LDS per frame, then one atomic per frame and workgroup.
+// iff s ^ xor of [APP < 0] over its variables is 1.  A lane tests V adjacent
+// frames of one check (V divides FT); failures are OR-ed in LDS per frame,
+// then one atomic per failing frame and workgroup.
 // Ad (may be null): degree-1 APPs held per check instead of in A.
+template <int V>
 __global__ void __launch_bounds__(256) k_syndrome(const float *__restrict__ A, const float *__restrict__ Ad,
                                                   const uint8_t *__restrict__ Sil, const RowDesc *rows,
                                                   uint32_t *fail, int Z, int ftl, int ntiles, int chunks, int parts,
                                                   int64_t strideA, int64_t strideM, const int32_t *ctl) {
+    typedef float vf __attribute__((ext_vector_type(V)));
+    typedef uint8_t vb __attribute__((ext_vector_type(V)));
     __shared__ uint32_t lf[64];
     const int b = blockIdx.x;
     const int tile = b % ntiles;
@@ -122,30 +141,42 @@ __global__ void __launch_bounds__(256) k_syndrome(const float *__restrict__ A, c
     const int FT = 1 << ftl;
     if (tid < 64) lf[tid] = 0u;
     __syncthreads();
-    const RowDesc *rd = rows + rs;
+    ConstRowDesc *rd = as_const(rows + rs);
     const float *At = A + (int64_t)tile * strideA;
     const uint8_t *St = Sil + (int64_t)tile * strideM;
+    const int d = rd->d, row = rd->row, d1col = rd->d1col, d1shift = rd->d1shift;
     for (int c = part; c < chunks; c += parts) {
-        const int idx = c * (int)blockDim.x + tid;
+        const int idx = (c * (int)blockDim.x + tid) * V;
         if (idx < (Z << ftl)) {
             const int k = idx >> ftl;
             const int fl = idx & (FT - 1);
-            uint32_t par = St[((rd->row * Z + k) << ftl) + fl] & 1u;
-            for (int j = 0; j < rd->d; ++j) {
+            const int moff = ((row * Z + k) << ftl) + fl;
+            const vb sb = *reinterpret_cast<const vb *>(St + moff);
+            uint32_t par[V];
+#pragma unroll
+            for (int i = 0; i < V; ++i) par[i] = sb[i] & 1u;
+            for (int j = 0; j < d; ++j) {
                 int v = k + rd->shift[j];
                 v = v >= Z ? v - Z : v;
-                par ^= (uint32_t)(At[((rd->col[j] * Z + v) << ftl) + fl] < 0.0f);
+                const vf a = *reinterpret_cast<const vf *>(At + (((rd->col[j] * Z + v) << ftl) + fl));
+#pragma unroll
+                for (int i = 0; i < V; ++i) par[i] ^= (uint32_t)(a[i] < 0.0f);
             }
-            if (rd->d1col >= 0) {
+            if (d1col >= 0) {
+                vf a;
                 if (Ad) {
-                    par ^= (uint32_t)(Ad[(int64_t)tile * strideM + (((rd->row * Z + k) << ftl) + fl)] < 0.0f);
+                    a = *reinterpret_cast<const vf *>(Ad + (int64_t)tile * strideM + moff);
                 } else {
-                    int v = k + rd->d1shift;
+                    int v = k + d1shift;
                     v = v >= Z ? v - Z : v;
-                    par ^= (uint32_t)(At[((rd->d1col * Z + v) << ftl) + fl] < 0.0f);
+                    a = *reinterpret_cast<const vf *>(At + (((d1col * Z + v) << ftl) + fl));
                 }
+#pragma unroll
+                for (int i = 0; i < V; ++i) par[i] ^= (uint32_t)(a[i] < 0.0f);
             }
-            if (par) lf[fl] = 1u;
+#pragma unroll
+            for (int i = 0; i < V; ++i)
+                if (par[i]) lf[fl + i] = 1u;
         }
     }
     __syncthreads();
@@ -657,25 +688,33 @@ inline int chunks_for(int Z, int ftl, int block) { return ((Z << ftl) + block - 
 
 hipError_t qm_launch_to_tiles_f32(const float *in, float *out, int F, int64_t N, int ft_log2, int ntiles,
                                   hipStream_t s) {
-    dim3 grid((unsigned)((N + 63) / 64), (unsigned)ntiles);
-    hipLaunchKernelGGL(k_to_tiles<float>, grid, dim3(256), 0, s, in, out, F, N, ft_log2);
+    dim3 grid((unsigned)((N + kRun - 1) / kRun), (unsigned)ntiles);
+    const size_t lds = ((size_t)(kRun + 1) << ft_log2) * 4;
+    hipLaunchKernelGGL(k_to_tiles<float>, grid, dim3(256), lds, s, in, out, F, N, ft_log2);
     return hipGetLastError();
 }
 
 hipError_t qm_launch_to_tiles_u8(const uint8_t *in, uint8_t *out, int F, int64_t N, int ft_log2, int ntiles,
                                  hipStream_t s) {
-    dim3 grid((unsigned)((N + 63) / 64), (unsigned)ntiles);
-    hipLaunchKernelGGL(k_to_tiles<uint8_t>, grid, dim3(256), 0, s, in, out, F, N, ft_log2);
+    dim3 grid((unsigned)((N + kRun - 1) / kRun), (unsigned)ntiles);
+    const size_t lds = (((size_t)(kRun + 1) << ft_log2) + 3) / 4 * 4;
+    hipLaunchKernelGGL(k_to_tiles<uint8_t>, grid, dim3(256), lds, s, in, out, F, N, ft_log2);
     return hipGetLastError();
 }
 
 hipError_t qm_launch_kappa(const float *A, const uint8_t *Sil, float *K, const RowDesc *rows, int mb,
                            const TileGeom &g, hipStream_t s) {
-    const int chunks = chunks_for(g.Z, g.ft_log2, 256);
+    const int V = g.ft_log2 >= 2 ? 4 : 1;  // 4 frames per lane (16-byte accesses) when a node holds >= 4
+    const int chunks = chunks_for(g.Z, g.ft_log2, 256 * V);
     const int64_t blocks = (int64_t)g.ntiles * mb * chunks;
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_kappa, dim3((unsigned)blocks), dim3(256), 0, s, A, Sil, K, rows, g.Z, g.ft_log2,
-                       g.ntiles, chunks, (int64_t)g.n << g.ft_log2, (int64_t)g.m << g.ft_log2);
+    const int64_t sA = (int64_t)g.n << g.ft_log2, sM = (int64_t)g.m << g.ft_log2;
+    if (V == 4)
+        hipLaunchKernelGGL(k_kappa<4>, dim3((unsigned)blocks), dim3(256), 0, s, A, Sil, K, rows, g.Z, g.ft_log2,
+                           g.ntiles, chunks, sA, sM);
+    else
+        hipLaunchKernelGGL(k_kappa<1>, dim3((unsigned)blocks), dim3(256), 0, s, A, Sil, K, rows, g.Z, g.ft_log2,
+                           g.ntiles, chunks, sA, sM);
     return hipGetLastError();
 }
 
@@ -718,13 +757,19 @@ hipError_t qm_launch_layer_multi(const MultiLayerArgs &m, int msgk, int maxd, in
 
 hipError_t qm_launch_syndrome_et(const float *A, const float *Ad, const uint8_t *Sil, const RowDesc *rows, int mb,
                                  uint32_t *fail, const int32_t *ctl, const TileGeom &g, hipStream_t s) {
-    const int chunks = chunks_for(g.Z, g.ft_log2, 256);
+    if ((1 << g.ft_log2) > 64) return hipErrorInvalidConfiguration;  // per-frame LDS flags
+    const int V = g.ft_log2 >= 2 ? 4 : 1;  // 4 frames per lane (16-byte loads) when a node holds >= 4
+    const int chunks = chunks_for(g.Z, g.ft_log2, 256 * V);
     const int parts = chunks < 16 ? chunks : 16;
     const int64_t blocks = (int64_t)g.ntiles * mb * parts;
     if (blocks == 0) return hipSuccess;
-    if ((1 << g.ft_log2) > 64) return hipErrorInvalidConfiguration;  // per-frame LDS flags
-    hipLaunchKernelGGL(k_syndrome, dim3((unsigned)blocks), dim3(256), 0, s, A, Ad, Sil, rows, fail, g.Z, g.ft_log2,
-                       g.ntiles, chunks, parts, (int64_t)g.n << g.ft_log2, (int64_t)g.m << g.ft_log2, ctl);
+    const int64_t sA = (int64_t)g.n << g.ft_log2, sM = (int64_t)g.m << g.ft_log2;
+    if (V == 4)
+        hipLaunchKernelGGL(k_syndrome<4>, dim3((unsigned)blocks), dim3(256), 0, s, A, Ad, Sil, rows, fail, g.Z,
+                           g.ft_log2, g.ntiles, chunks, parts, sA, sM, ctl);
+    else
+        hipLaunchKernelGGL(k_syndrome<1>, dim3((unsigned)blocks), dim3(256), 0, s, A, Ad, Sil, rows, fail, g.Z,
+                           g.ft_log2, g.ntiles, chunks, parts, sA, sM, ctl);
     return hipGetLastError();
 }
 
@@ -735,8 +780,9 @@ hipError_t qm_launch_syndrome(const float *A, const float *Ad, const uint8_t *Si
 
 hipError_t qm_launch_finalize(const float *A, const uint32_t *fail, float *app, uint8_t *hard, uint8_t *flags,
                               int F, const TileGeom &g, hipStream_t s) {
-    dim3 grid((unsigned)((g.n + 63) / 64), (unsigned)g.ntiles);
-    hipLaunchKernelGGL(k_finalize, grid, dim3(256), 0, s, A, fail, app, hard, flags, F, g.n, g.ft_log2);
+    dim3 grid((unsigned)((g.n + kRun - 1) / kRun), (unsigned)g.ntiles);
+    const size_t lds = ((size_t)(kRun + 1) << g.ft_log2) * 4;
+    hipLaunchKernelGGL(k_finalize, grid, dim3(256), lds, s, A, fail, app, hard, flags, F, g.n, g.ft_log2);
     return hipGetLastError();
 }
 

@@ -537,20 +537,21 @@ __global__ void __launch_bounds__(256) k_et_plan(uint32_t *fail, uint32_t *act, 
 // Outputs of the frames that stopped in the last planning call, read from
 // their slots before any data moves: frame-major APPs and hard decisions
 // (step 4: c = [APP < 0]), as k_finalize writes them.  Grid-stride over
-// (run of 64 nodes, tile) items of the first ntiles tiles; a tile without
-// an emitted slot is skipped.
+// (run of kRun nodes, tile) items of the first ntiles tiles; a tile without
+// an emitted slot is skipped.  (LDS: FT x (kRun + 1) floats, dynamic.)
 __global__ void __launch_bounds__(256) k_emit(const float *__restrict__ A, const int32_t *__restrict__ emit,
                                               const int32_t *ctl, float *__restrict__ app,
                                               uint8_t *__restrict__ hard, int64_t N, int ftl, int ntiles) {
     if (ctl[4] == 0) return;
-    __shared__ float lds[64][65];
+    extern __shared__ uint32_t dyn_lds[];
+    float *lds = reinterpret_cast<float *>(dyn_lds);
     __shared__ int32_t s_fr[64];
     const int FT = 1 << ftl;
     const int tid = threadIdx.x;
-    const int64_t items = ((N + 63) >> 6) * ntiles;
+    const int64_t items = ((N + kRun - 1) / kRun) * ntiles;
     for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
         const int tile = (int)(it % ntiles);
-        const int64_t v0 = (it / ntiles) << 6;
+        const int64_t v0 = (it / ntiles) * kRun;
         __syncthreads();  // the previous item is done with s_fr and lds
         if (tid < FT) s_fr[tid] = emit[tile * FT + tid];
         __syncthreads();
@@ -558,16 +559,16 @@ __global__ void __launch_bounds__(256) k_emit(const float *__restrict__ A, const
         for (int fl = 0; fl < FT; ++fl) any = any || s_fr[fl] >= 0;
         if (!any) continue;
         const float *a = A + ((int64_t)tile * N + v0) * FT;
-        for (int e = tid; e < (64 << ftl); e += 256) {
+        for (int e = tid; e < (kRun << ftl); e += 256) {
             const int vv = e >> ftl;
-            lds[e & (FT - 1)][vv] = (v0 + vv < N) ? a[e] : 0.0f;
+            lds[(e & (FT - 1)) * (kRun + 1) + vv] = (v0 + vv < N) ? a[e] : 0.0f;
         }
         __syncthreads();
-        for (int fl = tid >> 6; fl < FT; fl += 4) {
+        for (int fl = tid / kRun; fl < FT; fl += 256 / kRun) {
             const int f = s_fr[fl];
-            const int64_t v = v0 + (tid & 63);
+            const int64_t v = v0 + (tid % kRun);
             if (f >= 0 && v < N) {
-                const float x = lds[fl][tid & 63];
+                const float x = lds[fl * (kRun + 1) + tid % kRun];
                 if (app) app[(int64_t)f * N + v] = x;
                 hard[(int64_t)f * N + v] = x < 0.0f ? 1 : 0;
             }
@@ -901,10 +902,11 @@ hipError_t qm_launch_et_plan(uint32_t *fail, uint32_t *act, uint64_t *tmask, int
 hipError_t qm_launch_emit(const float *A, const int32_t *emit, const int32_t *ctl, float *app, uint8_t *hard,
                           const TileGeom &g, hipStream_t s) {
     if ((1 << g.ft_log2) > 64) return hipErrorInvalidValue;
-    const int64_t items = ((g.n + 63) >> 6) * g.ntiles;
+    const int64_t items = ((g.n + kRun - 1) / kRun) * g.ntiles;
     if (items == 0) return hipSuccess;
     const unsigned blocks = (unsigned)std::min<int64_t>(items, 4096);
-    hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(256), 0, s, A, emit, ctl, app, hard, g.n, g.ft_log2, g.ntiles);
+    const size_t lds = ((size_t)(kRun + 1) << g.ft_log2) * 4;
+    hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(256), lds, s, A, emit, ctl, app, hard, g.n, g.ft_log2, g.ntiles);
     return hipGetLastError();
 }
 

@@ -77,7 +77,14 @@ def train(spec, shifts, steps=2000, frames=16, T=100, lr=1e-3, snrs=(0.161, 0.15
         if step % log_every == 0 or step == 1 or step == steps:
             lv = float(loss.item())
             history.append((step, lv))
-            log(json.dumps({"step": step, "loss": round(lv, 6), "grad_norm": float(grad.norm().item()),
+            # gradients through long unrolls can exceed float32 range (the
+            # library bounds the adjoints, Adam skips non-finite entries):
+            # report how many entries are finite and the largest of those
+            gd = grad.double()
+            fin = torch.isfinite(gd)
+            gmax = float(gd[fin].abs().max().item()) if bool(fin.any()) else None
+            log(json.dumps({"step": step, "loss": round(lv, 6), "grad_finite_frac": round(float(fin.double().mean()), 4),
+                            "grad_absmax_finite": gmax,
                             "alpha_mean": float(w[..., 0].mean().item()), "beta_mean": float(w[..., 1].mean().item()),
                             "elapsed_s": round(time.perf_counter() - t0, 1)}))
     torch.cuda.synchronize()

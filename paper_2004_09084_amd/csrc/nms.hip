@@ -516,17 +516,23 @@ __global__ void __launch_bounds__(256) k_nms_bwd(const NmsBwdArgs ba) {
     }
 }
 
-// grad[t][i][tau][alpha|beta] = sum over the workgroups of (t, i), fixed order
+// grad[t][i][tau][alpha|beta] = sum over the workgroups of (t, i), fixed
+// order.  The sum is taken in double: with adjoints at their bound (long
+// unrolls) the partials are finite but their float32 sum can overflow; the
+// result saturates at the largest float32 instead of becoming infinite, so
+// it keeps its sign for the optimiser.
 __global__ void k_grad_reduce(const float *part, float *grad, int T, int mb, int per_row) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;  // (t, i, component)
     if (e >= T * mb * 4) return;
     const int comp = e & 3;
     const int ti = e >> 2;
     const float *p = part + (int64_t)ti * per_row * 4 + comp;
-    float s = 0.0f;
-    for (int i = 0; i < per_row; ++i) s += p[(int64_t)i * 4];
+    double s = 0.0;
+    for (int i = 0; i < per_row; ++i) s += (double)p[(int64_t)i * 4];
+    constexpr double kMax = 3.4028234663852886e38;  // largest float32
+    s = s > kMax ? kMax : s < -kMax ? -kMax : s;
     // part components: 0 dalpha(type 1), 1 dbeta(type 1), 2 dalpha(degree 1), 3 dbeta(degree 1)
-    grad[(int64_t)ti * 4 + comp] = s;
+    grad[(int64_t)ti * 4 + comp] = (float)s;
 }
 
 // Adam (Kingma & Ba): m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,

@@ -169,8 +169,8 @@ struct qm_decoder {
     char *nws = nullptr;
     size_t nws_bytes = 0;
     int32_t nT = 0, ntrain = 0;
-    size_t oAd = 0, oAct = 0, oIt = 0, oCols = 0, oLossP = 0, oLoss = 0, oX = 0, ogA = 0, ogAd = 0, ogR = 0, oQ = 0,
-           oCkA = 0, oCkR = 0, oPart = 0, nTotal = 0;
+    size_t oAd = 0, oAct = 0, oTmask = 0, oIt = 0, oCols = 0, oLossP = 0, oLoss = 0, oX = 0, ogA = 0, ogAd = 0,
+           ogR = 0, oQ = 0, oCkA = 0, oCkR = 0, oPart = 0, nTotal = 0;
     std::vector<int32_t> acols;  // columns whose APP lives in A (degree != 1)
     int64_t lds_limit = 0;      // LDS bytes one workgroup may use (queried at bind)
     // LDS-resident codes of a mixed decode run on a side stream, forked from
@@ -1005,6 +1005,7 @@ void nms_layout(qm_decoder &d, const Slot &s, int32_t T, int32_t train) {
     size_t off = 0;
     d.oAd = off; off = align_up(off + fp * m * 4);
     d.oAct = off; off = align_up(off + fp * 4);
+    d.oTmask = off; off = align_up(off + fp * 8);  // one word per tile (at most Fpad tiles)
     d.oIt = off; off = align_up(off + fp * 4);
     d.oCols = off; off = align_up(off + (size_t)s.code->nb * 4);
     // partial loss sums: one per workgroup of the loss kernel (256 lanes)
@@ -1050,6 +1051,7 @@ int nms_init(qm_decoder &d, Slot &s, const float *llr, const uint8_t *syn, hipSt
     QM_HIP(qm_launch_fill_u32(b.fail, 0u, (size_t)s.Fpad, st));
     QM_HIP(qm_launch_commit_d1(b.A, nws_ptr<float>(d, d.oAd), 0, b.rows, c.mb, g, st));
     QM_HIP(qm_launch_fill_u32(nws_ptr<uint32_t>(d, d.oAct), 1u, (size_t)s.Fpad, st));
+    QM_HIP(qm_launch_tile_masks(nws_ptr<uint32_t>(d, d.oAct), nws_ptr<uint64_t>(d, d.oTmask), s.Fpad, g.ft_log2, st));
     QM_HIP(qm_launch_fill_u32(nws_ptr<uint32_t>(d, d.oIt), 0u, (size_t)s.Fpad, st));
     return QM_OK;
 }
@@ -1061,6 +1063,7 @@ int nms_sweep(qm_decoder &d, Slot &s, const float *W, int t, int last, const uin
     na.L.last = last;
     na.W = W + (size_t)t * s.code->mb * 4;
     na.act = act;
+    na.tmask = act ? nws_ptr<uint64_t>(d, d.oTmask) : nullptr;
     na.Q = Q;
     const int G = (int)s.gptr.size() - 1;
     for (int gi = 0; gi < G; ++gi) {
@@ -1511,14 +1514,14 @@ int qm_nms_decode(qm_decoder *d, const float *W, const float *llr, const uint8_t
     if (early_stop) {
         // frames whose channel decisions already satisfy H c = s stop at 0
         QM_HIP(qm_launch_syndrome(b.A, Ad, b.S, b.rows, c.mb, b.fail, g, st));
-        QM_HIP(qm_launch_et_update(b.fail, act, it, s->Fpad, 0, st));
+        QM_HIP(qm_launch_et_update(b.fail, act, nws_ptr<uint64_t>(*d, d->oTmask), it, s->Fpad, g.ft_log2, 0, st));
     }
     for (int t = 0; t < T; ++t) {
         const int last = early_stop ? 1 : (t == T - 1);
         if ((rc = nms_sweep(*d, *s, W, t, last, early_stop ? act : nullptr, nullptr, st)) != QM_OK) return rc;
         if (early_stop) {
             QM_HIP(qm_launch_syndrome(b.A, Ad, b.S, b.rows, c.mb, b.fail, g, st));
-            QM_HIP(qm_launch_et_update(b.fail, act, it, s->Fpad, t + 1, st));
+            QM_HIP(qm_launch_et_update(b.fail, act, nws_ptr<uint64_t>(*d, d->oTmask), it, s->Fpad, g.ft_log2, t + 1, st));
         }
     }
     if (early_stop) {

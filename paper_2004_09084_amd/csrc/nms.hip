@@ -36,18 +36,17 @@ struct Min2 {
         m1 = m2 = kInf;
         p1 = p2 = -1;
     }
+    // branch-free (selects), so that loads after an insertion are not held
+    // behind a divergent branch on the inserted value
     __device__ __forceinline__ void insert(float v, int p) {
-        const bool lt1 = v < m1 || (v == m1 && p < p1);
-        const bool lt2 = v < m2 || (v == m2 && p < p2);
-        if (lt1) {
-            m2 = m1;
-            p2 = p1;
-            m1 = v;
-            p1 = p;
-        } else if (lt2) {
-            m2 = v;
-            p2 = p;
-        }
+        const bool lt1 = (v < m1) | ((v == m1) & (p < p1));
+        const bool lt2 = (v < m2) | ((v == m2) & (p < p2));
+        const float nm2 = lt1 ? m1 : (lt2 ? v : m2);
+        const int np2 = lt1 ? p1 : (lt2 ? p : p2);
+        m1 = lt1 ? v : m1;
+        p1 = lt1 ? p : p1;
+        m2 = nm2;
+        p2 = np2;
     }
     // exclusive minimum for the edge at position p, saturated at 30 (also
     // when p is the only edge)
@@ -98,18 +97,33 @@ __device__ __forceinline__ void check_nms(const LaneCtx &c, ConstRowDesc *rd, co
     ConstF *w = (ConstF *)na.W + row * 4;
     const float a1 = w[0], b1 = w[1], a2 = w[2], b2 = w[3];
 
+    // frames still decoding: the tile's mask (one scalar load; a tile with
+    // none exits as a whole), so no per-lane flag load is waited for before
+    // the first data load
     bool live[FPL];
-    bool any = false;
-    const int f0 = tile * (1 << c.ftl) + (int)(c.node & ((1u << c.ftl) - 1u));
+    const uint64_t tm = na.tmask ? ((const __attribute__((address_space(4))) uint64_t *)na.tmask)[tile] : ~0ull;
+    if (tm == 0ull) return;
+    const int fl0 = (int)(c.node & ((1u << c.ftl) - 1u));
 #pragma unroll
-    for (int f = 0; f < FPL; ++f) {
-        live[f] = na.act ? (na.act[f0 + f] != 0u) : true;
-        any = any || live[f];
-    }
-    if (!any) return;
+    for (int f = 0; f < FPL; ++f) live[f] = ((tm >> (fl0 + f)) & 1ull) != 0ull;
 
     float kap[FPL];
     bload_f32<FPL>(c.rK, vo4, row_so, kap);
+    // the degree-1 APP inputs, loaded here so they are not a round trip of
+    // their own at the end
+    const bool form_d1 = c.last && has_d1;
+    float lam[FPL];
+    if (form_d1) bload_f32<FPL>(c.rA, shifted_off(c, d1shift), (uint32_t)d1col * col_bytes, lam);
+    float q[D > 0 ? D : 1][FPL], av[D > 0 ? D : 1][FPL], rv[D > 0 ? D : 1][FPL];
+    uint32_t aoff[D > 0 ? D : 1];
+    // every load of the check first, then the arithmetic (the two smallest
+    // (value, position) pairs do not depend on the insertion order)
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        aoff[j] = shifted_off(c, sh[j]);
+        bload_f32<FPL>(c.rA, aoff[j], col_so[j], av[j]);
+        bload_f32<FPL>(c.rR, vo4, ent_so[j], rv[j]);
+    }
     bool neg[FPL];
     Min2 mn[FPL];
 #pragma unroll
@@ -118,13 +132,8 @@ __device__ __forceinline__ void check_nms(const LaneCtx &c, ConstRowDesc *rd, co
         mn[f].init();
         if (has_d1) mn[f].insert(fabsf(kap[f]), d1pos);
     }
-    float q[D > 0 ? D : 1][FPL], av[D > 0 ? D : 1][FPL], rv[D > 0 ? D : 1][FPL];
-    uint32_t aoff[D > 0 ? D : 1];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-        aoff[j] = shifted_off(c, sh[j]);
-        bload_f32<FPL>(c.rA, aoff[j], col_so[j], av[j]);
-        bload_f32<FPL>(c.rR, vo4, ent_so[j], rv[j]);
 #pragma unroll
         for (int f = 0; f < FPL; ++f) {
             q[j][f] = av[j][f] - rv[j][f];
@@ -145,18 +154,27 @@ __device__ __forceinline__ void check_nms(const LaneCtx &c, ConstRowDesc *rd, co
         bstore_f32<FPL>(c.rR, vo4, ent_so[j], rm);
         bstore_f32<FPL>(c.rA, aoff[j], col_so[j], an);
     }
-    if (c.last && has_d1) {
-        const uint32_t off = shifted_off(c, d1shift);
-        float lam[FPL], ad_old[FPL], out[FPL];
-        bload_f32<FPL>(c.rA, off, (uint32_t)d1col * col_bytes, lam);
-        if (na.act) bload_f32<FPL>(nd.rAd, vo4, row_so, ad_old);
+    if (form_d1) {
+        float out[FPL];
+        bool all = true;
 #pragma unroll
         for (int f = 0; f < FPL; ++f) {
             // sign: s ^ xor over the degree>=2 edges = neg ^ [lam < 0]
             const float r = nms_msg(neg[f] != (lam[f] < 0.0f), a2, b2, mn[f].excl(d1pos));
-            out[f] = (!na.act || live[f]) ? lam[f] + r : ad_old[f];
+            out[f] = lam[f] + r;
+            all = all && live[f];
         }
-        bstore_f32<FPL>(nd.rAd, vo4, row_so, out);
+        // a stopped frame keeps its degree-1 APPs: only live frames store
+        if (all) {
+            bstore_f32<FPL>(nd.rAd, vo4, row_so, out);
+        } else {
+#pragma unroll
+            for (int f = 0; f < FPL; ++f)
+                if (live[f]) {
+                    const float one[1] = {out[f]};
+                    bstore_f32<1>(nd.rAd, vo4 + 4u * (uint32_t)f, row_so, one);
+                }
+        }
     }
 }
 
@@ -264,15 +282,36 @@ __global__ void __launch_bounds__(256) k_commit_d1(float *__restrict__ A, float 
         *pd = *pa;
 }
 
-// after a syndrome pass: frames that became valid stop (iterations = done)
-__global__ void k_et_update(uint32_t *fail, uint32_t *act, int32_t *iters, int Fpad, int done) {
+// per-tile live masks from the per-frame flags: one ballot per wave, the
+// first lane of each tile's frames stores (FT <= 64 divides the wave)
+__device__ __forceinline__ void store_tile_masks(bool live, int f, int Fpad, int ftl, uint64_t *tmask) {
+    const uint64_t b = __ballot(live);
+    const int FT = 1 << ftl;
+    const int lane = (int)(threadIdx.x & 63u);
+    const uint64_t mask = FT >= 64 ? ~0ull : (1ull << FT) - 1ull;
+    if (f < Fpad && (f & (FT - 1)) == 0) tmask[f >> ftl] = (b >> (lane & ~(FT - 1))) & mask;
+}
+
+__global__ void k_tile_masks(const uint32_t *act, uint64_t *tmask, int Fpad, int ftl) {
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= Fpad) return;
-    if (act[f] && fail[f] == 0u) {
-        act[f] = 0u;
-        iters[f] = done;
+    store_tile_masks(f < Fpad && act[f] != 0u, f, Fpad, ftl, tmask);
+}
+
+// after a syndrome pass: frames that became valid stop (iterations = done)
+__global__ void k_et_update(uint32_t *fail, uint32_t *act, uint64_t *tmask, int32_t *iters, int Fpad, int ftl,
+                            int done) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    bool live = false;
+    if (f < Fpad) {
+        live = act[f] != 0u;
+        if (live && fail[f] == 0u) {
+            live = false;
+            act[f] = 0u;
+            iters[f] = done;
+        }
+        fail[f] = 0u;
     }
-    fail[f] = 0u;
+    store_tile_masks(live, f, Fpad, ftl, tmask);
 }
 
 __global__ void k_et_final(const uint32_t *act, int32_t *iters, int Fpad, int T) {
@@ -632,9 +671,17 @@ hipError_t qm_launch_commit_d1(float *A, float *Ad, int to_A, const RowDesc *row
     return hipGetLastError();
 }
 
-hipError_t qm_launch_et_update(uint32_t *fail, uint32_t *act, int32_t *iters, int Fpad, int done, hipStream_t s) {
-    hipLaunchKernelGGL(k_et_update, dim3((unsigned)((Fpad + 255) / 256)), dim3(256), 0, s, fail, act, iters, Fpad,
-                       done);
+hipError_t qm_launch_et_update(uint32_t *fail, uint32_t *act, uint64_t *tmask, int32_t *iters, int Fpad, int ft_log2,
+                               int done, hipStream_t s) {
+    if (ft_log2 < 0 || ft_log2 > 6 || (Fpad & ((1 << ft_log2) - 1))) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_et_update, dim3((unsigned)((Fpad + 255) / 256)), dim3(256), 0, s, fail, act, tmask, iters,
+                       Fpad, ft_log2, done);
+    return hipGetLastError();
+}
+
+hipError_t qm_launch_tile_masks(const uint32_t *act, uint64_t *tmask, int Fpad, int ft_log2, hipStream_t s) {
+    if (ft_log2 < 0 || ft_log2 > 6 || (Fpad & ((1 << ft_log2) - 1))) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_tile_masks, dim3((unsigned)((Fpad + 255) / 256)), dim3(256), 0, s, act, tmask, Fpad, ft_log2);
     return hipGetLastError();
 }
 

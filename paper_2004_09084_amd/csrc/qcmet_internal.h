@@ -130,6 +130,7 @@ struct NmsLayerArgs {
     float *Q;                 // [ntiles][nent1*Z][FT] q recorded for the backward pass, or null
     const float *W;           // this sweep's weights [mb][2 target types][alpha, beta]
     const uint32_t *act;      // [Fpad] per-frame active flags (early termination), or null
+    const uint64_t *tmask;    // [ntiles] the same per tile (bit fl), with act
 };
 
 struct NmsBwdArgs {
@@ -231,7 +232,10 @@ hipError_t qm_launch_nms_bwd(const NmsBwdArgs &ba, int maxd, int fpl, int block,
 // to_A = 1: A[d1col][(k + a) mod Z] = Ad[row][k]; to_A = 0: the reverse.
 hipError_t qm_launch_commit_d1(float *A, float *Ad, int to_A, const RowDesc *rows, int mb, const TileGeom &g,
                                hipStream_t s);
-hipError_t qm_launch_et_update(uint32_t *fail, uint32_t *act, int32_t *iters, int Fpad, int done, hipStream_t s);
+hipError_t qm_launch_et_update(uint32_t *fail, uint32_t *act, uint64_t *tmask, int32_t *iters, int Fpad, int ft_log2,
+                               int done, hipStream_t s);
+// tmask[tile] = bits fl of the slots tile*FT + fl with act != 0
+hipError_t qm_launch_tile_masks(const uint32_t *act, uint64_t *tmask, int Fpad, int ft_log2, hipStream_t s);
 hipError_t qm_launch_et_final(const uint32_t *act, int32_t *iters, int Fpad, int T, hipStream_t s);
 int qm_bce_blocks(int ncols, int mb, const TileGeom &g);
 hipError_t qm_launch_bce(const float *A, const float *Ad, const uint8_t *X, float *gA, float *gAd, float *part,

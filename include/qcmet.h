@@ -204,14 +204,17 @@ int qm_decode_early(qm_decoder *dec, const float *llr, const uint8_t *syndrome, 
                     uint8_t *hard, float *app, uint8_t *flags, int32_t *iters_used, void *stream);
 
 /* Times result-preserving tunings on the given inputs and keeps the fastest:
- * frames per tile {16, 32, 64} x frames per lane {1, 2} x block {128, 256},
- * then, on the best, per-row launches, unfused codes, graph replay, the
- * other stream_hint, (if a code fits) the other lds_resident and (one code)
- * 2 and 4 tile groups.  The
- * schedule (row order) is never changed, so every trial decodes to the same
- * bits.  Each trial decodes min(iters, 8) sweeps into the caller's output
- * buffers (same shapes as qm_decode); the call synchronises the stream.
- * cache_path (may be NULL) gets one JSON line appended per trial. */
+ * frames per tile {16, 32, 64} x frames per lane {1, 2} x block {128, 256}
+ * (each trial decoding min(iters, 8) sweeps), then, on the best, per-row
+ * launches, the other mixed-batch mode (streams per code or fused launches),
+ * graph replay, the other stream_hint, (if a code fits) the other
+ * lds_resident, (one code) 2 and 4 tile groups and (fused launches) the
+ * other spread_codes, each decoding min(iters, 256) sweeps: a graph or extra
+ * streams over a few sweeps do not predict the whole decode.  The schedule
+ * (row order) is never changed, so every trial decodes to the same bits.
+ * Trials decode into the caller's output buffers (same shapes as
+ * qm_decode); the call synchronises the stream.  cache_path (may be NULL)
+ * gets one JSON line appended per trial. */
 int qm_autotune(qm_decoder *dec, const float *llr, const uint8_t *syndrome, int32_t iters,
                 uint8_t *hard, float *app, uint8_t *flags, const char *cache_path, void *stream);
 

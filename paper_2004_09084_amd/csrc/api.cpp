@@ -1636,13 +1636,13 @@ int qm_autotune(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t ite
     int ncodes = 0;
     for (const Slot &s : d->slots) ncodes += s.F > 0 ? 1 : 0;
 
-    auto trial = [&](const qm_tuning &t, float *ms) -> int {
+    auto trial = [&](const qm_tuning &t, float *ms, int n) -> int {
         d->tun = t;
         drop_graph(*d);
-        int rc = qm_decode(d, llr, syn, probe, hard, app, flags, stream);  // warm-up (and capture)
+        int rc = qm_decode(d, llr, syn, n, hard, app, flags, stream);  // warm-up (and capture)
         if (rc != QM_OK) return rc;
         QM_HIP(hipEventRecord(e0, st));
-        for (int r = 0; r < 2 && rc == QM_OK; ++r) rc = qm_decode(d, llr, syn, probe, hard, app, flags, stream);
+        for (int r = 0; r < 2 && rc == QM_OK; ++r) rc = qm_decode(d, llr, syn, n, hard, app, flags, stream);
         if (rc != QM_OK) return rc;
         QM_HIP(hipEventRecord(e1, st));
         QM_HIP(hipEventSynchronize(e1));
@@ -1655,7 +1655,7 @@ int qm_autotune(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t ite
                          "\"fuse_codes\": %d, \"graph\": %d, \"stream_hint\": %d, \"lds_resident\": %d, "
                          "\"tile_groups\": %d, \"spread_codes\": %d, \"iters\": %d, \"ms\": %.4f}\n",
                          t.frames_per_tile, t.frames_per_lane, t.block, t.merge, t.fuse_codes, t.graph,
-                         t.stream_hint, t.lds_resident, t.tile_groups, t.spread_codes, probe, *ms);
+                         t.stream_hint, t.lds_resident, t.tile_groups, t.spread_codes, n, *ms);
         return QM_OK;
     };
 
@@ -1671,10 +1671,9 @@ int qm_autotune(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t ite
                 t.frames_per_lane = fpls[b];
                 t.block = blocks[c];
                 t.merge = 1;
-                t.fuse_codes = 1;
                 t.graph = 0;
                 float ms = 0.0f;
-                rc = trial(t, &ms);
+                rc = trial(t, &ms, probe);
                 if (rc == QM_OK && ms < best_ms) {
                     best_ms = ms;
                     best = t;
@@ -1688,7 +1687,11 @@ int qm_autotune(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t ite
         for (const Slot &s : d->slots) lds_candidate = lds_candidate || lds_slot(*d, s);
         d->tun = keep;
     }
-    // structural variants on top of the best launch shape
+    // structural variants on top of the best launch shape, timed over the
+    // full sweep count (at most 256): a graph captured for a few sweeps, or
+    // extra streams over a few sweeps, do not predict the whole decode
+    const int full = std::min<int>(iters, 256);
+    if (rc == QM_OK) rc = trial(best, &best_ms, full);
     for (int v = 0; v < 8 && rc == QM_OK; ++v) {
         qm_tuning t = best;
         if (v == 7) {
@@ -1711,7 +1714,7 @@ int qm_autotune(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t ite
         }
         if (v == 2) t.graph = 1;
         float ms = 0.0f;
-        rc = trial(t, &ms);
+        rc = trial(t, &ms, full);
         if (rc == QM_OK && ms < best_ms) {
             best_ms = ms;
             best = t;

@@ -102,6 +102,9 @@ def main():
     ap.add_argument("--flooding", action="store_true", help="flooding schedule instead of layers")
     ap.add_argument("--early-stop", action="store_true",
                     help="qm_decode_early: frames stop once H c = s (iterations = the maximum)")
+    ap.add_argument("--end-to-end", action="store_true",
+                    help="also time decodes that include copying the LLRs and syndromes from pinned host memory "
+                         "and the hard decisions and flags back (reported beside the value, never as it)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run one plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -245,6 +248,35 @@ def main():
                     "timing": "HIP events around whole sweeps on the decode stream"
                               + (" (first sweep of each decode, every tile decoding)" if args.early_stop else "")}
 
+    e2e = None
+    if args.end_to_end:
+        # pinned host copies of the inputs and outputs (allocated pinned, not
+        # registered); each timed step copies in, decodes, copies out
+        h_llr = torch.empty(llr.numel(), dtype=llr.dtype, pin_memory=True)
+        h_syn = torch.empty(syn.numel(), dtype=syn.dtype, pin_memory=True)
+        h_llr.copy_(llr.cpu())
+        h_syn.copy_(syn.cpu())
+        h_hard = torch.empty(out[0].numel(), dtype=out[0].dtype, pin_memory=True)
+        h_flags = torch.empty(out[2].numel(), dtype=out[2].dtype, pin_memory=True)
+
+        def e2e_step():
+            llr.copy_(h_llr, non_blocking=True)
+            syn.copy_(h_syn, non_blocking=True)
+            step()
+            h_hard.copy_(out[0], non_blocking=True)
+            h_flags.copy_(out[2], non_blocking=True)
+
+        e2e_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            e2e_step()
+        torch.cuda.synchronize()
+        dt_e = (time.perf_counter() - t0) / args.steps
+        e2e = {"value": round(bits / 1e6 / dt_e, 3), "unit": "Mbit/s", "ms_per_step": round(dt_e * 1e3, 3),
+               "copies": "LLR + syndrome host-to-device, hard decisions + flags device-to-host, pinned host memory, "
+                         "not overlapped with the decode"}
+
     early = None
     cpu_iters = iters
     if args.early_stop:
@@ -277,6 +309,7 @@ def main():
         "hbm_gbs": None if roofline is None else roofline["achieved"],
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "end_to_end": e2e,
     }
     print(json.dumps(line), flush=True)
 

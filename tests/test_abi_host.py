@@ -133,3 +133,33 @@ def test_decode_without_workspace_fails_before_any_device_work():
     assert rc == Q.QM_ERR_NO_WORKSPACE
     assert b"workspace" in Q.lib().qm_last_error()
     Q.qm_decoder_destroy(d)
+
+
+def _header_struct_fields(name):
+    """(field, C type) pairs of `typedef struct { ... } name;` in the header,
+    in declaration order (comments removed; `T a, b;` gives two fields)."""
+    txt = open(os.path.join(ROOT, "include", "qcmet.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    m = re.search(r"typedef struct \{([^{}]*)\}\s*" + name + r"\s*;", txt)
+    assert m, name
+    out = []
+    for decl in m.group(1).split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        ctype, names = decl.split(None, 1)
+        out += [(n.strip(), ctype) for n in names.split(",")]
+    return out
+
+
+@pytest.mark.parametrize("name,cls", [("qm_code_info", Q.qm_code_info), ("qm_tuning", Q.qm_tuning),
+                                      ("qm_profile", Q.qm_profile)])
+def test_binding_structs_match_header(name, cls):
+    # the ctypes mirrors of the header's structs: same fields, order and types
+    ctypes_of = {"int32_t": ctypes.c_int32, "int64_t": ctypes.c_int64, "double": ctypes.c_double,
+                 "uint32_t": ctypes.c_uint32}
+    hdr = _header_struct_fields(name)
+    got = [(f, t) for f, t in cls._fields_]
+    assert [f for f, _ in hdr] == [f for f, _ in got], name
+    for (f, ct), (_, pt) in zip(hdr, got):
+        assert ctypes_of[ct] is pt, (name, f, ct, pt)

@@ -102,6 +102,9 @@ def main():
     ap.add_argument("--flooding", action="store_true", help="flooding schedule instead of layers")
     ap.add_argument("--early-stop", action="store_true",
                     help="qm_decode_early: frames stop once H c = s (iterations = the maximum)")
+    ap.add_argument("--gpu-frames", action="store_true",
+                    help="draw the frames on the GPU (library Philox generator) instead of numpy on the host; "
+                         "for large --frames (no CPU baseline then)")
     ap.add_argument("--end-to-end", action="store_true",
                     help="also time decodes that include copying the LLRs and syndromes from pinned host memory "
                          "and the hard decisions and flags back (reported beside the value, never as it)")
@@ -130,19 +133,52 @@ def main():
     F = sum(Fs)
     torch.cuda.set_device(0)
 
-    wls = []
-    for spec, Fc in zip(specs, Fs):
-        snr = spec.snr if args.snr is None else args.snr
-        print(f"[bench] generating {Fc} frames of {spec.name} (n={spec.n}) at SNR {snr}", file=sys.stderr, flush=True)
-        wls.append(W.build(spec, Fc, graph_seed=0, frame_seed=args.frame_seed, snr=snr))
-    llr = torch.from_numpy(np.concatenate([w.llr.reshape(-1) for w in wls])).cuda()
-    syn = torch.from_numpy(np.concatenate([w.s.reshape(-1) for w in wls])).cuda()
-    codes = [Q.Code(w.shifts, spec.Z) for w, spec in zip(wls, specs)]
     tuning = json.loads(args.tuning) if args.tuning else None
     flags = (Q.QM_MSG_FP16 if args.fp16 else 0) | (Q.QM_MSG_FP8 if args.fp8 else 0) \
         | (Q.QM_EARLY_STOP if args.early_stop else 0) | (Q.QM_FLOODING if args.flooding else 0)
     msg_name = "FP16" if args.fp16 else "FP8 (e4m3)" if args.fp8 else "FP32"
-    dec = Q.Decoder(codes, Fs, flags=flags, tuning=tuning)
+    if args.gpu_frames:
+        # frames drawn on the device by the library's Philox generator (keyed
+        # by the frame seed and frame index): for large frame counts, whose
+        # host generation would take minutes; same code construction
+        import types
+        args.no_cpu_baseline = True
+        codes, wls = [], []
+        for spec in specs:
+            shifts = W.make_code(spec, 0)
+            codes.append(Q.Code(shifts, spec.Z))
+            wls.append(types.SimpleNamespace(shifts=shifts, meta={"snr": spec.snr if args.snr is None else args.snr}))
+        dec = Q.Decoder(codes, Fs, flags=flags, tuning=tuning)
+        n_all = sum(Fc * spec.n for Fc, spec in zip(Fs, specs))
+        m_all = sum(Fc * spec.m for Fc, spec in zip(Fs, specs))
+        x = torch.empty(n_all, dtype=torch.uint8, device="cuda")
+        llr = torch.empty(n_all, dtype=torch.float32, device="cuda")
+        syn = torch.empty(m_all, dtype=torch.uint8, device="cuda")
+        on = om = 0
+        for c, (spec, Fc, w) in enumerate(zip(specs, Fs, wls)):
+            print(f"[bench] drawing {Fc} frames of {spec.name} (n={spec.n}) at SNR {w.meta['snr']} on the GPU",
+                  file=sys.stderr, flush=True)
+            Q.qm_generate_frames(dec.handle, c, args.frame_seed, 0, w.meta["snr"], Fc, x[on:on + Fc * spec.n],
+                                 llr[on:on + Fc * spec.n], syn[om:om + Fc * spec.m])
+            on += Fc * spec.n
+            om += Fc * spec.m
+        torch.cuda.synchronize()
+        on = 0
+        for spec, Fc, w in zip(specs, Fs, wls):
+            w.x = x[on:on + Fc * spec.n].cpu().numpy().reshape(Fc, -1)
+            on += Fc * spec.n
+        del x
+    else:
+        wls = []
+        for spec, Fc in zip(specs, Fs):
+            snr = spec.snr if args.snr is None else args.snr
+            print(f"[bench] generating {Fc} frames of {spec.name} (n={spec.n}) at SNR {snr}", file=sys.stderr,
+                  flush=True)
+            wls.append(W.build(spec, Fc, graph_seed=0, frame_seed=args.frame_seed, snr=snr))
+        llr = torch.from_numpy(np.concatenate([w.llr.reshape(-1) for w in wls])).cuda()
+        syn = torch.from_numpy(np.concatenate([w.s.reshape(-1) for w in wls])).cuda()
+        codes = [Q.Code(w.shifts, spec.Z) for w, spec in zip(wls, specs)]
+        dec = Q.Decoder(codes, Fs, flags=flags, tuning=tuning)
     out = dec.alloc_outputs(want_app=True)
     iters_used = None
 
@@ -296,7 +332,7 @@ def main():
         "value": round(mbit_s, 3), "unit": "Mbit/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if msg_name == "FP32" else f"f32 ({msg_name} messages)", "data": "synthetic",
+        "dtype": "f32" if msg_name == "FP32" else f"f32 ({msg_name} messages)", "data": "synthetic" + (" (frames drawn on the GPU)" if args.gpu_frames else ""),
         "config": {"workload": " + ".join(
                        f"{Fc} x {spec.name} (rate {spec.rate:.2f} QC-MET-LDPC, {spec.mb}x{spec.nb} base, Z={spec.Z}, "
                        f"n={spec.n}, SNR {w.meta['snr']})" for w, spec, Fc in zip(wls, specs, Fs))

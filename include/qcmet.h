@@ -119,6 +119,15 @@ typedef struct {
                                  launch carries a similar share of the traffic; 0 runs every code
                                  from the first launch until its layers are done.  Each code
                                  keeps its own layer order, so results are bit-identical. */
+    int32_t frames_per_batch; /* layered decode of one code: frames whose sweeps run together.  With
+                                 more frames, whole frame tiles are decoded in batches, one batch's
+                                 sweeps after another's (each launch then touches one batch's state:
+                                 past about 12 GiB of per-frame state, address translation slows
+                                 every launch).  0 (default): all frames while their state stays
+                                 within 12 GiB, else batches of the largest power-of-two tile count
+                                 within it; otherwise rounded down to whole tiles (at least one).
+                                 Frames never
+                                 depend on other frames, so results are bit-identical. */
 } qm_tuning;
 
 int qm_abi_version(void);

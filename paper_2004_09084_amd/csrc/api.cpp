@@ -404,11 +404,31 @@ int enqueue_finalize(qm_decoder &d, uint8_t *hard, float *app, uint8_t *flags, h
 // Sweeps of one code, one launch per layer (or per row with merge = 0).
 // Tile groups of a layered decode (tuning tile_groups): usable count for a
 // code (it must divide the number of tiles).
-int tile_groups(const qm_decoder &d, const Slot &s) {
-    const int nt = geom(d, s).ntiles;
+// tile groups (tuning tile_groups) usable over nt tiles: a divisor of nt
+int tile_groups(const qm_decoder &d, int nt) {
     int g = std::max(1, std::min<int>(d.tun.tile_groups, nt));
     while (g > 1 && nt % g) --g;
     return g;
+}
+
+// Frame tiles decoded together by a layered decode of one code (tuning
+// frames_per_batch): all of them unless their per-frame state (APPs,
+// messages, K, syndrome bits) exceeds kBatchBytes, then batches of the
+// largest power-of-two tile count within it (a multiple of the 8 XCDs keeps
+// each tile's workgroups on one XCD); an explicit frames_per_batch is
+// rounded down to whole tiles.
+constexpr size_t kBatchBytes = (size_t)12 << 30;
+
+int batch_tiles(const qm_decoder &d, const Slot &s) {
+    const TileGeom g = geom(d, s);
+    const int ft = 1 << g.ft_log2;
+    if (d.tun.frames_per_batch > 0)
+        return (int)std::max<int64_t>(1, std::min<int64_t>(g.ntiles, d.tun.frames_per_batch / ft));
+    const size_t per_frame = (size_t)s.n * 4 + (size_t)s.code->nent1 * s.code->Z * msg_bytes(d) + (size_t)s.m * 5;
+    if ((size_t)g.ntiles * ft * per_frame <= kBatchBytes) return g.ntiles;
+    int64_t bt = 1;
+    while ((size_t)(bt * 2) * ft * per_frame <= kBatchBytes) bt *= 2;
+    return (int)std::min<int64_t>(g.ntiles, bt);
 }
 
 int ensure_group_streams(qm_decoder &d, int groups) {
@@ -428,13 +448,34 @@ int ensure_group_streams(qm_decoder &d, int groups) {
 // With tile groups, each group of consecutive frame tiles runs its own layer
 // sequence on its own stream (frames never depend on other frames), so one
 // group's launch can fill the ramp-down of another's.
+int enqueue_sweeps_tiles(qm_decoder &d, Slot &s, int32_t iters, hipStream_t st, int t0, int nt, bool profile);
+
 int enqueue_sweeps_slot(qm_decoder &d, Slot &s, int32_t iters, hipStream_t st) {
+    const int ntiles = geom(d, s).ntiles;
+    const int bt = batch_tiles(d, s);
+    for (int t0 = 0; t0 < ntiles; t0 += bt) {
+        const int rc = enqueue_sweeps_tiles(d, s, iters, st, t0, std::min(bt, ntiles - t0), t0 == 0);
+        if (rc != QM_OK) return rc;
+    }
+    return QM_OK;
+}
+
+// The sweeps of tiles [t0, t0 + nt) of one code; profile: time the middle
+// sweeps (the first batch of a batched decode).
+int enqueue_sweeps_tiles(qm_decoder &d, Slot &s, int32_t iters, hipStream_t st, int t0, int nt, bool profile) {
     const int msgk = msg_kind(d);
     const size_t msg = msg_bytes(d);
     const RowDesc *rows = slot_bufs(d, s).rows;
     LayerArgs la = layer_args(d, s);
+    la.A += (int64_t)t0 * la.strideA;
+    la.R = static_cast<char *>(la.R) + (int64_t)t0 * la.strideR * (int64_t)msg;
+    la.K += (int64_t)t0 * la.strideK;
+    la.ntiles = nt;
+    // share of the code's frames in these tiles (padding frames excluded)
+    const int ft = 1 << la.ft_log2;
+    const double share = (double)std::max(0, std::min(nt * ft, s.F - t0 * ft)) / (double)std::max(s.F, 1);
     const int G = (int)s.gptr.size() - 1;
-    const int ng = tile_groups(d, s);
+    const int ng = tile_groups(d, nt);
     std::vector<LayerArgs> lg(ng, la);
     std::vector<hipStream_t> gs(ng, st);
     if (ng > 1) {
@@ -453,7 +494,7 @@ int enqueue_sweeps_slot(qm_decoder &d, Slot &s, int32_t iters, hipStream_t st) {
     // profiled: up to 4 sweeps from the middle of the decode, never the last
     // (which also forms the degree-1 APPs); one event pair per sweep, so no
     // event sits between two layer launches
-    const int t0p = (iters - 1) / 2, t1p = d.profiling ? std::min(t0p + 4, iters - 1) : -1;
+    const int t0p = (iters - 1) / 2, t1p = (d.profiling && profile) ? std::min(t0p + 4, iters - 1) : -1;
     for (int t = 0; t < iters; ++t) {
         const bool prof = t >= t0p && t < t1p;
         // with tile groups the window is timed on the decode stream, where
@@ -475,8 +516,8 @@ int enqueue_sweeps_slot(qm_decoder &d, Slot &s, int32_t iters, hipStream_t st) {
                 }
                 double b, ch;
                 layer_work(s, s.hrows.data() + p, step, msg, &b, &ch);
-                bytes += b;
-                checks += ch;
+                bytes += b * share;
+                checks += ch * share;
                 ++launches;
             }
         }
@@ -1264,6 +1305,7 @@ int qm_decoder_create(const qm_code *const *codes, int32_t ncodes, const int32_t
     d->tun.stream_hint = 1;
     d->tun.tile_groups = 1;
     d->tun.spread_codes = 1;
+    d->tun.frames_per_batch = 0;
     layout(*d);
     *out = d;
     return QM_OK;
@@ -1334,6 +1376,7 @@ int qm_decoder_set_tuning(qm_decoder *d, const qm_tuning *t) {
     n.stream_hint = n.stream_hint ? 1 : 0;
     n.lds_resident = n.lds_resident ? 1 : 0;
     n.spread_codes = n.spread_codes ? 1 : 0;
+    if (n.frames_per_batch < 0) return fail(QM_ERR_INVALID_ARG, "frames_per_batch must be >= 0");
     if (n.tile_groups == 0) n.tile_groups = 1;
     if (n.tile_groups != 1 && n.tile_groups != 2 && n.tile_groups != 4 && n.tile_groups != 8)
         return fail(QM_ERR_INVALID_ARG, "tile_groups must be 1, 2, 4 or 8");

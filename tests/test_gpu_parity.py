@@ -345,6 +345,25 @@ def test_tile_groups_are_bit_identical():
         torch.ones(8, device="cuda").mul_(2.0)
 
 
+def test_frame_batches_are_bit_identical():
+    # frame tiles decoded in batches, one batch's sweeps after another's
+    # (with and without tile groups inside a batch, and a last batch that is
+    # smaller): every output is unchanged
+    wl = _wl(SMALL, 56, snr=0.3, seed=10)
+    ref = gpu_decode(wl.shifts, SMALL.Z, wl.llr, wl.s, 9, tuning=dict(frames_per_tile=8))
+    for tun in (dict(frames_per_tile=8, frames_per_batch=16), dict(frames_per_tile=8, frames_per_batch=24),
+                dict(frames_per_tile=8, frames_per_batch=8, merge=0),
+                dict(frames_per_tile=8, frames_per_batch=32, tile_groups=2), dict(frames_per_tile=8, frames_per_batch=5)):
+        got = gpu_decode(wl.shifts, SMALL.Z, wl.llr, wl.s, 9, tuning=tun)
+        for x, y in zip(got, ref):
+            assert np.array_equal(x, y), tun
+    fp16 = gpu_decode(wl.shifts, SMALL.Z, wl.llr, wl.s, 9, flags=Q.QM_MSG_FP16, tuning=dict(frames_per_tile=8))
+    got = gpu_decode(wl.shifts, SMALL.Z, wl.llr, wl.s, 9, flags=Q.QM_MSG_FP16,
+                     tuning=dict(frames_per_tile=8, frames_per_batch=16))
+    for x, y in zip(got, fp16):
+        assert np.array_equal(x, y)
+
+
 def test_tile_groups_fullsize():
     import torch
     spec = W.RATE01

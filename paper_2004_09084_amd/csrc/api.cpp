@@ -401,10 +401,8 @@ int enqueue_finalize(qm_decoder &d, uint8_t *hard, float *app, uint8_t *flags, h
     return QM_OK;
 }
 
-// Sweeps of one code, one launch per layer (or per row with merge = 0).
-// Tile groups of a layered decode (tuning tile_groups): usable count for a
-// code (it must divide the number of tiles).
-// tile groups (tuning tile_groups) usable over nt tiles: a divisor of nt
+// Tile groups (tuning tile_groups) usable over nt frame tiles: the largest
+// count not above the tuning value that divides nt.
 int tile_groups(const qm_decoder &d, int nt) {
     int g = std::max(1, std::min<int>(d.tun.tile_groups, nt));
     while (g > 1 && nt % g) --g;
@@ -444,12 +442,11 @@ int ensure_group_streams(qm_decoder &d, int groups) {
     return QM_OK;
 }
 
-// Sweeps of one code, one launch per layer (or per row with merge = 0).
-// With tile groups, each group of consecutive frame tiles runs its own layer
-// sequence on its own stream (frames never depend on other frames), so one
-// group's launch can fill the ramp-down of another's.
 int enqueue_sweeps_tiles(qm_decoder &d, Slot &s, int32_t iters, hipStream_t st, int t0, int nt, bool profile);
 
+// Sweeps of one code, one launch per layer (or per row with merge = 0), over
+// its frame tiles in batches (batch_tiles): each batch runs every sweep before
+// the next starts.
 int enqueue_sweeps_slot(qm_decoder &d, Slot &s, int32_t iters, hipStream_t st) {
     const int ntiles = geom(d, s).ntiles;
     const int bt = batch_tiles(d, s);
@@ -461,7 +458,10 @@ int enqueue_sweeps_slot(qm_decoder &d, Slot &s, int32_t iters, hipStream_t st) {
 }
 
 // The sweeps of tiles [t0, t0 + nt) of one code; profile: time the middle
-// sweeps (the first batch of a batched decode).
+// sweeps (the first batch of a batched decode). With tile groups, each group
+// of consecutive tiles runs its own layer sequence on its own stream (frames
+// never depend on other frames), so one group's launch can fill the
+// ramp-down of another's.
 int enqueue_sweeps_tiles(qm_decoder &d, Slot &s, int32_t iters, hipStream_t st, int t0, int nt, bool profile) {
     const int msgk = msg_kind(d);
     const size_t msg = msg_bytes(d);

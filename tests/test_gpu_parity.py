@@ -364,6 +364,28 @@ def test_frame_batches_are_bit_identical():
         assert np.array_equal(x, y)
 
 
+def test_frame_batches_graph_replays_match_eager():
+    # batched sweeps inside a captured graph, replayed with eager work between
+    # replays: every replay equals the unbatched eager decode
+    import torch
+    wl = _wl(SMALL, 40, snr=0.3, seed=12)
+    ref = gpu_decode(wl.shifts, SMALL.Z, wl.llr, wl.s, 7, tuning=dict(frames_per_tile=8))
+    code = Q.Code(wl.shifts, SMALL.Z)
+    dec = Q.Decoder([code], [40], tuning=dict(frames_per_tile=8, frames_per_batch=16, graph=1))
+    L, S = to_dev(wl.llr), to_dev(wl.s)
+    out = dec.alloc_outputs()
+    for rep in range(3):
+        dec.decode(L, S, 7, out=out)
+        torch.cuda.synchronize()
+        junk = torch.randn(1 << 16, device="cuda").sum()
+        torch.cuda.synchronize()
+        assert np.array_equal(out[0].cpu().numpy().reshape(40, -1), ref[0]), rep
+        assert np.array_equal(out[1].cpu().numpy().reshape(40, -1), ref[1]), rep
+        assert np.array_equal(out[2].cpu().numpy(), ref[2]), rep
+        out[1].fill_(7.0)
+        out[0].fill_(3)
+
+
 def test_tile_groups_fullsize():
     import torch
     spec = W.RATE01

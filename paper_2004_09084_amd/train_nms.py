@@ -91,6 +91,30 @@ def train(spec, shifts, steps=2000, frames=16, T=100, lr=1e-3, snrs=(0.161, 0.15
     return w, history, time.perf_counter() - t0
 
 
+def heldout_loss(spec, shifts, weights, T, frames=16, snrs=(0.161, 0.15), seed=1, batches=8):
+    """Mean training loss (BCE of the sweep-T APPs against the transmitted
+    bits) over fresh frames drawn with another generator seed."""
+    import torch
+    code = Q.Code(shifts, spec.Z)
+    dec = Q.Decoder([code], [frames])
+    dec.nms_bind(T, train=True)
+    x = torch.empty(frames * spec.n, dtype=torch.uint8, device="cuda")
+    llr = torch.empty(frames * spec.n, dtype=torch.float32, device="cuda")
+    syn = torch.empty(frames * spec.m, dtype=torch.uint8, device="cuda")
+    per = frames // len(snrs)
+    w = weights[:T].contiguous()
+    total = 0.0
+    for b in range(batches):
+        for i, snr in enumerate(snrs):
+            F = per if i < len(snrs) - 1 else frames - per * (len(snrs) - 1)
+            o = i * per
+            Q.qm_generate_frames(dec.handle, 0, seed, b * frames + o, snr, F, x[o * spec.n:(o + F) * spec.n],
+                                 llr[o * spec.n:(o + F) * spec.n], syn[o * spec.m:(o + F) * spec.m])
+        loss, _ = dec.nms_loss_grad(w, llr, syn, x, T)
+        total += float(loss.item())
+    return total / batches
+
+
 def evaluate(spec, shifts, weights, T_nms=100, T_sp=200, frames=128, frame_seed=2, snr=None, log=print):
     """FER / mean iterations / Mbit/s of min-sum (+ sum-product fallback) and
     of plain sum-product on one seeded batch."""
@@ -150,6 +174,7 @@ def evaluate(spec, shifts, weights, T_nms=100, T_sp=200, frames=128, frame_seed=
         be = bit_errors(hard)
         err = be.any(axis=1)
         res[name] = {"fer_minsum_only": float(frame_errors(hn).mean()),
+                     "ber_minsum_only": float(bit_errors(hn).mean()),
                      "syndrome_fail_minsum_only": float(1 - ok.mean()),
                      "converged": int(ok.sum()),
                      "ber_with_fallback": float(be.mean()),
@@ -174,6 +199,8 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--eval-frames", type=int, default=128)
+    ap.add_argument("--train-snrs", default="0.161,0.15",
+                    help="SNRs of the training frames, an equal share of each batch per SNR")
     ap.add_argument("--eval-snrs", default="0.161")
     ap.add_argument("--save", default=None, help="write trained weights (.npy)")
     ap.add_argument("--load", default=None, help="start from weights (.npy)")
@@ -187,12 +214,21 @@ def main():
     w = w0
     T_train = args.T_train or args.T
     if args.steps > 0:
-        w, hist, secs = train(spec, shifts, steps=args.steps, frames=args.frames, T=T_train, lr=args.lr,
+        snrs = tuple(float(x) for x in args.train_snrs.split(",") if x)
+        w, hist, secs = train(spec, shifts, steps=args.steps, frames=args.frames, T=T_train, lr=args.lr, snrs=snrs,
                               seed=args.seed, weights=None if w0 is None else w0[:T_train].contiguous())
-        print(json.dumps({"trained_steps": args.steps, "T_train": T_train, "train_seconds": round(secs, 1),
+        print(json.dumps({"trained_steps": args.steps, "T_train": T_train, "train_snrs": snrs,
+                          "train_seconds": round(secs, 1),
                           "loss_first": hist[0][1], "loss_last": hist[-1][1]}), flush=True)
     if w is None:
         w = plain_minsum_weights(args.T, spec.mb)
+    if args.steps > 0:
+        # the training objective on frames it never saw, trained against plain min-sum
+        snrs = tuple(float(x) for x in args.train_snrs.split(",") if x)
+        lt = heldout_loss(spec, shifts, w, T_train, frames=args.frames, snrs=snrs, seed=args.seed + 1)
+        lp = heldout_loss(spec, shifts, plain_minsum_weights(T_train, spec.mb), T_train, frames=args.frames, snrs=snrs,
+                          seed=args.seed + 1)
+        print(json.dumps({"heldout_loss_trained": round(lt, 6), "heldout_loss_plain_minsum": round(lp, 6)}), flush=True)
     w = extend_weights(w, args.T)
     if args.save:
         np.save(args.save, w.cpu().numpy())

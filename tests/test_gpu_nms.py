@@ -1,6 +1,7 @@
 """Learned decoder (normalized/offset min-sum) on the GPU against the FP64
 oracle: forward APPs, early-stop iteration counts, loss and weight
-gradients; determinism of the gradient reduction; the Adam step."""
+gradients; determinism of the gradient reduction; the Adam step; a short
+training run lowering the loss on unseen frames."""
 import numpy as np
 import pytest
 
@@ -163,6 +164,23 @@ def test_adam_step_matches_numpy():
     w2 = w - 1e-3 * (m2 / (1 - 0.9 ** 5)) / (np.sqrt(v2 / (1 - 0.999 ** 5)) + 1e-8)
     assert np.allclose(wd.cpu().numpy(), w2, rtol=1e-5, atol=1e-7)
     assert np.allclose(md.cpu().numpy(), m2, rtol=1e-5, atol=1e-7)
+
+
+def test_training_lowers_the_loss_on_unseen_frames():
+    # what the learned weights gain over plain min-sum, on the objective they
+    # are trained for: a short run (frames drawn on the GPU, exact gradients
+    # from the reverse sweeps, Adam) on the small rate-0.1 code, then the
+    # loss on frames from another generator seed.  The FP64 oracle running
+    # the same recipe (its own frames) ends at 0.61 against 0.86.
+    from paper_2004_09084_amd import train_nms as TN
+    H = W.make_code(SMALL, 0)
+    T = 10
+    w, hist, _ = TN.train(SMALL, H, steps=150, frames=16, T=T, lr=1e-2, seed=3, log_every=1000, log=lambda *_: None)
+    lt = TN.heldout_loss(SMALL, H, w, T, frames=16, seed=4, batches=4)
+    lp = TN.heldout_loss(SMALL, H, TN.plain_minsum_weights(T, SMALL.mb), T, frames=16, seed=4, batches=4)
+    say("training loss", hist[0][1], "->", hist[-1][1], "held-out: trained", lt, "plain", lp)
+    assert np.isfinite(lt) and np.isfinite(lp)
+    assert lt < 0.85 * lp
 
 
 def test_nms_requires_one_float32_code():

@@ -128,6 +128,14 @@ typedef struct {
                                  within it; otherwise rounded down to whole tiles (at least one).
                                  Frames never
                                  depend on other frames, so results are bit-identical. */
+    int32_t resident_cap;     /* codes on their own streams (fuse_codes 2): workgroups per compute
+                                 unit that the layer launches of every code but the one with the
+                                 most layers per sweep may hold at once, so the launches of that
+                                 longest chain (which bounds the decode) find free slots.  Applied
+                                 as a request of (LDS per compute unit) / resident_cap bytes of
+                                 dynamic LDS that the kernels leave unused.  0: no cap; otherwise
+                                 3..64 (default 10, measured with 128-lane workgroups).  Results
+                                 are bit-identical. */
 } qm_tuning;
 
 int qm_abi_version(void);
@@ -202,7 +210,7 @@ int qm_decode(qm_decoder *dec, const float *llr, const uint8_t *syndrome, int32_
  *   max_iters  >= 0: sweeps for frames that never pass
  *   iters_used device int32 [sum_c F_c] out: sweeps each frame ran (or NULL)
  *   other arguments as qm_decode.
- * The host polls the device every 4 sweeps (pinned memory, one poll late) and
+ * The host polls the device every 2 sweeps (pinned memory, one poll late) and
  * stops enqueueing sweeps once no frame is left, so the call returns before
  * the decode has finished but may block on earlier sweeps; it is not
  * captured into a graph (QM_GRAPH does not apply).  With profiling on, the
@@ -217,8 +225,9 @@ int qm_decode_early(qm_decoder *dec, const float *llr, const uint8_t *syndrome, 
  * (each trial decoding min(iters, 8) sweeps), then, on the best, per-row
  * launches, the other mixed-batch mode (streams per code or fused launches),
  * graph replay, the other stream_hint, (if a code fits) the other
- * lds_resident, (one code) 2 and 4 tile groups and (fused launches) the
- * other spread_codes, each decoding min(iters, 256) sweeps: a graph or extra
+ * lds_resident, (one code) 2 and 4 tile groups, (fused launches) the
+ * other spread_codes and (streams per code) resident_cap 0, 8 and 12, each
+ * decoding min(iters, 256) sweeps: a graph or extra
  * streams over a few sweeps do not predict the whole decode.  The schedule
  * (row order) is never changed, so every trial decodes to the same bits.
  * Trials decode into the caller's output buffers (same shapes as

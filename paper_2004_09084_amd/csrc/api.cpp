@@ -173,6 +173,7 @@ struct qm_decoder {
            ogR = 0, oQ = 0, oCkA = 0, oCkR = 0, oPart = 0, nTotal = 0;
     std::vector<int32_t> acols;  // columns whose APP lives in A (degree != 1)
     int64_t lds_limit = 0;      // LDS bytes one workgroup may use (queried at bind)
+    int64_t lds_per_cu = 0;     // LDS bytes of one compute unit (queried at bind)
     // LDS-resident codes of a mixed decode run on a side stream, forked from
     // and joined back to the decode stream with events
     hipStream_t side = nullptr;
@@ -743,9 +744,14 @@ int enqueue_sweeps_streams(qm_decoder &d, int32_t iters, hipStream_t st) {
     std::vector<LayerArgs> base(nc);
     std::vector<int> G(nc);
     int64_t steps = 0;
+    // every chain but the longest (act[0]) holds at most resident_cap
+    // workgroups per compute unit, through an unused dynamic LDS request
+    const uint32_t cap_lds =
+        d.tun.resident_cap > 0 ? (uint32_t)std::min(d.lds_per_cu / d.tun.resident_cap, d.lds_limit) : 0u;
     for (int c = 0; c < nc; ++c) {
         if (c > 0) cs[c] = d.gstreams[c - 1];
         base[c] = layer_args(d, *act[c]);
+        base[c].shmem = c > 0 ? cap_lds : 0u;
         G[c] = (int)act[c]->gptr.size() - 1;
         steps = std::max<int64_t>(steps, (int64_t)iters * G[c]);
     }
@@ -1306,6 +1312,7 @@ int qm_decoder_create(const qm_code *const *codes, int32_t ncodes, const int32_t
     d->tun.tile_groups = 1;
     d->tun.spread_codes = 1;
     d->tun.frames_per_batch = 0;
+    d->tun.resident_cap = 10;
     layout(*d);
     *out = d;
     return QM_OK;
@@ -1351,6 +1358,8 @@ int qm_decoder_bind_workspace(qm_decoder *d, void *dev, size_t bytes) {
     QM_HIP(hipGetDevice(&device));
     QM_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
     d->lds_limit = lds;
+    QM_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device));
+    d->lds_per_cu = lds;
     d->bound = true;
     return QM_OK;
 }
@@ -1377,6 +1386,8 @@ int qm_decoder_set_tuning(qm_decoder *d, const qm_tuning *t) {
     n.lds_resident = n.lds_resident ? 1 : 0;
     n.spread_codes = n.spread_codes ? 1 : 0;
     if (n.frames_per_batch < 0) return fail(QM_ERR_INVALID_ARG, "frames_per_batch must be >= 0");
+    if (n.resident_cap != 0 && (n.resident_cap < 3 || n.resident_cap > 64))
+        return fail(QM_ERR_INVALID_ARG, "resident_cap must be 0 or in [3, 64]");
     if (n.tile_groups == 0) n.tile_groups = 1;
     if (n.tile_groups != 1 && n.tile_groups != 2 && n.tile_groups != 4 && n.tile_groups != 8)
         return fail(QM_ERR_INVALID_ARG, "tile_groups must be 1, 2, 4 or 8");
@@ -1696,9 +1707,10 @@ int qm_autotune(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t ite
             std::fprintf(log,
                          "{\"frames_per_tile\": %d, \"frames_per_lane\": %d, \"block\": %d, \"merge\": %d, "
                          "\"fuse_codes\": %d, \"graph\": %d, \"stream_hint\": %d, \"lds_resident\": %d, "
-                         "\"tile_groups\": %d, \"spread_codes\": %d, \"iters\": %d, \"ms\": %.4f}\n",
+                         "\"tile_groups\": %d, \"spread_codes\": %d, \"resident_cap\": %d, \"iters\": %d, "
+                         "\"ms\": %.4f}\n",
                          t.frames_per_tile, t.frames_per_lane, t.block, t.merge, t.fuse_codes, t.graph,
-                         t.stream_hint, t.lds_resident, t.tile_groups, t.spread_codes, n, *ms);
+                         t.stream_hint, t.lds_resident, t.tile_groups, t.spread_codes, t.resident_cap, n, *ms);
         return QM_OK;
     };
 
@@ -1735,8 +1747,15 @@ int qm_autotune(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t ite
     // extra streams over a few sweeps, do not predict the whole decode
     const int full = std::min<int>(iters, 256);
     if (rc == QM_OK) rc = trial(best, &best_ms, full);
-    for (int v = 0; v < 8 && rc == QM_OK; ++v) {
+    const int caps[3] = {0, 8, 12};
+    for (int v = 0; v < 11 && rc == QM_OK; ++v) {
         qm_tuning t = best;
+        if (v >= 8) {
+            // codes on their own streams: other residency caps of the
+            // shorter chains (the default is 10)
+            if (ncodes < 2 || t.fuse_codes != 2 || t.resident_cap == caps[v - 8]) continue;
+            t.resident_cap = caps[v - 8];
+        }
         if (v == 7) {
             if (ncodes < 2 || !t.fuse_codes) continue;
             t.spread_codes = !t.spread_codes;

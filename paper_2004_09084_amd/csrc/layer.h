@@ -318,19 +318,19 @@ __global__ void __launch_bounds__(256) k_layer_multi(const MultiLayerArgs m) {
 struct LayerSp {
     template <typename T, int D, int P, int H>
     static void go(dim3 g, dim3 b, hipStream_t s, const LayerArgs &a) {
-        hipLaunchKernelGGL((k_layer_sp<T, D, P, H>), g, b, 0, s, a);
+        hipLaunchKernelGGL((k_layer_sp<T, D, P, H>), g, b, a.shmem, s, a);
     }
 };
 struct LayerSpEt {
     template <typename T, int D, int P, int H>
     static void go(dim3 g, dim3 b, hipStream_t s, const LayerArgs &a) {
-        hipLaunchKernelGGL((k_layer_sp_et<T, D, P, H>), g, b, 0, s, a);
+        hipLaunchKernelGGL((k_layer_sp_et<T, D, P, H>), g, b, a.shmem, s, a);
     }
 };
 struct LayerFlood {
     template <typename T, int D, int P, int H>
     static void go(dim3 g, dim3 b, hipStream_t s, const LayerArgs &a) {
-        hipLaunchKernelGGL((k_layer_flood<T, D, P, H>), g, b, 0, s, a);
+        hipLaunchKernelGGL((k_layer_flood<T, D, P, H>), g, b, a.shmem, s, a);
     }
 };
 

@@ -65,6 +65,8 @@ struct LayerArgs {
                               // variable (bit = frame), max(FT, 8) bits each
     const uint8_t *PS;        // [ntiles][m] syndrome bits, packed the same way (K is formed from
                               // them and Ad; the K array is not read)
+    uint32_t shmem;           // dynamic LDS bytes requested per workgroup; the kernels do not use
+                              // it, it only caps how many workgroups a compute unit holds
 };
 
 // bytes of one packed field of FT = 2^ft_log2 frame bits

@@ -66,7 +66,7 @@ class qm_tuning(ctypes.Structure):
                 ("frames_per_lane", ctypes.c_int32), ("fuse_codes", ctypes.c_int32),
                 ("stream_hint", ctypes.c_int32), ("lds_resident", ctypes.c_int32),
                 ("tile_groups", ctypes.c_int32), ("spread_codes", ctypes.c_int32),
-                ("frames_per_batch", ctypes.c_int32)]
+                ("frames_per_batch", ctypes.c_int32), ("resident_cap", ctypes.c_int32)]
 
 
 class qm_profile(ctypes.Structure):
@@ -213,9 +213,9 @@ def qm_decoder_bind_workspace(dec, ws) -> None:
 
 def qm_decoder_set_tuning(dec, frames_per_tile=0, block=0, merge=1, graph=0, frames_per_lane=0, fuse_codes=2,
                           stream_hint=1, lds_resident=0, tile_groups=1, spread_codes=1,
-                          frames_per_batch=0) -> None:
+                          frames_per_batch=0, resident_cap=10) -> None:
     t = qm_tuning(frames_per_tile, block, merge, graph, frames_per_lane, fuse_codes, stream_hint, lds_resident,
-                  tile_groups, spread_codes, frames_per_batch)
+                  tile_groups, spread_codes, frames_per_batch, resident_cap)
     _check(lib().qm_decoder_set_tuning(dec, ctypes.byref(t)))
 
 

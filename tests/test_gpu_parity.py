@@ -235,25 +235,29 @@ def test_fused_mixed_batch_equals_unfused_and_single_code():
     Fs = [64, 32, 32]
     wls, codes, L, S = _mixed(specs, Fs)
     outs = {}
-    # fuse 1 / spread 1: layers spread over the launches; fuse 1 / spread 0:
-    # every code from the first launch on; fuse 2: each code on its own
-    # stream; fuse 0: codes one after another
-    for fuse, spread in ((1, 1), (1, 0), (2, 1), (0, 1)):
+    # fused launches with each code's layers spread over the launches, or
+    # every code from the first launch on; each code on its own stream, with
+    # the shorter chains' residency capped at the default 10, at 3 or not at
+    # all; codes one after another
+    modes = {"fused": dict(fuse_codes=1, spread_codes=1), "fused_unspread": dict(fuse_codes=1, spread_codes=0),
+             "streams": dict(fuse_codes=2), "streams_cap3": dict(fuse_codes=2, resident_cap=3),
+             "streams_nocap": dict(fuse_codes=2, resident_cap=0), "sequential": dict(fuse_codes=0)}
+    for name, tun in modes.items():
         for flags in (0, Q.QM_MSG_FP16):
-            dec = Q.Decoder(codes, Fs, flags=flags, tuning=dict(fuse_codes=fuse, spread_codes=spread))
+            dec = Q.Decoder(codes, Fs, flags=flags, tuning=tun)
             h, a, f = dec.decode(L, S, 9)
             torch.cuda.synchronize()
-            outs[(fuse, spread, flags)] = (h.cpu().numpy(), a.cpu().numpy(), f.cpu().numpy())
+            outs[(name, flags)] = (h.cpu().numpy(), a.cpu().numpy(), f.cpu().numpy())
     for flags in (0, Q.QM_MSG_FP16):
-        for other in ((1, 0, flags), (2, 1, flags), (0, 1, flags)):
-            for x, y in zip(outs[(1, 1, flags)], outs[other]):
-                assert np.array_equal(x, y), other
+        for name in modes:
+            for x, y in zip(outs[("fused", flags)], outs[(name, flags)]):
+                assert np.array_equal(x, y), (name, flags)
     # and against one decoder per code (FP32)
     on = of = 0
     for w, s, F in zip(wls, specs, Fs):
         h1, a1, f1 = gpu_decode(w.shifts, s.Z, w.llr, w.s, 9)
-        assert np.array_equal(outs[(1, 1, 0)][1][on:on + F * s.n], a1.reshape(-1))
-        assert np.array_equal(outs[(1, 1, 0)][2][of:of + F], f1)
+        assert np.array_equal(outs[("fused", 0)][1][on:on + F * s.n], a1.reshape(-1))
+        assert np.array_equal(outs[("fused", 0)][2][of:of + F], f1)
         on += F * s.n
         of += F
 

@@ -193,7 +193,9 @@ int qm_decoder_get_tuning(const qm_decoder *dec, qm_tuning *tuning);
  *   app      device float [sum_c F_c * n_c]  out: APP LLRs, or NULL
  *   flags    device uint8 [sum_c F_c]        out: 1 iff H c = s for the frame
  * Degree-1 variables are deferred (their single check makes q = LLR exact at
- * every layer); their APP is formed from the messages of the last sweep. */
+ * every layer); their APP is formed from the messages of the last sweep.
+ * Codes created with 0 frames take no part.  A decoder without any frame
+ * returns QM_OK at once (as does qm_decode_early); its buffers may be NULL. */
 int qm_decode(qm_decoder *dec, const float *llr, const uint8_t *syndrome, int32_t iters,
               uint8_t *hard, float *app, uint8_t *flags, void *stream);
 

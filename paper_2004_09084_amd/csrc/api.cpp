@@ -404,6 +404,12 @@ int enqueue_finalize(qm_decoder &d, uint8_t *hard, float *app, uint8_t *flags, h
 
 // Tile groups (tuning tile_groups) usable over nt frame tiles: the largest
 // count not above the tuning value that divides nt.
+int64_t total_frames(const qm_decoder &d) {
+    int64_t F = 0;
+    for (const Slot &s : d.slots) F += s.F;
+    return F;
+}
+
 int tile_groups(const qm_decoder &d, int nt) {
     int g = std::max(1, std::min<int>(d.tun.tile_groups, nt));
     while (g > 1 && nt % g) --g;
@@ -1406,8 +1412,9 @@ int qm_decode(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t iters
               uint8_t *flags, void *stream) {
     if (!d) return fail(QM_ERR_INVALID_ARG, "decoder is NULL");
     if (!d->bound) return fail(QM_ERR_NO_WORKSPACE, "no workspace bound");
-    if (!llr || !syn || !hard || !flags) return fail(QM_ERR_INVALID_ARG, "NULL buffer");
     if (iters < 0) return fail(QM_ERR_INVALID_ARG, "iters must be >= 0");
+    if (total_frames(*d) == 0) return QM_OK;  // nothing to decode; the buffers may be NULL
+    if (!llr || !syn || !hard || !flags) return fail(QM_ERR_INVALID_ARG, "NULL buffer");
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (d->flags & QM_VALIDATE) {
         const int rc = validate_inputs(*d, llr, syn, st);
@@ -1453,8 +1460,9 @@ int qm_decode_early(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t
     if (!d) return fail(QM_ERR_INVALID_ARG, "decoder is NULL");
     if (!(d->flags & QM_EARLY_STOP)) return fail(QM_ERR_UNSUPPORTED, "decoder was not created with QM_EARLY_STOP");
     if (!d->bound) return fail(QM_ERR_NO_WORKSPACE, "no workspace bound");
-    if (!llr || !syn || !hard || !flags) return fail(QM_ERR_INVALID_ARG, "NULL buffer");
     if (max_iters < 0) return fail(QM_ERR_INVALID_ARG, "max_iters must be >= 0");
+    if (total_frames(*d) == 0) return QM_OK;  // nothing to decode; the buffers may be NULL
+    if (!llr || !syn || !hard || !flags) return fail(QM_ERR_INVALID_ARG, "NULL buffer");
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (d->flags & QM_VALIDATE) {
         const int rc = validate_inputs(*d, llr, syn, st);

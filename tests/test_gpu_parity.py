@@ -262,6 +262,50 @@ def test_fused_mixed_batch_equals_unfused_and_single_code():
         of += F
 
 
+def test_codes_without_frames():
+    # a code given 0 frames takes no part (every mixed-batch mode, early
+    # termination); a decoder with no frame at all decodes nothing, with
+    # empty buffers
+    import torch
+    specs = [SMALL, W.RATE005.with_Z(16), W.RATE002.with_Z(16)]
+    Fs = [5, 0, 3]
+    wls = [_wl(s, max(F, 1), snr=0.4, seed=13 + i) for i, (s, F) in enumerate(zip(specs, Fs))]
+    codes = [Q.Code(w.shifts, s.Z) for w, s in zip(wls, specs)]
+    L = to_dev(np.concatenate([w.llr[:F].reshape(-1) for w, F in zip(wls, Fs)]))
+    S = to_dev(np.concatenate([w.s[:F].reshape(-1) for w, F in zip(wls, Fs)]))
+    ref = [gpu_decode(w.shifts, s.Z, w.llr[:F], w.s[:F], 7) if F else None for w, s, F in zip(wls, specs, Fs)]
+    for tun in (dict(fuse_codes=0), dict(fuse_codes=1), dict(fuse_codes=2)):
+        dec = Q.Decoder(codes, Fs, tuning=tun)
+        h, a, f = dec.decode(L, S, 7)
+        torch.cuda.synchronize()
+        h, a, f = h.cpu().numpy(), a.cpu().numpy(), f.cpu().numpy()
+        on = of = 0
+        for r, s, F in zip(ref, specs, Fs):
+            if not F:
+                continue
+            assert np.array_equal(a[on:on + F * s.n], r[1].reshape(-1)), tun
+            assert np.array_equal(h[on:on + F * s.n], r[0].reshape(-1)), tun
+            assert np.array_equal(f[of:of + F], r[2]), tun
+            on += F * s.n
+            of += F
+    dec = Q.Decoder(codes, Fs, flags=Q.QM_EARLY_STOP)
+    h, a, f, it = dec.decode_early(L, S, 7)
+    torch.cuda.synchronize()
+    assert h.numel() == sum(F * s.n for s, F in zip(specs, Fs)) and it.numel() == sum(Fs)
+    it = it.cpu().numpy()
+    assert ((it >= 0) & (it <= 7)).all()
+    for flags in (0, Q.QM_EARLY_STOP):
+        empty = Q.Decoder([codes[0]], [0], flags=flags)
+        e = torch.empty(0, device="cuda")
+        e8 = torch.empty(0, dtype=torch.uint8, device="cuda")
+        if flags:
+            out = empty.decode_early(e, e8, 5)
+        else:
+            out = empty.decode(e, e8, 5)
+        torch.cuda.synchronize()
+        assert all(x is None or x.numel() == 0 for x in out)
+
+
 def test_code_streams_graph_replays_match_eager():
     # each code on its own stream (fuse_codes = 2) inside a captured graph,
     # replayed with eager work between the replays

@@ -65,14 +65,19 @@ def load_traffic(workload_key: str, msg: str):
     return ent.get("bytes_per_launch")
 
 
-def cpu_baseline(spec, shifts, frames_llr, frames_s, iters_full):
+def cpu_baseline(spec, shifts, frames_llr, frames_s, iters_full, target_s=10.0):
     """The FP64 oracle, as it stands, on a bounded sample: `threads` frames
-    (one per host core, at most 16) for 2 iterations; scaled to Mbit/s at the
-    full iteration count (with early termination: the GPU's mean count)."""
+    (one per host core, at most 16), timed over as many iterations as take
+    about `target_s` seconds (2 to 64, from a 2-iteration probe); scaled to
+    Mbit/s at the full iteration count (with early termination: the GPU's
+    mean count)."""
     import oracle
     threads = min(16, os.cpu_count() or 1)
     F = min(threads, frames_llr.shape[0])
-    sample_iters = 2
+    t0 = time.perf_counter()
+    oracle.decode_sp(shifts, spec.Z, frames_llr[:F], frames_s[:F], 2, threads=threads)
+    probe = time.perf_counter() - t0
+    sample_iters = int(max(2, min(64, round(target_s / max(probe / 2, 1e-3)))))
     t0 = time.perf_counter()
     _, _, _, used = oracle.decode_sp(shifts, spec.Z, frames_llr[:F], frames_s[:F], sample_iters, threads=threads)
     dt = time.perf_counter() - t0

@@ -104,8 +104,10 @@ typedef struct {
                                  LDS (at most 8 such entries per row) is decoded by one workgroup
                                  per frame that keeps those APPs in LDS through every sweep, with
                                  workgroup barriers between layers (one launch per decode; such a
-                                 code uses one frame per tile).  Bit-identical to the layer
-                                 kernels. */
+                                 code uses one frame per tile).  2 (default): the same, only for a
+                                 code with at least as many frames as the device has compute
+                                 units (with fewer, compute units stay idle and the layer kernels
+                                 are faster).  0: never.  Bit-identical to the layer kernels. */
     int32_t tile_groups;      /* 1, 2, 4 or 8 (0 = 1): a layered decode of one code splits its frame
                                  tiles into this many groups (fewer if it does not divide the
                                  tile count), each running its own layer sequence on its own
@@ -226,8 +228,8 @@ int qm_decode_early(qm_decoder *dec, const float *llr, const uint8_t *syndrome, 
  * frames per tile {16, 32, 64} x frames per lane {1, 2} x block {128, 256}
  * (each trial decoding min(iters, 8) sweeps), then, on the best, per-row
  * launches, the other mixed-batch mode (streams per code or fused launches),
- * graph replay, the other stream_hint, (if a code fits) the other
- * lds_resident, (one code) 2 and 4 tile groups, (fused launches) the
+ * graph replay, the other stream_hint, (if a code fits) lds_resident 1
+ * and 0, (one code) 2 and 4 tile groups, (fused launches) the
  * other spread_codes and (streams per code) resident_cap 0, 8 and 12, each
  * decoding min(iters, 256) sweeps: a graph or extra
  * streams over a few sweeps do not predict the whole decode.  The schedule

@@ -174,6 +174,7 @@ struct qm_decoder {
     std::vector<int32_t> acols;  // columns whose APP lives in A (degree != 1)
     int64_t lds_limit = 0;      // LDS bytes one workgroup may use (queried at bind)
     int64_t lds_per_cu = 0;     // LDS bytes of one compute unit (queried at bind)
+    int32_t ncu = 0;            // compute units of the device (queried at bind)
     // LDS-resident codes of a mixed decode run on a side stream, forked from
     // and joined back to the decode stream with events
     hipStream_t side = nullptr;
@@ -201,9 +202,13 @@ size_t msg_bytes(const qm_decoder &d) {
     return k == QM_MSGK_F16 ? 2 : k == QM_MSGK_F8 ? 1 : 4;
 }
 
-// decoded by the LDS-resident kernel (one frame per tile)?
+// decoded by the LDS-resident kernel (one frame per tile)?  Tuning
+// lds_resident 1: whenever the code fits; 2: when it fits and has at least
+// one frame per compute unit (with fewer, its one workgroup per frame leaves
+// compute units idle and the layer kernels are faster)
 bool lds_slot(const qm_decoder &d, const Slot &s) {
-    return d.tun.lds_resident && !(d.flags & QM_FLOODING) && s.F > 0 && s.code->max_d <= 8 && d.lds_limit > 0 &&
+    const bool want = d.tun.lds_resident == 1 || (d.tun.lds_resident == 2 && d.ncu > 0 && s.F >= d.ncu);
+    return want && !(d.flags & QM_FLOODING) && s.F > 0 && s.code->max_d <= 8 && d.lds_limit > 0 &&
            (int64_t)qm_lds_bytes((int)s.cols1.size(), s.code->Z) <= d.lds_limit;
 }
 
@@ -1317,6 +1322,7 @@ int qm_decoder_create(const qm_code *const *codes, int32_t ncodes, const int32_t
     d->tun.stream_hint = 1;
     d->tun.tile_groups = 1;
     d->tun.spread_codes = 1;
+    d->tun.lds_resident = 2;
     d->tun.frames_per_batch = 0;
     d->tun.resident_cap = 10;
     layout(*d);
@@ -1366,6 +1372,8 @@ int qm_decoder_bind_workspace(qm_decoder *d, void *dev, size_t bytes) {
     d->lds_limit = lds;
     QM_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device));
     d->lds_per_cu = lds;
+    QM_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMultiprocessorCount, device));
+    d->ncu = lds;
     d->bound = true;
     return QM_OK;
 }
@@ -1389,7 +1397,7 @@ int qm_decoder_set_tuning(qm_decoder *d, const qm_tuning *t) {
     n.graph = n.graph ? 1 : 0;
     if (n.fuse_codes < 0 || n.fuse_codes > 2) return fail(QM_ERR_INVALID_ARG, "fuse_codes must be 0, 1 or 2");
     n.stream_hint = n.stream_hint ? 1 : 0;
-    n.lds_resident = n.lds_resident ? 1 : 0;
+    if (n.lds_resident < 0 || n.lds_resident > 2) return fail(QM_ERR_INVALID_ARG, "lds_resident must be 0, 1 or 2");
     n.spread_codes = n.spread_codes ? 1 : 0;
     if (n.frames_per_batch < 0) return fail(QM_ERR_INVALID_ARG, "frames_per_batch must be >= 0");
     if (n.resident_cap != 0 && (n.resident_cap < 3 || n.resident_cap > 64))
@@ -1756,7 +1764,7 @@ int qm_autotune(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t ite
     const int full = std::min<int>(iters, 256);
     if (rc == QM_OK) rc = trial(best, &best_ms, full);
     const int caps[3] = {0, 8, 12};
-    for (int v = 0; v < 11 && rc == QM_OK; ++v) {
+    for (int v = 0; v < 12 && rc == QM_OK; ++v) {
         qm_tuning t = best;
         if (v >= 8) {
             // codes on their own streams: other residency caps of the
@@ -1773,8 +1781,12 @@ int qm_autotune(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t ite
             t.tile_groups = v == 5 ? 2 : 4;
         }
         if (v == 4) {
-            if (!lds_candidate) continue;
-            t.lds_resident = !t.lds_resident;
+            if (!lds_candidate || t.lds_resident == 1) continue;
+            t.lds_resident = 1;
+        }
+        if (v == 11) {
+            if (!lds_candidate || t.lds_resident == 0) continue;
+            t.lds_resident = 0;
         }
         if (v == 3) t.stream_hint = !t.stream_hint;
         if (v == 0) t.merge = 0;

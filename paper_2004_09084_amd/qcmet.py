@@ -212,7 +212,7 @@ def qm_decoder_bind_workspace(dec, ws) -> None:
 
 
 def qm_decoder_set_tuning(dec, frames_per_tile=0, block=0, merge=1, graph=0, frames_per_lane=0, fuse_codes=2,
-                          stream_hint=1, lds_resident=0, tile_groups=1, spread_codes=1,
+                          stream_hint=1, lds_resident=2, tile_groups=1, spread_codes=1,
                           frames_per_batch=0, resident_cap=10) -> None:
     t = qm_tuning(frames_per_tile, block, merge, graph, frames_per_lane, fuse_codes, stream_hint, lds_resident,
                   tile_groups, spread_codes, frames_per_batch, resident_cap)

@@ -110,13 +110,14 @@ def test_tuning_validation():
     H = W.make_code(W.RATE01_SMALL, 0)
     c = Q.Code(H, 64)
     d = Q.qm_decoder_create([c.handle], [8], 0)
-    assert Q.qm_decoder_get_tuning(d)["resident_cap"] == 10   # the library's default
+    t0 = Q.qm_decoder_get_tuning(d)
+    assert t0["resident_cap"] == 10 and t0["lds_resident"] == 2   # the library's defaults
     Q.qm_decoder_set_tuning(d, frames_per_tile=8, block=128, merge=0)
     t = Q.qm_decoder_get_tuning(d)
     assert t["frames_per_tile"] == 8 and t["block"] == 128 and t["merge"] == 0
     for bad in (dict(frames_per_tile=3), dict(frames_per_tile=128), dict(block=100), dict(block=512),
                 dict(frames_per_lane=3), dict(resident_cap=1), dict(resident_cap=2), dict(resident_cap=65),
-                dict(resident_cap=-1), dict(frames_per_batch=-1)):
+                dict(resident_cap=-1), dict(frames_per_batch=-1), dict(lds_resident=3), dict(lds_resident=-1)):
         with pytest.raises(Q.QMError) as e:
             Q.qm_decoder_set_tuning(d, **bad)
         assert e.value.code == Q.QM_ERR_INVALID_ARG

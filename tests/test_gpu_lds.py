@@ -62,6 +62,28 @@ def test_lds_resident_fullsize_rate002():
     _assert_same(outs[0], outs[1], "full size")
 
 
+def test_lds_resident_auto_takes_codes_with_a_frame_per_compute_unit():
+    # lds_resident 2 (the default) runs the LDS-resident kernel only for a
+    # code with at least as many frames as the device has compute units;
+    # either way the outputs equal the layer kernels'
+    import torch
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    spec = W.RATE002.with_Z(16)
+    for F, want in ((ncu - 1, 0), (ncu + 3, 1)):
+        wl = W.build(spec, F, snr=0.3, frame_seed=21)
+        code = Q.Code(wl.shifts, spec.Z)
+        outs = []
+        for lds in (0, 2):
+            dec = Q.Decoder([code], [F], tuning=dict(lds_resident=lds))
+            dec.set_profiling(True)
+            h, a, f = dec.decode(to_dev(wl.llr), to_dev(wl.s), 5)
+            torch.cuda.synchronize()
+            p = dec.profile()
+            assert p["lds_launches"] == (want if lds == 2 else 0), (F, lds, p)
+            outs.append((h.cpu().numpy(), a.cpu().numpy(), f.cpu().numpy()))
+        _assert_same(outs[0], outs[1], f"auto, {F} frames")
+
+
 def test_lds_resident_falls_back_when_too_big():
     # rate 0.1 at Z = 20000: 5 x 20000 x 4 B = 400 KB does not fit
     import torch

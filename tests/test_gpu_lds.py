@@ -82,6 +82,14 @@ def test_lds_resident_auto_takes_codes_with_a_frame_per_compute_unit():
             assert p["lds_launches"] == (want if lds == 2 else 0), (F, lds, p)
             outs.append((h.cpu().numpy(), a.cpu().numpy(), f.cpu().numpy()))
         _assert_same(outs[0], outs[1], f"auto, {F} frames")
+    # an early-terminating decoder keeps the layer kernels (and its frame
+    # tiles) whatever lds_resident says
+    dec = Q.Decoder([code], [F], flags=Q.QM_EARLY_STOP, tuning=dict(lds_resident=1))
+    dec.set_profiling(True)
+    dec.decode(to_dev(wl.llr), to_dev(wl.s), 5)
+    dec.decode_early(to_dev(wl.llr), to_dev(wl.s), 5)
+    torch.cuda.synchronize()
+    assert dec.profile()["lds_launches"] == 0
 
 
 def test_lds_resident_falls_back_when_too_big():

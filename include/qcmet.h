@@ -108,8 +108,8 @@ typedef struct {
                                  code with at least as many frames as the device has compute
                                  units (with fewer, compute units stay idle and the layer kernels
                                  are faster).  0: never.  Decoders created with QM_FLOODING or
-                                 QM_EARLY_STOP always use the layer kernels.  Bit-identical to the
-                                 layer kernels. */
+                                 QM_EARLY_STOP, or with a min-sum workspace bound, always use the
+                                 layer kernels.  Bit-identical to the layer kernels. */
     int32_t tile_groups;      /* 1, 2, 4 or 8 (0 = 1): a layered decode of one code splits its frame
                                  tiles into this many groups (fewer if it does not divide the
                                  tile count), each running its own layer sequence on its own

@@ -206,10 +206,11 @@ size_t msg_bytes(const qm_decoder &d) {
 // lds_resident 1: whenever the code fits; 2: when it fits and has at least
 // one frame per compute unit (with fewer, its one workgroup per frame leaves
 // compute units idle and the layer kernels are faster).  Flooding and
-// early-terminating decoders always use the layer kernels.
+// early-terminating decoders, and decoders with a min-sum workspace bound
+// (whose kernels take the same frame tiles), always use the layer kernels.
 bool lds_slot(const qm_decoder &d, const Slot &s) {
     const bool want = d.tun.lds_resident == 1 || (d.tun.lds_resident == 2 && d.ncu > 0 && s.F >= d.ncu);
-    return want && !(d.flags & (QM_FLOODING | QM_EARLY_STOP)) && s.F > 0 && s.code->max_d <= 8 && d.lds_limit > 0 &&
+    return want && !(d.flags & (QM_FLOODING | QM_EARLY_STOP)) && !d.nws && s.F > 0 && s.code->max_d <= 8 && d.lds_limit > 0 &&
            (int64_t)qm_lds_bytes((int)s.cols1.size(), s.code->Z) <= d.lds_limit;
 }
 

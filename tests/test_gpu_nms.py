@@ -166,6 +166,26 @@ def test_adam_step_matches_numpy():
     assert np.allclose(md.cpu().numpy(), m2, rtol=1e-5, atol=1e-7)
 
 
+def test_minsum_keeps_frame_tiles_whatever_lds_resident():
+    # the LDS-resident engine is sum-product only: a decoder bound for
+    # min-sum decodes the same with lds_resident 1 as with 0, also for a
+    # code that engine could take (a frame per compute unit, APPs fit in LDS)
+    import torch
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    spec = W.RATE002.with_Z(16)
+    F, T = ncu + 3, 4
+    wl = W.build(spec, F, snr=0.4, frame_seed=22)
+    w = torch.from_numpy(_weights(T, spec.mb, seed=1)[0]).cuda()
+    outs = []
+    for lds in (0, 1):
+        _, dec = _dec(wl.shifts, spec.Z, F, T, tuning=dict(lds_resident=lds))
+        h, a, f, it = dec.nms_decode(w, to_dev(wl.llr), to_dev(wl.s), T, early_stop=True)
+        torch.cuda.synchronize()
+        outs.append([x.cpu().numpy() for x in (h, a, f, it)])
+    for x, y in zip(*outs):
+        assert np.array_equal(x, y)
+
+
 def test_training_lowers_the_loss_on_unseen_frames():
     # what the learned weights gain over plain min-sum, on the objective they
     # are trained for: a short run (frames drawn on the GPU, exact gradients

@@ -118,7 +118,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build decodes on a single MI355X "
+        print("bench.py measures one GPU only: the library decodes on a single MI355X "
               "(frames would shard across GPUs with no exchange; not built). Use --gpus 1.",
               file=sys.stderr)
         sys.exit(2)

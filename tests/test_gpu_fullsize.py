@@ -82,3 +82,29 @@ def test_fullsize_against_stored_oracle(case):
         # T2: frames the oracle decodes to a valid word are bit-identical
         if flag_o:
             assert same_hash and viol == 0
+
+
+def test_default_frame_batches_at_1024_frames():
+    # 1024 frames of the rate-0.1 code hold about 19 GiB of decoder state,
+    # more than the 12 GiB the default puts in one batch, so the default
+    # decodes them as two batches of 512 frames; every output equals the
+    # decode with all frames in every launch
+    import torch
+    spec = W.RATE01
+    F, T = 1024, 2
+    code = Q.Code(W.make_code(spec, 0), spec.Z)
+    dec = Q.Decoder([code], [F])
+    x = torch.empty(F * spec.n, dtype=torch.uint8, device="cuda")
+    llr = torch.empty(F * spec.n, dtype=torch.float32, device="cuda")
+    syn = torch.empty(F * spec.m, dtype=torch.uint8, device="cuda")
+    Q.qm_generate_frames(dec.handle, 0, 5, 0, 0.3, F, x, llr, syn)
+    say("1024 frames: decoding in default batches")
+    h1, a1, f1 = dec.decode(llr, syn, T)
+    torch.cuda.synchronize()
+    dec.set_tuning(frames_per_batch=F)
+    say("1024 frames: decoding in one batch")
+    h2, a2, f2 = dec.decode(llr, syn, T)
+    torch.cuda.synchronize()
+    assert torch.equal(h1, h2) and torch.equal(a1, a2) and torch.equal(f1, f2)
+    # the decode did something: hard decisions differ from the channel's somewhere
+    assert not torch.equal(h1, (llr < 0).to(torch.uint8))

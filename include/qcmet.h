@@ -203,6 +203,28 @@ int qm_decoder_get_tuning(const qm_decoder *dec, qm_tuning *tuning);
 int qm_decode(qm_decoder *dec, const float *llr, const uint8_t *syndrome, int32_t iters,
               uint8_t *hard, float *app, uint8_t *flags, void *stream);
 
+/* Allocation-free variant of qm_decode, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  It decodes exactly as qm_decode (same
+ * kernels, bit-identical outputs) but takes as the decoder's workspace a
+ * static array of QM_NOALLOC_SCRATCH_BYTES that the library holds on every
+ * device it runs on until the process ends; no workspace need be bound, and
+ * a bound one is neither used nor changed.  The call allocates nothing: it
+ * copies the decoder's descriptors (a few KB) into the array on `stream` and
+ * launches on `stream` alone (no graph, tile groups, side streams or
+ * profiling for this call; each gives bit-identical outputs).
+ *   Limits: qm_decoder_workspace_bytes(dec) <= QM_NOALLOC_SCRATCH_BYTES, else
+ *   QM_ERR_NO_WORKSPACE (for example 3 frames of a 10^6-bit rate-0.1 code,
+ *   or thousands of frames of a 3200-bit code); decoders created with
+ *   QM_EARLY_STOP or QM_FLOODING give QM_ERR_UNSUPPORTED.
+ *   Every call on one device shares that device's array and overwrites it
+ *   (each call initialises what it reads), so calls that overlap on one
+ *   device, on any streams, race: the caller must order them.
+ * Arguments as qm_decode. */
+#define QM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int qm_decode_noalloc(qm_decoder *dec, const float *llr, const uint8_t *syndrome, int32_t iters,
+                      uint8_t *hard, float *app, uint8_t *flags, void *stream);
+
 /* Layered sum-product decode with early termination (Results, Table
  * tabearly): before the first sweep and after every sweep each frame's hard
  * decisions are tested against its syndrome, and a frame that passes stops

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqcmet.so")
 SOURCES = ["kernels.hip", "layer_f32.hip", "layer_f16.hip", "layer_f8.hip", "lds_sweeps.hip", "nms.hip", "framegen.hip",
-           "api.cpp"]
+           "noalloc.hip", "api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -1465,6 +1465,89 @@ int qm_decode(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t iters
     return QM_OK;
 }
 
+}  // extern "C"
+
+int qm_set_error(int code, const char *msg) { return fail(code, msg); }
+
+// One fixed-sweep decode with `ws` as the decoder's workspace for this call
+// only (the allocation-free entry point passes its static scratch array).
+// Nothing here allocates: the row, group and column descriptors are copied
+// into `ws` on the stream, every kernel argument is a plain pointer into it,
+// and the call takes the single-stream launch sequence (no graph, no side or
+// group streams, no profiling events).  The tuning switches that would need
+// those resources are overridden for the call; each alternative they select
+// gives bit-identical outputs.  The decoder's own workspace binding, tuning
+// and cached graph are left as they were.
+int qm_decode_on_workspace(qm_decoder *d, char *ws, size_t ws_bytes, const float *llr, const uint8_t *syn,
+                           int32_t iters, uint8_t *hard, float *app, uint8_t *flags, hipStream_t st) {
+    if (!d) return fail(QM_ERR_INVALID_ARG, "decoder is NULL");
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0)
+        return fail(QM_ERR_INVALID_ARG, "scratch missing or not 256-byte aligned");
+    if (iters < 0) return fail(QM_ERR_INVALID_ARG, "iters must be >= 0");
+    if (d->flags & (QM_EARLY_STOP | QM_FLOODING))
+        return fail(QM_ERR_UNSUPPORTED, "the allocation-free decode takes fixed-sweep layered decoders only");
+    if (d->total > ws_bytes)
+        return fail(QM_ERR_NO_WORKSPACE, "the decoder needs " + std::to_string(d->total) +
+                                             " workspace bytes; the static scratch holds " + std::to_string(ws_bytes));
+    if (total_frames(*d) == 0) return QM_OK;
+    if (!llr || !syn || !hard || !flags) return fail(QM_ERR_INVALID_ARG, "NULL buffer");
+    int device = 0, v = 0;
+    QM_HIP(hipGetDevice(&device));
+    // the decoder's state that this call swaps out, restored on every return
+    struct Saved {
+        qm_decoder *d;
+        char *ws;
+        size_t ws_bytes;
+        bool bound;
+        qm_tuning tun;
+        int32_t profiling;
+        int64_t lds_limit, lds_per_cu;
+        int32_t ncu;
+        ~Saved() {
+            d->ws = ws;
+            d->ws_bytes = ws_bytes;
+            d->bound = bound;
+            d->tun = tun;
+            d->profiling = profiling;
+            d->lds_limit = lds_limit;
+            d->lds_per_cu = lds_per_cu;
+            d->ncu = ncu;
+        }
+    } saved{d, d->ws, d->ws_bytes, d->bound, d->tun, d->profiling, d->lds_limit, d->lds_per_cu, d->ncu};
+    d->ws = ws;
+    d->ws_bytes = ws_bytes;
+    d->bound = true;
+    d->profiling = 0;
+    d->tun.graph = 0;
+    d->tun.tile_groups = 1;
+    d->tun.lds_resident = 0;
+    if (d->tun.fuse_codes == 2) d->tun.fuse_codes = 1;
+    QM_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
+    d->lds_limit = v;
+    QM_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device));
+    d->lds_per_cu = v;
+    QM_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device));
+    d->ncu = v;
+    // the scratch keeps whatever the previous call on this device left there
+    for (const Slot &s : d->slots) {
+        QM_HIP(hipMemcpyAsync(ws + s.oRows, s.hrows.data(), s.hrows.size() * sizeof(RowDesc), hipMemcpyHostToDevice,
+                              st));
+        QM_HIP(hipMemcpyAsync(ws + s.oGptr, s.gptr.data(), s.gptr.size() * 4, hipMemcpyHostToDevice, st));
+        if (!s.cols1.empty())
+            QM_HIP(hipMemcpyAsync(ws + s.oCols1, s.cols1.data(), s.cols1.size() * 4, hipMemcpyHostToDevice, st));
+        if (!s.hcols.empty())
+            QM_HIP(hipMemcpyAsync(ws + s.oColD, s.hcols.data(), s.hcols.size() * sizeof(ColDesc),
+                                  hipMemcpyHostToDevice, st));
+    }
+    if (d->flags & QM_VALIDATE) {
+        const int rc = validate_inputs(*d, llr, syn, st);
+        if (rc != QM_OK) return rc;
+    }
+    return enqueue_decode(*d, llr, syn, iters, hard, app, flags, st);
+}
+
+extern "C" {
+
 int qm_decode_early(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t max_iters, uint8_t *hard,
                     float *app, uint8_t *flags, int32_t *iters_used, void *stream) {
     if (!d) return fail(QM_ERR_INVALID_ARG, "decoder is NULL");

@@ -253,3 +253,10 @@ hipError_t qm_launch_framegen(uint8_t *x, float *llr, uint8_t *syn, const RowDes
 
 hipError_t qm_launch_validate(const float *llr, size_t nl, const uint8_t *syn, size_t ns,
                               uint32_t *err, hipStream_t s);
+
+// Host runtime entry points shared with the allocation-free decode
+// (noalloc.hip).
+struct qm_decoder;
+int qm_set_error(int code, const char *msg);
+int qm_decode_on_workspace(qm_decoder *d, char *ws, size_t ws_bytes, const float *llr, const uint8_t *syn,
+                           int32_t iters, uint8_t *hard, float *app, uint8_t *flags, hipStream_t st);

@@ -42,8 +42,10 @@ EXPORTED = [
     "qm_decoder_workspace_bytes", "qm_decoder_bind_workspace", "qm_decoder_set_tuning",
     "qm_decoder_get_tuning", "qm_decode", "qm_decode_early", "qm_autotune", "qm_decoder_set_profiling",
     "qm_decoder_get_profile", "qm_nms_workspace_bytes", "qm_nms_bind_workspace", "qm_nms_decode",
-    "qm_nms_loss_grad", "qm_adam_step", "qm_generate_frames",
+    "qm_nms_loss_grad", "qm_adam_step", "qm_generate_frames", "qm_decode_noalloc",
 ]
+
+QM_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class QMError(RuntimeError):
@@ -104,6 +106,7 @@ def lib():
         L.qm_decoder_get_tuning.argtypes = [p, ctypes.POINTER(qm_tuning)]
         L.qm_decode.argtypes = [p, p, p, i32, p, p, p, p]
         L.qm_decode_early.argtypes = [p, p, p, i32, p, p, p, p, p]
+        L.qm_decode_noalloc.argtypes = [p, p, p, i32, p, p, p, p]
         L.qm_autotune.argtypes = [p, p, p, i32, p, p, p, ctypes.c_char_p, p]
         L.qm_decoder_set_profiling.argtypes = [p, i32]
         L.qm_decoder_get_profile.argtypes = [p, ctypes.POINTER(qm_profile), i32]
@@ -228,6 +231,11 @@ def qm_decoder_get_tuning(dec) -> dict:
 def qm_decode(dec, llr, syndrome, iters: int, hard, app, flags, stream=None) -> None:
     _check(lib().qm_decode(dec, _dptr(llr), _dptr(syndrome), int(iters), _dptr(hard), _dptr(app),
                            _dptr(flags), _stream_handle(stream)))
+
+
+def qm_decode_noalloc(dec, llr, syndrome, iters: int, hard, app, flags, stream=None) -> None:
+    _check(lib().qm_decode_noalloc(dec, _dptr(llr), _dptr(syndrome), int(iters), _dptr(hard), _dptr(app),
+                                   _dptr(flags), _stream_handle(stream)))
 
 
 def qm_decode_early(dec, llr, syndrome, max_iters: int, hard, app, flags, iters_used=None, stream=None) -> None:

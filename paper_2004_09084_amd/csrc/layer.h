@@ -353,7 +353,7 @@ void layer_maxd(dim3 g, dim3 b, hipStream_t s, const LayerArgs &a, int maxd, int
         case 5: { QM_LP(5) }
         case 6: { QM_LP(6) }
         case 8: { QM_LP(8) }
-        default: { layer_go<K, T, 16, 1>(g, b, s, a, hint); break; }
+        default: { QM_LP(16) }
     }
 #undef QM_LP
 }
@@ -396,7 +396,7 @@ hipError_t layer_multi_msg(const MultiLayerArgs &m, int maxd, int fpl, int block
         case 5: { QM_LP(5) }
         case 6: { QM_LP(6) }
         case 8: { QM_LP(8) }
-        default: { QM_L(16, 1); break; }
+        default: { QM_LP(16) }
     }
 #undef QM_LP
 #undef QM_L

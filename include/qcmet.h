@@ -250,10 +250,11 @@ int qm_decode_early(qm_decoder *dec, const float *llr, const uint8_t *syndrome, 
 
 /* Times result-preserving tunings on the given inputs and keeps the fastest:
  * frames per tile {16, 32, 64} x frames per lane {1, 2} x block {128, 256}
- * (each trial decoding min(iters, 8) sweeps), then, on the best, per-row
+ * on the layer kernels (lds_resident 0; each trial decoding min(iters, 8)
+ * sweeps), then, on the best, per-row
  * launches, the other mixed-batch mode (streams per code or fused launches),
- * graph replay, the other stream_hint, (if a code fits) lds_resident 1
- * and 0, (one code) 2 and 4 tile groups, (fused launches) the
+ * graph replay, the other stream_hint, (if a code fits) lds_resident 1,
+ * (one code) 2 and 4 tile groups, (fused launches) the
  * other spread_codes and (streams per code) resident_cap 0, 8 and 12, each
  * decoding min(iters, 256) sweeps: a graph or extra
  * streams over a few sweeps do not predict the whole decode.  The schedule
@@ -308,7 +309,7 @@ int qm_decoder_get_profile(qm_decoder *dec, qm_profile *out, int32_t reset);
  * reaches APP_d = LLR_d + r_d.  The decoder must hold exactly one code with
  * float32 messages (QM_ERR_UNSUPPORTED otherwise).
  * Workspace: a second device buffer, sized for at most T sweeps; train = 1
- * adds the per-sweep checkpoints (T x (APP + messages)) and adjoints. */
+ * adds the per-sweep records of q (T x messages) and the adjoints. */
 size_t qm_nms_workspace_bytes(const qm_decoder *dec, int32_t T, int32_t train);
 int qm_nms_bind_workspace(qm_decoder *dec, void *device_ptr, size_t bytes, int32_t T, int32_t train);
 
@@ -320,18 +321,36 @@ int qm_nms_bind_workspace(qm_decoder *dec, void *device_ptr, size_t bytes, int32
 int qm_nms_decode(qm_decoder *dec, const float *weights, const float *llr, const uint8_t *syndrome, int32_t T,
                   int32_t early_stop, uint8_t *hard, float *app, uint8_t *flags, int32_t *iters_used, void *stream);
 
-/* Training step core: T fixed min-sum sweeps from the channel LLRs, the mean
- * binary cross-entropy of the final APPs against the true bits x,
- *   loss = mean over frames and all n bits of softplus(-(1 - 2x) APP)
- * (P(bit = 1) = sigmoid(-APP)), and its exact gradient with respect to the
- * weights by a reverse sweep that restores each sweep's starting state from
- * its checkpoint and recomputes it.  Gradient sums over workgroups are
- * reduced in a fixed order (run-to-run identical).  Over many sweeps the
- * reverse-sweep adjoints can grow geometrically; they are bounded at 1e30
- * (no inf or NaN in float32), which leaves the gradient exact wherever it
- * stays below that bound.
+/* Training step core: T fixed min-sum sweeps from the channel LLRs, a loss
+ * on the APPs against the true bits x, and its gradient with respect to the
+ * weights by reverse sweeps over the q's each forward sweep recorded.
+ * Loss term of sweep t: the mean over frames and all n bits of
+ *   softplus(-(1 - 2x) APP_t)   (binary cross-entropy, P(bit = 1) = sigmoid(-APP)),
+ * APP_t being the APPs after sweep t (degree-1 variables included).
+ *   every_sweep = 0: loss = the term of the last sweep;
+ *   every_sweep = 1: loss = the mean of the T terms.
+ *   window in [1, T] (0 = T): the gradient of each term runs back through at
+ *   most `window` sweeps, the term's own and the ones before it, holding the
+ *   state before the earliest of them fixed; the weights of sweep u then
+ *   receive the exact derivatives of the terms t = u .. u + window - 1.
+ *   every_sweep = 0 with window = T is the exact gradient of the final-sweep
+ *   loss (qm_nms_loss_grad).
+ * Over many sweeps the reverse-sweep adjoints grow geometrically (about 20x
+ * per sweep on the workload codes); each is bounded at 1e30, so nothing
+ * becomes inf or NaN, and `clamped` (device int32, or NULL) receives how
+ * many adjoint components reached the bound: 0 means the gradient is exact.
+ * Gradient sums over workgroups are reduced in a fixed order (run-to-run
+ * identical).
  *   x: device uint8 [F][n]; loss: device float scalar; grad: device float,
- *   same layout as weights (first T sweeps).  Needs a train workspace. */
+ *   same layout as weights (first T sweeps).  Needs a train workspace bound
+ *   for at least T sweeps. */
+int qm_nms_train_grad(qm_decoder *dec, const float *weights, const float *llr, const uint8_t *syndrome,
+                      const uint8_t *x, int32_t T, int32_t every_sweep, int32_t window, float *loss, float *grad,
+                      int32_t *clamped, void *stream);
+
+/* qm_nms_train_grad with every_sweep = 0, window = T, clamped = NULL: the
+ * mean binary cross-entropy of the final APPs and its exact gradient
+ * (wherever no adjoint reaches the bound). */
 int qm_nms_loss_grad(qm_decoder *dec, const float *weights, const float *llr, const uint8_t *syndrome,
                      const uint8_t *x, int32_t T, float *loss, float *grad, void *stream);
 

@@ -52,6 +52,9 @@ def _load(path: str):
     L.qo_nms_decode.restype = i32
     L.qo_nms_decode.argtypes = [i32, i32, i32, p, i32, p, p, i32, p, p, i32, p, p, i32,
                                 p, p, p, p, i32]
+    L.qo_nms_train_grad.restype = i32
+    L.qo_nms_train_grad.argtypes = [i32, i32, i32, p, i32, p, p, i32, p, p, p, i32, p, p, i32, i32,
+                                    p, p, p, p, i32]
     L.qo_nms_loss_grad.restype = i32
     L.qo_nms_loss_grad.argtypes = [i32, i32, i32, p, i32, p, p, i32, p, p, p, i32, p, p,
                                    p, p, p, p, i32]
@@ -248,4 +251,28 @@ def nms_loss_grad(shifts, Z, llr, syn, x, T, alpha, beta, schedule=None, threads
                                 _ptr(ga), _ptr(gb), int(threads))
     if rc <= 0:
         raise RuntimeError(f"qo_nms_loss_grad failed: {rc}")
+    return loss.value, ga, gb, app
+
+
+def nms_train_grad(shifts, Z, llr, syn, x, T, alpha, beta, every_sweep, window, schedule=None, threads=0):
+    """Min-sum training objective and its gradient: every_sweep False gives
+    the mean BCE of the APPs after the last sweep, True the mean over the T
+    sweeps of the mean BCE after each sweep; the gradient of each loss term
+    runs back through at most `window` sweeps (its own and the ones before),
+    holding the state before them fixed.  Returns (loss, g_alpha [T,mb,2],
+    g_beta, app)."""
+    sh, mb, nb, n, m, L, S, gp, rw = _prep(shifts, Z, llr, syn, schedule)
+    F = L.shape[0]
+    X = np.ascontiguousarray(np.atleast_2d(x), dtype=np.uint8)
+    a = np.ascontiguousarray(np.broadcast_to(alpha, (T, mb, 2)), dtype=np.float64)
+    b = np.ascontiguousarray(np.broadcast_to(beta, (T, mb, 2)), dtype=np.float64)
+    app = np.empty((F, n), dtype=np.float64)
+    loss = ctypes.c_double(0.0)
+    ga = np.zeros((T, mb, 2), dtype=np.float64)
+    gb = np.zeros((T, mb, 2), dtype=np.float64)
+    rc = lib().qo_nms_train_grad(mb, nb, Z, _ptr(sh), len(gp) - 1, _ptr(gp), _ptr(rw), F, _ptr(L), _ptr(S),
+                                 _ptr(X), int(T), _ptr(a), _ptr(b), 1 if every_sweep else 0, int(window),
+                                 _ptr(app), ctypes.byref(loss), _ptr(ga), _ptr(gb), int(threads))
+    if rc <= 0:
+        raise RuntimeError(f"qo_nms_train_grad failed: {rc}")
     return loss.value, ga, gb, app

@@ -45,7 +45,9 @@
  *                     (Results, kernel optimisations: clipping keeps the
  *                     iterated values finite); analytic reverse-mode
  *                     gradients of the mean binary cross-entropy of the
- *                     final APP (no gradient through an active clip).
+ *                     final APP, or of its mean over the sweeps with each
+ *                     term's gradient taken through a window of sweeps
+ *                     (no gradient through an active clip).
  *
  * Parity pins (tests): brute-force bitwise MAP on cycle-free lifts, brute-
  * force ML on tiny loopy codes, single-check closed form (tanh rule),
@@ -474,6 +476,8 @@ typedef struct {
     double *app; uint8_t *hard, *flags; int32_t *iters;
     /* training */
     int want_grad;
+    int every_sweep;       /* 0: loss on the APPs after the last sweep; 1: mean over sweeps */
+    int window;            /* each loss term's gradient spans at most this many sweeps */
     double *loss_f;        /* [F] per-frame loss sums */
     double *ga_f, *gb_f;   /* [F][T*mb*2] per-frame gradient sums */
     int err;
@@ -505,6 +509,70 @@ static double excl_min(const double *q, int d, int a, int *arg) {
     return mu;
 }
 
+/* Loss term of one frame on its current APPs: adds softplus(-(1-2x) APP)
+ * summed over the n bits, times wt, to *L, and sets gA to its derivative
+ * with respect to each APP (the binary cross-entropy with
+ * P(bit = 1) = sigmoid(-APP); the mean over frames and bits is taken by the
+ * caller). */
+static void nms_loss_term(const double *app, const uint8_t *xb, int n, double wt, double *L, double *gA) {
+    double sum = 0.0;
+    for (int v = 0; v < n; v++) {
+        double sg = xb[v] ? -1.0 : 1.0;          /* 1 - 2x */
+        sum += softplus(-sg * app[v]);
+        gA[v] = -sg * sigmoid(-sg * app[v]);      /* d softplus(-sg A)/dA */
+        gA[v] *= wt;
+    }
+    *L += wt * sum;
+}
+
+/* Reverse of sweep t of one frame, from its recorded q's (tape_t): gA holds
+ * dL/dAPP after the sweep and gR dL/dr for the messages the sweep wrote (what
+ * their later use as r_old sent back); on return they hold the same for the
+ * state before the sweep.  Adds the weight gradients of sweep t into ga, gb. */
+static void nms_backward_sweep(const nms_ctx *x, const uint8_t *s, const double *tape_t, int t, double *gA,
+                               double *gR, double *ga, double *gb, double *q, double *gq, double *gr) {
+    const code_t *c = x->c;
+    const int Z = c->Z, mb = c->mb;
+    for (int g = x->G - 1; g >= 0; g--) {
+        for (int p = x->gptr[g + 1] - 1; p >= x->gptr[g]; p--) {
+            int i = x->rows[p];
+            for (int k = Z - 1; k >= 0; k--) {
+                int chk = i * Z + k;
+                int e0 = c->chk_ptr[chk], d = c->chk_ptr[chk + 1] - e0;
+                for (int a = 0; a < d; a++) q[a] = tape_t[e0 + a];
+                /* APP_new = q + r_new: both receive dL/dAPP_new; r_new
+                 * also carries what its later use as r_old sent back */
+                for (int a = 0; a < d; a++) {
+                    int vn = c->chk_vn[e0 + a];
+                    gq[a] = gA[vn];
+                    gr[a] = gA[vn] + gR[e0 + a];
+                }
+                for (int a = 0; a < d; a++) {
+                    int arg;
+                    double mu = excl_min(q, d, a, &arg);
+                    int neg = s[chk] & 1;
+                    for (int b = 0; b < d; b++) if (b != a) neg ^= (q[b] < 0.0);
+                    double sgn = neg ? -1.0 : 1.0;
+                    int tau = edge_type(c, e0 + a);
+                    size_t w = ((size_t)t * mb + (size_t)i) * 2 + (size_t)tau;
+                    double z = mu - x->beta[w];
+                    ga[w] += gr[a] * sgn * (z > 0.0 ? z : 0.0);
+                    if (z > 0.0) {
+                        double gz = gr[a] * sgn * x->alpha[w];
+                        gb[w] -= gz;
+                        if (arg >= 0) gq[arg] += gz * dabs(q[arg]);
+                    }
+                }
+                /* q = APP_old - r_old */
+                for (int a = 0; a < d; a++) {
+                    gA[c->chk_vn[e0 + a]] = gq[a];
+                    gR[e0 + a] = -gq[a];
+                }
+            }
+        }
+    }
+}
+
 static void nms_frame(void *vctx, int f) {
     nms_ctx *x = (nms_ctx *)vctx;
     const code_t *c = x->c;
@@ -521,9 +589,15 @@ static void nms_frame(void *vctx, int f) {
     double *rn = (double *)malloc(sizeof(double) * (size_t)D);
     double *gq = (double *)malloc(sizeof(double) * (size_t)D);
     double *gr = (double *)malloc(sizeof(double) * (size_t)D);
-    if (!r || !q || !rn || !gq || !gr || (x->want_grad && !tape)) {
-        x->err = -1; free(r); free(tape); free(q); free(rn); free(gq); free(gr); return;
+    double *gA = x->want_grad ? (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1)) : NULL;
+    double *gR = x->want_grad ? (double *)malloc(sizeof(double) * E) : NULL;
+    if (!r || !q || !rn || !gq || !gr || (x->want_grad && (!tape || !gA || !gR))) {
+        x->err = -1; free(r); free(tape); free(q); free(rn); free(gq); free(gr); free(gA); free(gR); return;
     }
+    const uint8_t *xb = x->want_grad ? x->xbits + (size_t)f * n : NULL;
+    double *ga = x->want_grad ? x->ga_f + (size_t)f * (size_t)T * mb * 2 : NULL;
+    double *gb = x->want_grad ? x->gb_f + (size_t)f * (size_t)T * mb * 2 : NULL;
+    if (x->want_grad) x->loss_f[f] = 0.0;
     for (int v = 0; v < n; v++) app[v] = (double)llr[v];
     int used = 0;
     int ok = hard_and_check(c, app, s, hard);
@@ -559,80 +633,32 @@ static void nms_frame(void *vctx, int f) {
         }
         used = t + 1;
         ok = hard_and_check(c, app, s, hard);
+        if (x->want_grad && (x->every_sweep || t == T - 1)) {
+            /* this sweep's loss term, then its gradient back through at most
+             * `window` sweeps (t down to t - window + 1), holding the state
+             * before the earliest of them fixed */
+            nms_loss_term(app, xb, n, x->every_sweep ? 1.0 / (double)T : 1.0, &x->loss_f[f], gA);
+            for (size_t e = 0; e < E; e++) gR[e] = 0.0;
+            int lo = t - x->window + 1;
+            if (lo < 0) lo = 0;
+            for (int u = t; u >= lo; u--)
+                nms_backward_sweep(x, s, tape + (size_t)u * E, u, gA, gR, ga, gb, q, gq, gr);
+        }
     }
     ok = hard_and_check(c, app, s, hard);
     x->flags[f] = (uint8_t)ok;
     if (x->iters) x->iters[f] = used;
 
-    if (x->want_grad) {
-        /* loss: mean over frames and bits of softplus(-(1-2x) APP), i.e. the
-         * binary cross-entropy with P(bit = 1) = sigmoid(-APP).  The per-frame
-         * sums are divided by F*n by the caller. */
-        const uint8_t *xb = x->xbits + (size_t)f * n;
-        double *gA = (double *)malloc(sizeof(double) * (size_t)n);
-        double *gR = (double *)calloc(E, sizeof(double));
-        double *ga = x->ga_f + (size_t)f * (size_t)T * mb * 2;
-        double *gb = x->gb_f + (size_t)f * (size_t)T * mb * 2;
-        if (!gA || !gR) { x->err = -1; free(gA); free(gR); goto done; }
-        double L = 0.0;
-        for (int v = 0; v < n; v++) {
-            double sg = xb[v] ? -1.0 : 1.0;          /* 1 - 2x */
-            L += softplus(-sg * app[v]);
-            gA[v] = -sg * sigmoid(-sg * app[v]);      /* d softplus(-sg A)/dA */
-        }
-        x->loss_f[f] = L;
-        for (int t = T - 1; t >= 0; t--) {
-            for (int g = x->G - 1; g >= 0; g--) {
-                for (int p = x->gptr[g + 1] - 1; p >= x->gptr[g]; p--) {
-                    int i = x->rows[p];
-                    for (int k = Z - 1; k >= 0; k--) {
-                        int chk = i * Z + k;
-                        int e0 = c->chk_ptr[chk], d = c->chk_ptr[chk + 1] - e0;
-                        for (int a = 0; a < d; a++) q[a] = tape[(size_t)t * E + (size_t)(e0 + a)];
-                        /* APP_new = q + r_new: both receive dL/dAPP_new; r_new
-                         * also carries what its later use as r_old sent back */
-                        for (int a = 0; a < d; a++) {
-                            int vn = c->chk_vn[e0 + a];
-                            gq[a] = gA[vn];
-                            gr[a] = gA[vn] + gR[e0 + a];
-                        }
-                        for (int a = 0; a < d; a++) {
-                            int arg;
-                            double mu = excl_min(q, d, a, &arg);
-                            int neg = s[chk] & 1;
-                            for (int b = 0; b < d; b++) if (b != a) neg ^= (q[b] < 0.0);
-                            double sgn = neg ? -1.0 : 1.0;
-                            int tau = edge_type(c, e0 + a);
-                            size_t w = ((size_t)t * mb + (size_t)i) * 2 + (size_t)tau;
-                            double z = mu - x->beta[w];
-                            ga[w] += gr[a] * sgn * (z > 0.0 ? z : 0.0);
-                            if (z > 0.0) {
-                                double gz = gr[a] * sgn * x->alpha[w];
-                                gb[w] -= gz;
-                                if (arg >= 0) gq[arg] += gz * dabs(q[arg]);
-                            }
-                        }
-                        /* q = APP_old - r_old */
-                        for (int a = 0; a < d; a++) {
-                            gA[c->chk_vn[e0 + a]] = gq[a];
-                            gR[e0 + a] = -gq[a];
-                        }
-                    }
-                }
-            }
-        }
-        free(gA); free(gR);
-    }
-done:
-    free(r); free(tape); free(q); free(rn); free(gq); free(gr);
+    free(r); free(tape); free(q); free(rn); free(gq); free(gr); free(gA); free(gR);
 }
 
 static int nms_run(int mb, int nb, int Z, const int *sh, int G, const int *gptr, const int *rows,
                    int F, const float *llr, const uint8_t *syn, const uint8_t *xbits, int T,
-                   const double *alpha, const double *beta, int early_stop,
+                   const double *alpha, const double *beta, int early_stop, int every_sweep, int window,
                    double *app, uint8_t *hard, uint8_t *flags, int32_t *iters,
                    double *loss, double *g_alpha, double *g_beta, int nthreads) {
     if (mb <= 0 || nb <= 0 || Z <= 0 || F < 0 || T < 0) return -1;
+    if (window <= 0 || window > T) window = T;
     if (qo_check_schedule(mb, nb, sh, G, gptr, rows) != 0) return -3;
     code_t c;
     int rc = code_build(&c, mb, nb, Z, sh);
@@ -644,6 +670,7 @@ static int nms_run(int mb, int nb, int Z, const int *sh, int G, const int *gptr,
     x.c = &c; x.G = G; x.gptr = gptr; x.rows = rows; x.llr = llr; x.syn = syn; x.xbits = xbits;
     x.T = T; x.early_stop = early_stop; x.alpha = alpha; x.beta = beta;
     x.app = app; x.hard = hard; x.flags = flags; x.iters = iters; x.want_grad = want;
+    x.every_sweep = every_sweep; x.window = window;
     if (want) {
         x.loss_f = (double *)calloc((size_t)(F > 0 ? F : 1), sizeof(double));
         x.ga_f = (double *)calloc((size_t)(F > 0 ? F : 1) * (W > 0 ? W : 1), sizeof(double));
@@ -675,21 +702,36 @@ int qo_nms_decode(int mb, int nb, int Z, const int *sh, int G, const int *gptr, 
                   int F, const float *llr, const uint8_t *syn, int T,
                   const double *alpha, const double *beta, int early_stop,
                   double *app, uint8_t *hard, uint8_t *flags, int32_t *iters, int nthreads) {
-    return nms_run(mb, nb, Z, sh, G, gptr, rows, F, llr, syn, NULL, T, alpha, beta, early_stop,
+    return nms_run(mb, nb, Z, sh, G, gptr, rows, F, llr, syn, NULL, T, alpha, beta, early_stop, 0, T,
                    app, hard, flags, iters, NULL, NULL, NULL, nthreads);
 }
 
 /* NMS forward over T fixed iterations, loss and analytic gradients.
- * loss: scalar mean BCE; g_alpha, g_beta: double [T][mb][2]. */
+ * every_sweep = 0: the loss is the mean BCE of the APPs after the last sweep;
+ * 1: the mean over the T sweeps of the mean BCE of the APPs after each sweep.
+ * window in [1, T] (anything else: T): the gradient of each loss term is
+ * taken through at most that many sweeps, ending with the term's own, with
+ * the state before the earliest of them held fixed; every_sweep = 0 with
+ * window = T is the exact gradient of the final-sweep loss.
+ * loss: scalar; g_alpha, g_beta: double [T][mb][2]. */
+int qo_nms_train_grad(int mb, int nb, int Z, const int *sh, int G, const int *gptr, const int *rows,
+                      int F, const float *llr, const uint8_t *syn, const uint8_t *xbits, int T,
+                      const double *alpha, const double *beta, int every_sweep, int window,
+                      double *app, double *loss, double *g_alpha, double *g_beta, int nthreads) {
+    uint8_t *hard = (uint8_t *)malloc((size_t)(F > 0 ? F : 1) * (size_t)nb * (size_t)Z);
+    uint8_t *flags = (uint8_t *)malloc((size_t)(F > 0 ? F : 1));
+    if (!hard || !flags) { free(hard); free(flags); return -1; }
+    int rc = nms_run(mb, nb, Z, sh, G, gptr, rows, F, llr, syn, xbits, T, alpha, beta, 0, every_sweep ? 1 : 0,
+                     window, app, hard, flags, NULL, loss, g_alpha, g_beta, nthreads);
+    free(hard); free(flags);
+    return rc;
+}
+
+/* The exact gradient of the final-sweep loss (every_sweep = 0, window = T). */
 int qo_nms_loss_grad(int mb, int nb, int Z, const int *sh, int G, const int *gptr, const int *rows,
                      int F, const float *llr, const uint8_t *syn, const uint8_t *xbits, int T,
                      const double *alpha, const double *beta,
                      double *app, double *loss, double *g_alpha, double *g_beta, int nthreads) {
-    uint8_t *hard = (uint8_t *)malloc((size_t)(F > 0 ? F : 1) * (size_t)nb * (size_t)Z);
-    uint8_t *flags = (uint8_t *)malloc((size_t)(F > 0 ? F : 1));
-    if (!hard || !flags) { free(hard); free(flags); return -1; }
-    int rc = nms_run(mb, nb, Z, sh, G, gptr, rows, F, llr, syn, xbits, T, alpha, beta, 0,
-                     app, hard, flags, NULL, loss, g_alpha, g_beta, nthreads);
-    free(hard); free(flags);
-    return rc;
+    return qo_nms_train_grad(mb, nb, Z, sh, G, gptr, rows, F, llr, syn, xbits, T, alpha, beta, 0, T,
+                             app, loss, g_alpha, g_beta, nthreads);
 }

@@ -170,7 +170,7 @@ struct qm_decoder {
     size_t nws_bytes = 0;
     int32_t nT = 0, ntrain = 0;
     size_t oAd = 0, oAct = 0, oTmask = 0, oIt = 0, oCols = 0, oLossP = 0, oLoss = 0, oX = 0, ogA = 0, ogAd = 0,
-           ogR = 0, oQ = 0, oCkA = 0, oCkR = 0, oPart = 0, nTotal = 0;
+           ogR = 0, oQ = 0, oPart = 0, oClamp = 0, nTotal = 0;
     std::vector<int32_t> acols;  // columns whose APP lives in A (degree != 1)
     int64_t lds_limit = 0;      // LDS bytes one workgroup may use (queried at bind)
     int64_t lds_per_cu = 0;     // LDS bytes of one compute unit (queried at bind)
@@ -1077,12 +1077,13 @@ void nms_layout(qm_decoder &d, const Slot &s, int32_t T, int32_t train) {
         d.ogA = off; off = align_up(off + fp * n * 4);
         d.ogAd = off; off = align_up(off + fp * m * 4);
         d.ogR = off; off = align_up(off + fp * e * 4);
-        d.oQ = off; off = align_up(off + fp * e * 4);
-        d.oCkA = off; off = align_up(off + (size_t)T * fp * n * 4);
-        d.oCkR = off; off = align_up(off + (size_t)T * fp * e * 4);
+        // the q's of every sweep inside a backward window (at most T),
+        // recorded by the forward sweeps: the reverse sweeps need nothing else
+        d.oQ = off; off = align_up(off + (size_t)T * fp * e * 4);
         // per-workgroup gradient sums of the reverse sweep: at most
         // Fpad*Z/64 + Fpad workgroups per (sweep, row)
         d.oPart = off; off = align_up(off + (size_t)T * s.code->mb * (fp * s.code->Z / 64 + fp + 1) * 16);
+        d.oClamp = off; off = align_up(off + 4);
     }
     d.nTotal = off;
 }
@@ -1638,6 +1639,9 @@ int qm_nms_bind_workspace(qm_decoder *d, void *dev, size_t bytes, int32_t T, int
     nms_layout(*d, *s, T, train);
     if (bytes < d->nTotal)
         return fail(QM_ERR_NO_WORKSPACE, "min-sum workspace too small: need " + std::to_string(d->nTotal) + " bytes");
+    // a bound min-sum workspace keeps every code on the layer kernels (the
+    // LDS-resident engine is not taken), so a graph captured before differs
+    drop_graph(*d);
     d->nws = static_cast<char *>(dev);
     d->nws_bytes = bytes;
     d->nT = T;
@@ -1692,11 +1696,14 @@ int qm_nms_decode(qm_decoder *d, const float *W, const float *llr, const uint8_t
     return QM_OK;
 }
 
-int qm_nms_loss_grad(qm_decoder *d, const float *W, const float *llr, const uint8_t *syn, const uint8_t *x,
-                     int32_t T, float *loss, float *grad, void *stream) {
+int qm_nms_train_grad(qm_decoder *d, const float *W, const float *llr, const uint8_t *syn, const uint8_t *x,
+                      int32_t T, int32_t every_sweep, int32_t window, float *loss, float *grad, int32_t *clamped,
+                      void *stream) {
     if (!d || !W || !llr || !syn || !x || !loss || !grad) return fail(QM_ERR_INVALID_ARG, "NULL argument");
     if (!d->bound || !d->nws || !d->ntrain) return fail(QM_ERR_NO_WORKSPACE, "training workspace not bound");
     if (T < 1 || T > d->nT) return fail(QM_ERR_INVALID_ARG, "T must be in [1, T of the bound workspace]");
+    if (window == 0) window = T;
+    if (window < 1 || window > T) return fail(QM_ERR_INVALID_ARG, "window must be 0 or in [1, T]");
     Slot *s = nullptr;
     int rc = nms_slot(*d, &s);
     if (rc != QM_OK) return rc;
@@ -1705,52 +1712,66 @@ int qm_nms_loss_grad(qm_decoder *d, const float *W, const float *llr, const uint
     const TileGeom g = geom(*d, *s);
     const SlotBufs b = slot_bufs(*d, *s);
     const size_t fp = (size_t)s->Fpad;
-    const size_t bytesA = fp * (size_t)s->n * 4, bytesR = fp * (size_t)c.nent1 * c.Z * 4;
-    char *ckA = d->nws + d->oCkA, *ckR = d->nws + d->oCkR;
+    const size_t qsz = fp * (size_t)c.nent1 * c.Z;  // floats of one sweep's q record
     float *Ad = nws_ptr<float>(*d, d->oAd), *Q = nws_ptr<float>(*d, d->oQ);
     float *gA = nws_ptr<float>(*d, d->ogA), *gAd = nws_ptr<float>(*d, d->ogAd), *gR = nws_ptr<float>(*d, d->ogR);
     float *part = nws_ptr<float>(*d, d->oPart);
+    int32_t *clamps = nws_ptr<int32_t>(*d, d->oClamp);
     uint8_t *X = nws_ptr<uint8_t>(*d, d->oX);
 
     if ((rc = nms_init(*d, *s, llr, syn, st)) != QM_OK) return rc;
     QM_HIP(qm_launch_to_tiles_u8(x, X, s->F, s->n, g.ft_log2, g.ntiles, st));
-    // forward, keeping the state at the start of every sweep
-    for (int t = 0; t < T; ++t) {
-        QM_HIP(hipMemcpyAsync(ckA + (size_t)t * bytesA, b.A, bytesA, hipMemcpyDeviceToDevice, st));
-        QM_HIP(hipMemcpyAsync(ckR + (size_t)t * bytesR, b.R, bytesR, hipMemcpyDeviceToDevice, st));
-        if ((rc = nms_sweep(*d, *s, W, t, t == T - 1, nullptr, nullptr, st)) != QM_OK) return rc;
-    }
-    QM_HIP(qm_launch_bce(b.A, Ad, X, gA, gAd, nws_ptr<float>(*d, d->oLossP), nws_ptr<int32_t>(*d, d->oCols),
-                         (int)d->acols.size(), b.rows, c.mb, g, s->F, loss, st));
-    QM_HIP(qm_launch_fill_u32(reinterpret_cast<uint32_t *>(gR), 0u, bytesR / 4, st));
-    // reverse sweeps: restore the sweep's starting state, recompute it while
-    // recording q, then walk its layers backwards
     const RowDesc *rows = b.rows;
     NmsBwdArgs ba;
     std::memset(&ba, 0, sizeof(ba));
     ba.L = layer_args(*d, *s);
-    ba.Q = Q;
     ba.gA = gA;
     ba.gR = gR;
     ba.gAd = gAd;
     ba.part = part;
+    ba.clamps = clamps;
     ba.mb = c.mb;
+    const int per_row = ba.L.ntiles * ba.L.chunks;
+    QM_HIP(qm_launch_fill_u32(reinterpret_cast<uint32_t *>(part), 0u, (size_t)T * c.mb * per_row * 4, st));
+    QM_HIP(qm_launch_fill_u32(reinterpret_cast<uint32_t *>(clamps), 0u, 1, st));
     const int G = (int)s->gptr.size() - 1;
-    for (int t = T - 1; t >= 0; --t) {
-        QM_HIP(hipMemcpyAsync(b.A, ckA + (size_t)t * bytesA, bytesA, hipMemcpyDeviceToDevice, st));
-        QM_HIP(hipMemcpyAsync(b.R, ckR + (size_t)t * bytesR, bytesR, hipMemcpyDeviceToDevice, st));
-        if ((rc = nms_sweep(*d, *s, W, t, 0, nullptr, Q, st)) != QM_OK) return rc;
-        ba.t = t;
-        ba.L.last = (t == T - 1) ? 1 : 0;
-        ba.W = W + (size_t)t * c.mb * 4;
-        for (int gi = G - 1; gi >= 0; --gi) {
-            ba.L.rows = rows + s->gptr[gi];
-            ba.L.nrows = s->gptr[gi + 1] - s->gptr[gi];
-            QM_HIP(qm_launch_nms_bwd(ba, s->maxd_t, ba.L.fpl, d->tun.block, st));
+    const float weight = every_sweep ? 1.0f / (float)T : 1.0f;
+    bool first_term = true;
+    for (int t = 0; t < T; ++t) {
+        // forward sweep t, recording its q's in the window's ring of records;
+        // the degree-1 APPs are formed in every sweep that ends a loss term
+        const bool term = every_sweep || t == T - 1;
+        if ((rc = nms_sweep(*d, *s, W, t, term ? 1 : 0, nullptr, Q + (size_t)(t % window) * qsz, st)) != QM_OK)
+            return rc;
+        if (!term) continue;
+        // this sweep's loss term and dL/dAPP; nothing flows back through
+        // the messages it wrote
+        QM_HIP(qm_launch_bce(b.A, Ad, X, gA, gAd, nws_ptr<float>(*d, d->oLossP), nws_ptr<int32_t>(*d, d->oCols),
+                             (int)d->acols.size(), b.rows, c.mb, g, s->F, weight, first_term ? 0 : 1, loss, st));
+        first_term = false;
+        QM_HIP(qm_launch_fill_u32(reinterpret_cast<uint32_t *>(gR), 0u, qsz, st));
+        // reverse sweeps t, t-1, ... down to the window's first, each from
+        // its recorded q's; the degree-1 edges are targets only in sweep t
+        for (int u = t; u >= 0 && u > t - window; --u) {
+            ba.t = u;
+            ba.Q = Q + (size_t)(u % window) * qsz;
+            ba.L.last = (u == t) ? 1 : 0;
+            ba.W = W + (size_t)u * c.mb * 4;
+            for (int gi = G - 1; gi >= 0; --gi) {
+                ba.L.rows = rows + s->gptr[gi];
+                ba.L.nrows = s->gptr[gi + 1] - s->gptr[gi];
+                QM_HIP(qm_launch_nms_bwd(ba, s->maxd_t, ba.L.fpl, d->tun.block, st));
+            }
         }
     }
-    QM_HIP(qm_launch_grad_reduce(part, grad, T, c.mb, ba.L.ntiles * ba.L.chunks, st));
+    QM_HIP(qm_launch_grad_reduce(part, grad, T, c.mb, per_row, st));
+    if (clamped) QM_HIP(hipMemcpyAsync(clamped, clamps, 4, hipMemcpyDeviceToDevice, st));
     return QM_OK;
+}
+
+int qm_nms_loss_grad(qm_decoder *d, const float *W, const float *llr, const uint8_t *syn, const uint8_t *x,
+                     int32_t T, float *loss, float *grad, void *stream) {
+    return qm_nms_train_grad(d, W, llr, syn, x, T, 0, T, loss, grad, nullptr, stream);
 }
 
 int qm_generate_frames(qm_decoder *d, int32_t code_index, uint64_t seed, uint64_t first_frame, float snr, int32_t F,
@@ -1828,6 +1849,9 @@ int qm_autotune(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t ite
                 t.block = blocks[c];
                 t.merge = 1;
                 t.graph = 0;
+                // the launch shape only matters to the layer kernels: time
+                // those (the LDS-resident engine is a structural variant)
+                t.lds_resident = 0;
                 float ms = 0.0f;
                 rc = trial(t, &ms, probe);
                 if (rc == QM_OK && ms < best_ms) {
@@ -1849,7 +1873,7 @@ int qm_autotune(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t ite
     const int full = std::min<int>(iters, 256);
     if (rc == QM_OK) rc = trial(best, &best_ms, full);
     const int caps[3] = {0, 8, 12};
-    for (int v = 0; v < 12 && rc == QM_OK; ++v) {
+    for (int v = 0; v < 11 && rc == QM_OK; ++v) {
         qm_tuning t = best;
         if (v >= 8) {
             // codes on their own streams: other residency caps of the
@@ -1868,10 +1892,6 @@ int qm_autotune(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t ite
         if (v == 4) {
             if (!lds_candidate || t.lds_resident == 1) continue;
             t.lds_resident = 1;
-        }
-        if (v == 11) {
-            if (!lds_candidate || t.lds_resident == 0) continue;
-            t.lds_resident = 0;
         }
         if (v == 3) t.stream_hint = !t.stream_hint;
         if (v == 0) t.merge = 0;

@@ -341,8 +341,9 @@ __device__ __forceinline__ float block_sum(float v, float *lds) {
     return s;
 }
 
-// binary cross-entropy of the final APPs: loss = sum softplus(-(1-2x) APP)
-// (scaled by inv_norm = 1/(F n) at the end); dL/dAPP = -(1-2x) sigmoid(-(1-2x) APP) * inv_norm.
+// binary cross-entropy of the current APPs: loss = sum softplus(-(1-2x) APP)
+// (scaled by inv_norm at the end: 1/(F n), divided by T for one term of a
+// loss over T sweeps); dL/dAPP = -(1-2x) sigmoid(-(1-2x) APP) * inv_norm.
 // part 0: variables of columns in `cols` (APP in A); part 1: degree-1
 // variables (APP in Ad, by check).  One partial sum per workgroup.
 __global__ void __launch_bounds__(256) k_bce(const float *__restrict__ A, const float *__restrict__ Ad,
@@ -388,12 +389,14 @@ __global__ void __launch_bounds__(256) k_bce(const float *__restrict__ A, const 
     if (threadIdx.x == 0) part[b] = s;
 }
 
-__global__ void k_sum_parts(const float *part, int n, float scale, float *out) {
+// *out = sum(part) * scale, or *out += that (accumulate: a loss with one term
+// per sweep, added in sweep order)
+__global__ void k_sum_parts(const float *part, int n, float scale, int accumulate, float *out) {
     __shared__ float lds[8];
     float v = 0.0f;
     for (int i = threadIdx.x; i < n; i += blockDim.x) v += part[i];
     const float s = block_sum(v, lds);
-    if (threadIdx.x == 0) *out = s * scale;
+    if (threadIdx.x == 0) *out = (accumulate ? *out : 0.0f) + s * scale;
 }
 
 // -------------------------------------------------------------- backward --
@@ -406,7 +409,7 @@ __global__ void k_sum_parts(const float *part, int n, float scale, float *out) {
 // the loss there); gradients into its q stop at the channel LLR.
 template <int D, int FPL>
 __device__ __forceinline__ void check_nms_bwd(const LaneCtx &c, ConstRowDesc *rd, const NmsBwdArgs &ba,
-                                              const NmsDev &nd, bool valid, float acc[4]) {
+                                              const NmsDev &nd, bool valid, float acc[4], int &clamped) {
     if (!valid) return;
     const uint32_t col_bytes = c.colw * 4u;
     const uint32_t vo4 = c.node * 4u;
@@ -506,7 +509,9 @@ __device__ __forceinline__ void check_nms_bwd(const LaneCtx &c, ConstRowDesc *rd
             if (pos[j] == mn[f].p1) g += G1[f] * dabs(q[j][f]);
             if (pos[j] == mn[f].p2) g += G2[f] * dabs(q[j][f]);
             // adjoints can grow geometrically over many reverse sweeps; bound
-            // them well inside float32 so that no inf (and no inf - inf) arises
+            // them well inside float32 so that no inf (and no inf - inf)
+            // arises, and count every component the bound changes
+            clamped += (fabsf(g) > kAdjointMax) ? 1 : 0;
             g = fminf(fmaxf(g, -kAdjointMax), kAdjointMax);
             ga[f] = g;
             gro[f] = -g;
@@ -518,13 +523,13 @@ __device__ __forceinline__ void check_nms_bwd(const LaneCtx &c, ConstRowDesc *rd
 
 template <int D, int FPL>
 __device__ __forceinline__ void dispatch_nms_bwd(int d, const LaneCtx &c, ConstRowDesc *rd, const NmsBwdArgs &ba,
-                                                 const NmsDev &nd, bool valid, float acc[4]) {
+                                                 const NmsDev &nd, bool valid, float acc[4], int &clamped) {
     if constexpr (D >= 0) {
         if (d == D) {
-            check_nms_bwd<D, FPL>(c, rd, ba, nd, valid, acc);
+            check_nms_bwd<D, FPL>(c, rd, ba, nd, valid, acc, clamped);
             return;
         }
-        dispatch_nms_bwd<D - 1, FPL>(d, c, rd, ba, nd, valid, acc);
+        dispatch_nms_bwd<D - 1, FPL>(d, c, rd, ba, nd, valid, acc, clamped);
     }
 }
 
@@ -544,14 +549,23 @@ __global__ void __launch_bounds__(256) k_nms_bwd(const NmsBwdArgs ba) {
     nd.rgAd = make_rsrc(ba.gAd + (int64_t)tile * sM, (uint32_t)(sM * 4));
     ConstRowDesc *rd = as_const(ba.L.rows + rs);
     float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    dispatch_nms_bwd<MAXD, FPL>(rd->d, c, rd, ba, nd, valid, acc);
+    int clamped = 0;
+    dispatch_nms_bwd<MAXD, FPL>(rd->d, c, rd, ba, nd, valid, acc, clamped);
+    // clamped adjoints (rare: long unrolls only): one atomic per wave that has any
+    if (__ballot(clamped != 0) != 0ull) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) clamped += __shfl_xor(clamped, o, 64);
+        if ((threadIdx.x & 63u) == 0u) atomicAdd(ba.clamps, clamped);
+    }
     float out[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) out[i] = block_sum(acc[i], lds);
     if (threadIdx.x == 0) {
+        // a sweep's weights take one partial per loss term whose window
+        // reaches them; the launches run in a fixed order, so the sums do too
         float *p = ba.part + ((((int64_t)ba.t * ba.mb + rd->row) * ba.L.ntiles + tile) * ba.L.chunks + chunk) * 4;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) p[i] = out[i];
+        for (int i = 0; i < 4; ++i) p[i] += out[i];
     }
 }
 
@@ -622,7 +636,7 @@ hipError_t qm_launch_nms_layer(const NmsLayerArgs &na, int maxd, int fpl, int bl
         case 5: { QM_NP(5) }
         case 6: { QM_NP(6) }
         case 8: { QM_NP(8) }
-        default: { QM_N(16, 1); break; }
+        default: { QM_NP(16) }
     }
 #undef QM_NP
 #undef QM_N
@@ -648,7 +662,7 @@ hipError_t qm_launch_nms_bwd(const NmsBwdArgs &ba, int maxd, int fpl, int block,
         case 5: { QM_BP(5) }
         case 6: { QM_BP(6) }
         case 8: { QM_BP(8) }
-        default: { QM_B(16, 1); break; }
+        default: { QM_BP(16) }
     }
 #undef QM_BP
 #undef QM_B
@@ -697,14 +711,14 @@ int qm_bce_blocks(int ncols, int mb, const TileGeom &g) {
 
 hipError_t qm_launch_bce(const float *A, const float *Ad, const uint8_t *X, float *gA, float *gAd, float *part,
                          const int32_t *cols, int ncols, const RowDesc *rows, int mb, const TileGeom &g, int F,
-                         float *loss, hipStream_t s) {
+                         float weight, int accumulate, float *loss, hipStream_t s) {
     const int chunks = ((g.Z << g.ft_log2) + 255) / 256;
     const int blocks = g.ntiles * (ncols + mb) * chunks;
-    const float inv = 1.0f / ((float)F * (float)g.n);
+    const float inv = weight / ((float)F * (float)g.n);
     hipLaunchKernelGGL(k_bce, dim3((unsigned)blocks), dim3(256), 0, s, A, Ad, X, gA, gAd, part, cols, ncols, rows,
                        mb, g.Z, g.ft_log2, g.ntiles, chunks, (int64_t)g.n << g.ft_log2, (int64_t)g.m << g.ft_log2,
                        F, inv);
-    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, part, blocks, inv, loss);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, part, blocks, inv, accumulate, loss);
     return hipGetLastError();
 }
 

@@ -142,7 +142,8 @@ struct NmsBwdArgs {
     float *gR;                // [ntiles][nent1*Z][FT] dLoss/dr from later sweeps (in/out)
     const float *gAd;         // [ntiles][m][FT] dLoss/dAPP of degree-1 variables (last sweep)
     const float *W;           // this sweep's weights
-    float *part;              // per-workgroup sums [T][mb][ntiles][chunks][4]
+    float *part;              // per-workgroup sums [T][mb][ntiles][chunks][4], accumulated
+    int32_t *clamps;          // adjoint components that reached the bound (device counter)
     int32_t t, mb;
 };
 
@@ -242,7 +243,7 @@ hipError_t qm_launch_et_final(const uint32_t *act, int32_t *iters, int Fpad, int
 int qm_bce_blocks(int ncols, int mb, const TileGeom &g);
 hipError_t qm_launch_bce(const float *A, const float *Ad, const uint8_t *X, float *gA, float *gAd, float *part,
                          const int32_t *cols, int ncols, const RowDesc *rows, int mb, const TileGeom &g, int F,
-                         float *loss, hipStream_t s);
+                         float weight, int accumulate, float *loss, hipStream_t s);
 hipError_t qm_launch_grad_reduce(const float *part, float *grad, int T, int mb, int per_row, hipStream_t s);
 hipError_t qm_launch_adam(float *w, const float *g, float *m, float *v, int n, float lr, float b1, float b2, float eps,
                           int step, hipStream_t s);

@@ -42,7 +42,7 @@ EXPORTED = [
     "qm_decoder_workspace_bytes", "qm_decoder_bind_workspace", "qm_decoder_set_tuning",
     "qm_decoder_get_tuning", "qm_decode", "qm_decode_early", "qm_autotune", "qm_decoder_set_profiling",
     "qm_decoder_get_profile", "qm_nms_workspace_bytes", "qm_nms_bind_workspace", "qm_nms_decode",
-    "qm_nms_loss_grad", "qm_adam_step", "qm_generate_frames", "qm_decode_noalloc",
+    "qm_nms_loss_grad", "qm_adam_step", "qm_generate_frames", "qm_decode_noalloc", "qm_nms_train_grad",
 ]
 
 QM_NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -115,6 +115,7 @@ def lib():
         L.qm_nms_bind_workspace.argtypes = [p, p, sz, i32, i32]
         L.qm_nms_decode.argtypes = [p, p, p, p, i32, i32, p, p, p, p, p]
         L.qm_nms_loss_grad.argtypes = [p, p, p, p, p, i32, p, p, p]
+        L.qm_nms_train_grad.argtypes = [p, p, p, p, p, i32, i32, i32, p, p, p, p]
         f32 = ctypes.c_float
         L.qm_adam_step.argtypes = [p, p, p, p, i32, f32, f32, f32, f32, i32, p]
         u64 = ctypes.c_uint64
@@ -278,6 +279,13 @@ def qm_nms_loss_grad(dec, weights, llr, syndrome, x, T: int, loss, grad, stream=
                                   _dptr(grad), _stream_handle(stream)))
 
 
+def qm_nms_train_grad(dec, weights, llr, syndrome, x, T: int, every_sweep: bool, window: int, loss, grad,
+                      clamped=None, stream=None) -> None:
+    _check(lib().qm_nms_train_grad(dec, _dptr(weights), _dptr(llr), _dptr(syndrome), _dptr(x), int(T),
+                                   1 if every_sweep else 0, int(window), _dptr(loss), _dptr(grad), _dptr(clamped),
+                                   _stream_handle(stream)))
+
+
 def qm_generate_frames(dec, code_index: int, seed: int, first_frame: int, snr: float, F: int, x, llr, syndrome,
                        stream=None) -> None:
     _check(lib().qm_generate_frames(dec, int(code_index), int(seed), int(first_frame), float(snr), int(F), _dptr(x),
@@ -428,6 +436,17 @@ class Decoder:
         qm_nms_loss_grad(self.handle, weights.reshape(-1), llr.reshape(-1), syndrome.reshape(-1), x.reshape(-1), T,
                          loss, grad, stream)
         return loss, grad
+
+    def nms_train_grad(self, weights, llr, syndrome, x, T: int, every_sweep: bool = True, window: int = 1,
+                       stream=None):
+        """Returns (loss, grad, clamped) device tensors (qm_nms_train_grad)."""
+        import torch
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        grad = torch.empty_like(weights)
+        clamped = torch.empty(1, dtype=torch.int32, device=self.device)
+        qm_nms_train_grad(self.handle, weights.reshape(-1), llr.reshape(-1), syndrome.reshape(-1), x.reshape(-1), T,
+                          every_sweep, window, loss, grad, clamped, stream)
+        return loss, grad, clamped
 
     def __del__(self):
         h = getattr(self, "handle", None)

@@ -1,10 +1,20 @@
 """Train and evaluate the learned (normalized/offset min-sum) decoder on the GPU.
 
 Training: every step draws fresh frames on the GPU (Philox4x32-10; half at
-each training SNR), runs T unrolled min-sum sweeps with per-sweep
-checkpoints, the mean binary cross-entropy of the final APPs and its exact
-gradient (qm_nms_loss_grad), then one Adam step (qm_adam_step).  Weights
+each training SNR), runs T unrolled min-sum sweeps recording each sweep's
+q's, a binary cross-entropy loss on the APPs and its gradient by reverse
+sweeps (qm_nms_train_grad), then one Adam step (qm_adam_step).  Weights
 start at plain min-sum (alpha = 1, beta = 0).
+
+The default objective is the mean over the T sweeps of the BCE of each
+sweep's APPs, each term's gradient taken back through `window` sweeps (its
+own and the ones before it, the state before them held fixed).  At the
+training SNRs the unrolled min-sum dynamics are chaotic: the exact gradient
+of the final sweep's loss grows about 20x per sweep (1e32 after 25 sweeps),
+beyond float32 and meaningless as a descent direction, while a short window
+keeps every term's gradient exact and small.  --loss final --window T gives
+the final-sweep loss with the full unroll; the training log reports how
+many adjoint components reached the library's bound (0 = exact gradients).
 
 Evaluation: a seeded batch from the workload module, decoded by the trained
 min-sum with per-sweep syndrome tests (early stop, mean iterations); frames
@@ -51,7 +61,7 @@ def extend_weights(w, T):
 
 
 def train(spec, shifts, steps=2000, frames=16, T=100, lr=1e-3, snrs=(0.161, 0.15), seed=0, log_every=100,
-          weights=None, log=print):
+          weights=None, log=print, every_sweep=True, window=2):
     import torch
     code = Q.Code(shifts, spec.Z)
     dec = Q.Decoder([code], [frames])
@@ -64,6 +74,8 @@ def train(spec, shifts, steps=2000, frames=16, T=100, lr=1e-3, snrs=(0.161, 0.15
     syn = torch.empty(frames * spec.m, dtype=torch.uint8, device="cuda")
     per = frames // len(snrs)
     history = []
+    clamp_total = torch.zeros(1, dtype=torch.int64, device="cuda")
+    clamp_logged = 0
     t0 = time.perf_counter()
     for step in range(1, steps + 1):
         for i, snr in enumerate(snrs):
@@ -72,7 +84,8 @@ def train(spec, shifts, steps=2000, frames=16, T=100, lr=1e-3, snrs=(0.161, 0.15
             Q.qm_generate_frames(dec.handle, 0, seed, (step * frames + o), snr, F,
                                  x[o * spec.n:(o + F) * spec.n], llr[o * spec.n:(o + F) * spec.n],
                                  syn[o * spec.m:(o + F) * spec.m])
-        loss, grad = dec.nms_loss_grad(w, llr, syn, x, T)
+        loss, grad, clamped = dec.nms_train_grad(w, llr, syn, x, T, every_sweep, window)
+        clamp_total += clamped
         Q.qm_adam_step(w, grad, m, v, lr, 0.9, 0.999, 1e-8, step)
         if step % log_every == 0 or step == 1 or step == steps:
             lv = float(loss.item())
@@ -83,17 +96,21 @@ def train(spec, shifts, steps=2000, frames=16, T=100, lr=1e-3, snrs=(0.161, 0.15
             gd = grad.double()
             fin = torch.isfinite(gd)
             gmax = float(gd[fin].abs().max().item()) if bool(fin.any()) else None
+            ct = int(clamp_total.item())
             log(json.dumps({"step": step, "loss": round(lv, 6), "grad_finite_frac": round(float(fin.double().mean()), 4),
-                            "grad_absmax_finite": gmax,
+                            "grad_absmax_finite": gmax, "clamped_adjoints": ct - clamp_logged,
+                            "clamped_adjoints_total": ct,
                             "alpha_mean": float(w[..., 0].mean().item()), "beta_mean": float(w[..., 1].mean().item()),
                             "elapsed_s": round(time.perf_counter() - t0, 1)}))
+            clamp_logged = ct
     torch.cuda.synchronize()
-    return w, history, time.perf_counter() - t0
+    return w, history, time.perf_counter() - t0, int(clamp_total.item())
 
 
-def heldout_loss(spec, shifts, weights, T, frames=16, snrs=(0.161, 0.15), seed=1, batches=8):
-    """Mean training loss (BCE of the sweep-T APPs against the transmitted
-    bits) over fresh frames drawn with another generator seed."""
+def heldout_loss(spec, shifts, weights, T, frames=16, snrs=(0.161, 0.15), seed=1, batches=8, every_sweep=True):
+    """Mean training loss (BCE of the APPs against the transmitted bits: the
+    mean over the T sweeps, or of the last sweep only) over fresh frames
+    drawn with another generator seed."""
     import torch
     code = Q.Code(shifts, spec.Z)
     dec = Q.Decoder([code], [frames])
@@ -110,7 +127,7 @@ def heldout_loss(spec, shifts, weights, T, frames=16, snrs=(0.161, 0.15), seed=1
             o = i * per
             Q.qm_generate_frames(dec.handle, 0, seed, b * frames + o, snr, F, x[o * spec.n:(o + F) * spec.n],
                                  llr[o * spec.n:(o + F) * spec.n], syn[o * spec.m:(o + F) * spec.m])
-        loss, _ = dec.nms_loss_grad(w, llr, syn, x, T)
+        loss, _, _ = dec.nms_train_grad(w, llr, syn, x, T, every_sweep, 1)
         total += float(loss.item())
     return total / batches
 
@@ -196,6 +213,10 @@ def main():
     ap.add_argument("--T-train", type=int, default=None,
                     help="unrolled sweeps while training (default T); later sweeps reuse the last trained sweep's "
                          "weights")
+    ap.add_argument("--loss", choices=("sweeps", "final"), default="sweeps",
+                    help="BCE averaged over every sweep's APPs, or of the last sweep's only")
+    ap.add_argument("--window", type=int, default=2,
+                    help="sweeps each loss term's gradient runs back through (0 = all)")
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--eval-frames", type=int, default=128)
@@ -215,19 +236,23 @@ def main():
     T_train = args.T_train or args.T
     if args.steps > 0:
         snrs = tuple(float(x) for x in args.train_snrs.split(",") if x)
-        w, hist, secs = train(spec, shifts, steps=args.steps, frames=args.frames, T=T_train, lr=args.lr, snrs=snrs,
-                              seed=args.seed, weights=None if w0 is None else w0[:T_train].contiguous())
-        print(json.dumps({"trained_steps": args.steps, "T_train": T_train, "train_snrs": snrs,
-                          "train_seconds": round(secs, 1),
+        every = args.loss == "sweeps"
+        win = args.window if args.window > 0 else T_train
+        w, hist, secs, clamped = train(spec, shifts, steps=args.steps, frames=args.frames, T=T_train, lr=args.lr, snrs=snrs,
+                              seed=args.seed, weights=None if w0 is None else w0[:T_train].contiguous(),
+                              every_sweep=every, window=win)
+        print(json.dumps({"trained_steps": args.steps, "T_train": T_train, "train_snrs": snrs, "loss": args.loss,
+                          "window": win, "train_seconds": round(secs, 1), "clamped_adjoints_total": clamped,
                           "loss_first": hist[0][1], "loss_last": hist[-1][1]}), flush=True)
     if w is None:
         w = plain_minsum_weights(args.T, spec.mb)
     if args.steps > 0:
         # the training objective on frames it never saw, trained against plain min-sum
         snrs = tuple(float(x) for x in args.train_snrs.split(",") if x)
-        lt = heldout_loss(spec, shifts, w, T_train, frames=args.frames, snrs=snrs, seed=args.seed + 1)
+        lt = heldout_loss(spec, shifts, w, T_train, frames=args.frames, snrs=snrs, seed=args.seed + 1,
+                          every_sweep=every)
         lp = heldout_loss(spec, shifts, plain_minsum_weights(T_train, spec.mb), T_train, frames=args.frames, snrs=snrs,
-                          seed=args.seed + 1)
+                          seed=args.seed + 1, every_sweep=every)
         print(json.dumps({"heldout_loss_trained": round(lt, 6), "heldout_loss_plain_minsum": round(lp, 6)}), flush=True)
     w = extend_weights(w, args.T)
     if args.save:

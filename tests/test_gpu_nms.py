@@ -195,12 +195,73 @@ def test_training_lowers_the_loss_on_unseen_frames():
     from paper_2004_09084_amd import train_nms as TN
     H = W.make_code(SMALL, 0)
     T = 10
-    w, hist, _ = TN.train(SMALL, H, steps=150, frames=16, T=T, lr=1e-2, seed=3, log_every=1000, log=lambda *_: None)
-    lt = TN.heldout_loss(SMALL, H, w, T, frames=16, seed=4, batches=4)
-    lp = TN.heldout_loss(SMALL, H, TN.plain_minsum_weights(T, SMALL.mb), T, frames=16, seed=4, batches=4)
-    say("training loss", hist[0][1], "->", hist[-1][1], "held-out: trained", lt, "plain", lp)
+    w, hist, _, clamped = TN.train(SMALL, H, steps=150, frames=16, T=T, lr=1e-2, seed=3, log_every=1000,
+                                   log=lambda *_: None, every_sweep=False, window=T)
+    lt = TN.heldout_loss(SMALL, H, w, T, frames=16, seed=4, batches=4, every_sweep=False)
+    lp = TN.heldout_loss(SMALL, H, TN.plain_minsum_weights(T, SMALL.mb), T, frames=16, seed=4, batches=4,
+                         every_sweep=False)
+    say("training loss", hist[0][1], "->", hist[-1][1], "held-out: trained", lt, "plain", lp, "clamped", clamped)
     assert np.isfinite(lt) and np.isfinite(lp)
     assert lt < 0.85 * lp
+
+
+@pytest.mark.parametrize("T,every,window", [(5, True, 1), (5, True, 3), (5, False, 2), (25, True, 1), (25, True, 3),
+                                           (25, False, 25)])
+def test_nms_train_grad_matches_oracle(T, every, window):
+    # the general objective (final-sweep loss or the mean over sweeps, each
+    # term's gradient through a window of sweeps) against the oracle, up to
+    # 25 unrolled sweeps.  At SNR 0.3 the unrolled dynamics are stable: an
+    # oracle-only check moves the 25-sweep gradients by under 1e-5 relative
+    # when the LLRs move by float32 rounding (at SNR 0.161 they change
+    # completely, so depth parity is only meaningful away from it)
+    import torch
+    F = 6
+    wl = W.build(SMALL, F, snr=0.3, frame_seed=4)
+    rng = np.random.default_rng(T + window)
+    w = np.stack([rng.uniform(0.7, 1.0, (T, SMALL.mb, 2)), rng.uniform(0.0, 0.2, (T, SMALL.mb, 2))],
+                 axis=-1).astype(np.float32)
+    a, b = w[..., 0].astype(np.float64), w[..., 1].astype(np.float64)
+    code, dec = _dec(wl.shifts, SMALL.Z, F, T, train=True)
+    loss, grad, clamped = dec.nms_train_grad(to_dev(w), to_dev(wl.llr), to_dev(wl.s), to_dev(wl.x), T, every, window)
+    torch.cuda.synchronize()
+    lo, ga, gb, _ = oracle.nms_train_grad(wl.shifts, SMALL.Z, wl.llr, wl.s, wl.x, T, a, b, every, window)
+    say(f"T={T} every={every} window={window}: loss gpu {float(loss.cpu()):.8f} oracle {lo:.8f}, "
+        f"clamped {int(clamped.cpu())}")
+    assert int(clamped.cpu()) == 0
+    assert abs(float(loss.cpu()) - lo) <= 1e-5 * abs(lo)
+    g = grad.cpu().numpy().reshape(T, SMALL.mb, 2, 2).astype(np.float64)
+    for comp, ref in ((0, ga), (1, gb)):
+        err = np.abs(g[..., comp] - ref)
+        lim = 1e-3 * np.abs(ref) + 2e-4 * np.abs(ref).max()
+        say(f"grad comp {comp}: max |g| {np.abs(ref).max():.3e} max err {err.max():.3e}")
+        assert np.all(err <= lim), (comp, np.argwhere(err > lim)[:5])
+
+
+def test_nms_train_grad_reports_clamped_adjoints():
+    # at SNR 0.161 the exact gradient of the final-sweep loss through 40
+    # sweeps exceeds the adjoint bound (the oracle's weight gradients reach
+    # about 1e51): the count says so; a one-sweep window over the same frames
+    # stays exact
+    import torch
+    T, F = 40, 4
+    wl = W.build(SMALL, F, snr=0.161, frame_seed=1)
+    w = _plain_weights(T)
+    code, dec = _dec(wl.shifts, SMALL.Z, F, T, train=True)
+    args = (to_dev(w), to_dev(wl.llr), to_dev(wl.s), to_dev(wl.x), T)
+    _, g_full, c_full = dec.nms_train_grad(*args, False, T)
+    _, g_win, c_win = dec.nms_train_grad(*args, True, 1)
+    torch.cuda.synchronize()
+    say("clamped: full unroll", int(c_full.cpu()), "window 1", int(c_win.cpu()))
+    assert int(c_full.cpu()) > 0
+    assert int(c_win.cpu()) == 0
+    assert torch.isfinite(g_full).all() and torch.isfinite(g_win).all()
+    assert float(g_win.abs().max()) < 1.0
+
+
+def _plain_weights(T):
+    w = np.zeros((T, SMALL.mb, 2, 2), dtype=np.float32)
+    w[..., 0] = 1.0
+    return w
 
 
 def test_nms_requires_one_float32_code():

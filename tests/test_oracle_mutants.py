@@ -36,6 +36,12 @@ MUTANTS = {
                         "for (size_t e = 0; e < (size_t)c->E; e++) r[e] = rn[e];\n        for (int v = 0; v < n; v++) app[v] = 0.0;"),
     "flood_drops_old_message": ("q[a] = app[c->chk_vn[e0 + a]] - r[e0 + a];\n                ph[a] = qo_phi(qo_clip(fabs(q[a])));\n            }\n            for (int a = 0; a < d; a++) {\n                double S = 0.0;\n                int neg = s[chk] & 1;",
                                 "q[a] = app[c->chk_vn[e0 + a]];\n                ph[a] = qo_phi(qo_clip(fabs(q[a])));\n            }\n            for (int a = 0; a < d; a++) {\n                double S = 0.0;\n                int neg = s[chk] & 1;"),
+    "loss_normalised_by_frames_only": ("double norm = 1.0 / ((double)F * (double)c.n);", "double norm = 1.0 / (double)F;"),
+    "loss_and_gradient_sign": ("sum += softplus(-sg * app[v]);\n        gA[v] = -sg * sigmoid(-sg * app[v]);",
+                               "sum -= softplus(-sg * app[v]);\n        gA[v] = sg * sigmoid(-sg * app[v]);"),
+    "window_one_sweep_long": ("int lo = t - x->window + 1;", "int lo = t - x->window;"),
+    "sweep_terms_unweighted": ("x->every_sweep ? 1.0 / (double)T : 1.0", "1.0"),
+    "sweep_terms_skip_first": ("if (x->want_grad && (x->every_sweep || t == T - 1)) {", "if (x->want_grad && ((x->every_sweep && t > 0) || t == T - 1)) {"),
     "loss_sign": ("gA[v] = -sg * sigmoid(-sg * app[v]);", "gA[v] = sg * sigmoid(-sg * app[v]);"),
 }
 

@@ -186,6 +186,7 @@ def test_sp_equals_minsum_on_degree2_codes():
 def test_tree_lift_gives_exact_map():
     # A cycle-free base graph lifts to a forest, where BP is exact (bitwise MAP)
     rng = np.random.default_rng(4)
+    ran = 0
     for trial in range(6):
         base = random_tree_base(rng, n_rows=int(rng.integers(2, 5)), max_new=2)
         Z = 2
@@ -198,6 +199,8 @@ def test_tree_lift_gives_exact_map():
         ref = map_llr(Hd, s, llr)
         app, _, _, _ = oracle.decode_sp(H, Z, llr[None], s[None], 12)
         assert np.max(np.abs(app[0] - ref)) < 1e-9, trial
+        ran += 1
+    assert ran >= 3, ran
 
 
 def test_tiny_loopy_codes_high_snr_match_ml_and_truth():
@@ -508,6 +511,81 @@ def test_nms_degree1_weights_only_act_in_the_last_iteration():
     assert np.all(ga[:T - 1, :, 1] == 0) and np.all(gb[:T - 1, :, 1] == 0)
     assert np.any(ga[T - 1, :, 1] != 0)
     assert np.any(ga[:, :, 0] != 0)
+
+
+def test_nms_sweep_mean_loss_and_windowed_gradients():
+    # loss over every sweep: the mean over tau = 1..T of the final-sweep loss
+    # after tau sweeps.  With a window of W sweeps, the gradient for the
+    # weights of sweep t collects the terms whose window reaches back to t,
+    # tau = t+1 .. min(T, t+W); the state before a window does not depend on
+    # the weights inside it, so each contribution is that term's full
+    # derivative, taken here by central differences of final-sweep losses
+    H, Z, X, L, S = _fd_setup()
+    T, W_, mb = 4, 2, H.shape[0]
+    rng = np.random.default_rng(15)
+    alpha = rng.uniform(0.6, 1.0, (T, mb, 2))
+    beta = rng.uniform(0.0, 0.3, (T, mb, 2))
+
+    def final_loss(tau, a, b):
+        return oracle.nms_loss_grad(H, Z, L, S, X, tau, a[:tau], b[:tau])[0]
+
+    loss, ga, gb, _ = oracle.nms_train_grad(H, Z, L, S, X, T, alpha, beta, True, W_)
+    ref = np.mean([final_loss(tau, alpha, beta) for tau in range(1, T + 1)])
+    assert abs(loss - ref) <= 1e-13 * ref, (loss, ref)
+    h = 1e-6
+    checked = 0
+    for (t, i, tau_e) in [(0, 0, 0), (1, 3, 0), (2, 5, 0), (3, 7, 1), (1, 10, 1), (0, 20, 0), (2, 30, 0)]:
+        for which, P, G in (("a", alpha, ga), ("b", beta, gb)):
+            fd = 0.0
+            for tau in range(t + 1, min(T, t + W_) + 1):
+                Pp = P.copy(); Pp[t, i, tau_e] += h
+                Pm = P.copy(); Pm[t, i, tau_e] -= h
+                if which == "a":
+                    fd += (final_loss(tau, Pp, beta) - final_loss(tau, Pm, beta)) / (2 * h)
+                else:
+                    fd += (final_loss(tau, alpha, Pp) - final_loss(tau, alpha, Pm)) / (2 * h)
+            fd /= T
+            assert abs(fd - G[t, i, tau_e]) <= 1e-6 * max(abs(fd), 1e-4) + 1e-9, (which, t, i, tau_e, fd, G[t, i, tau_e])
+            checked += 1
+    assert checked == 14
+    # the final-sweep loss with a full window is the exact gradient of that loss
+    l0, ga0, gb0, _ = oracle.nms_loss_grad(H, Z, L, S, X, T, alpha, beta)
+    l1, ga1, gb1, _ = oracle.nms_train_grad(H, Z, L, S, X, T, alpha, beta, False, T)
+    assert l0 == l1 and np.array_equal(ga0, ga1) and np.array_equal(gb0, gb1)
+
+
+def test_nms_loss_is_the_mean_bce_of_the_final_app():
+    # the loss is the binary cross-entropy with logits, P(bit = 1) =
+    # sigmoid(-APP), averaged over every frame and every one of the n bits:
+    # softplus(-(1 - 2x) APP) summed and divided by F*n.  The APPs come from
+    # the forward decode alone (which computes no loss) and the sum is numpy's
+    H, Z, X, L, S = _fd_setup()
+    T, mb = 3, H.shape[0]
+    rng = np.random.default_rng(14)
+    alpha = rng.uniform(0.6, 1.0, (T, mb, 2))
+    beta = rng.uniform(0.0, 0.3, (T, mb, 2))
+    app, _, _, _ = oracle.nms_decode(H, Z, L, S, T, alpha, beta)
+    loss, _, _, app_l = oracle.nms_loss_grad(H, Z, L, S, X, T, alpha, beta)
+    assert np.array_equal(app, app_l)
+    sign = 1.0 - 2.0 * X.astype(np.float64)
+    ref = np.logaddexp(0.0, -sign * app).sum() / (X.shape[0] * X.shape[1])
+    assert loss > 0.0
+    assert abs(loss - ref) <= 1e-12 * ref, (loss, ref)
+
+
+def test_nms_loss_hand_case():
+    # one degree-2 check (Z = 1) on bits x = (0, 1), LLRs (1.5, -0.5),
+    # syndrome 0, one min-sum sweep with alpha = 1, beta = 0: each message is
+    # the other bit's LLR, so both APPs are 1.5 - 0.5 = 1.0.  Bit 0 costs
+    # ln(1 + e^-1), bit 1 costs ln(1 + e^1); the loss is their mean.
+    H = np.array([[0, 0]], dtype=np.int32)
+    L = np.array([[1.5, -0.5]], dtype=np.float32)
+    S = np.array([[0]], dtype=np.uint8)
+    X = np.array([[0, 1]], dtype=np.uint8)
+    loss, _, _, app = oracle.nms_loss_grad(H, 1, L, S, X, 1, 1.0, 0.0)
+    assert np.array_equal(app[0], [1.0, 1.0])
+    hand = 0.5 * (math.log(1.0 + math.exp(-1.0)) + math.log(1.0 + math.exp(1.0)))
+    assert abs(loss - hand) <= 1e-15, (loss, hand)
 
 
 # --------------------------------------------------- paper table arithmetic --

@@ -16,6 +16,18 @@ APP_TOL = 1e-3   # |a - o| <= APP_TOL * max(|o|, 1)
 FP16_EXTRA = 2.0 * 2.0 ** -10 * 32.0
 
 
+def precision_bound(case: str) -> dict:
+    """Allowances of a reduced-precision message mode (binary16, e4m3) for
+    `case`, written by tests/golden/make_precision_bounds.py from an
+    oracle-only perturbation study: bound_mean_frac / bound_max_frac (APPs
+    outside the float32 tolerance, mean over frames / worst frame, as
+    fractions of n) and bound_max_rel (largest |a - o| / max(|o|, 1))."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "precision_bounds.json")
+    return json.load(open(path))["cases"][case]
+
+
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()

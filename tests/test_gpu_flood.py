@@ -8,7 +8,7 @@ import pytest
 import oracle
 from paper_2004_09084_amd import qcmet as Q
 from paper_2004_09084_amd import workload as W
-from tests.gpu_util import FP16_EXTRA, assert_tiered, compare, gpu_decode, say, to_dev
+from tests.gpu_util import FP16_EXTRA, assert_tiered, compare, gpu_decode, precision_bound, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -33,9 +33,11 @@ def test_flood_fp16_messages_match_oracle(T):
     hard, app, fl = gpu_decode(wl.shifts, SMALL.Z, wl.llr, wl.s, T, flags=FLOOD | Q.QM_MSG_FP16)
     appo, hardo, flo, _ = oracle.decode_flood(wl.shifts, SMALL.Z, wl.llr, wl.s, T, fp16_messages=True)
     rows = compare(app, hard, fl, appo, hardo, flo, extra=FP16_EXTRA)
+    b = precision_bound(f"fp16_flooding_T{T}")   # tests/golden/make_precision_bounds.py
     for r in rows:
         assert r["app_viol"] == 0 and r["bits_diff_confident"] == 0 and r["flag_o"] == r["flag_g"], r
-        assert r["strict_viol"] <= 1e-2 * SMALL.n, r
+        assert r["strict_viol"] <= b["bound_max_frac"] * SMALL.n, (r, b)
+        assert r["max_rel"] <= b["bound_max_rel"], (r, b)
 
 
 def test_flood_converging_frames():

@@ -9,7 +9,7 @@ import pytest
 import oracle
 from paper_2004_09084_amd import qcmet as Q
 from paper_2004_09084_amd import workload as W
-from tests.gpu_util import APP_TOL, FP16_EXTRA, assert_tiered, compare, gpu_decode, say, to_dev
+from tests.gpu_util import APP_TOL, FP16_EXTRA, assert_tiered, compare, gpu_decode, precision_bound, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -123,13 +123,15 @@ def test_fp16_messages_match_oracle_binary16_mode(T):
     appo, hardo, flo, _ = oracle.decode_sp(wl.shifts, SMALL.Z, wl.llr, wl.s, T, fp16_messages=True)
     rows = compare(app, hard, fl, appo, hardo, flo, extra=FP16_EXTRA)
     say(f"fp16 T={T}", rows)
+    # float32 and FP64 messages straddle a binary16 rounding boundary now and
+    # then; how many APPs that moves outside the float32 tolerance, and how
+    # far, is bounded by the oracle-only study in
+    # tests/golden/make_precision_bounds.py
+    b = precision_bound(f"fp16_layered_T{T}")
     for r in rows:
         assert r["app_viol"] == 0 and r["bits_diff_confident"] == 0, r
-        # rounding-boundary disagreements are rare: about 11k messages per
-        # frame and sweep, each with a ~1e-3 chance that the float32 and FP64
-        # values straddle a binary16 boundary; allow 1% of the APPs to sit
-        # outside the float32 tolerance (all stay within FP16_EXTRA)
-        assert r["strict_viol"] <= 1e-2 * SMALL.n, r
+        assert r["strict_viol"] <= b["bound_max_frac"] * SMALL.n, (r, b)
+        assert r["max_rel"] <= b["bound_max_rel"], (r, b)
 
 
 def test_fp16_messages_converging_frames():

@@ -7,7 +7,12 @@ Calls only the oracle and the seeded workload generator.  Stored per case:
 flag, hard-decision errors against the truth, a SHA-256 of the hard
 decisions, and the hard bits and APP values at 4096 sampled positions.
 
-    python tests/golden/make_fullsize_golden.py   (about 15 minutes on 8 cores)
+    python tests/golden/make_fullsize_golden.py            (all cases; about 25 minutes on 8 cores)
+    python tests/golden/make_fullsize_golden.py CASE ...   (only these; the others are kept)
+
+A case whose name ends in _fp16 decodes in the oracle's binary16-message
+mode.  The SNRs of the converging cases sit on each code's waterfall, where
+some frames reach a valid word and others do not.
 """
 import concurrent.futures as cf
 import hashlib
@@ -32,6 +37,9 @@ CASES = [
     ("r0.05_T200", W.RATE005, None, (0, 77), 200),
     ("r0.02_T200", W.RATE002, None, (0, 77), 200),
     ("r0.1_snr0.5_T60", W.RATE01, 0.5, (3, 100), 60),
+    ("r0.05_snr0.2_T200", W.RATE005, 0.2, (0, 4), 200),
+    ("r0.02_snr0.12_T200", W.RATE002, 0.12, (0, 2), 200),
+    ("r0.1_snr0.5_T60_fp16", W.RATE01, 0.5, (1, 2), 60),
 ]
 
 
@@ -49,7 +57,8 @@ def run_case(case):
         X.append(x); L.append(l); S.append(s)
     X, L, S = np.array(X), np.array(L), np.array(S)
     t0 = time.time()
-    app, hard, flags, _ = oracle.decode_sp(H, spec.Z, L, S, T, threads=len(frames))
+    app, hard, flags, _ = oracle.decode_sp(H, spec.Z, L, S, T, threads=len(frames),
+                                           fp16_messages=name.endswith("_fp16"))
     pos = positions(spec.n)
     res = {}
     for i, f in enumerate(frames):
@@ -66,9 +75,17 @@ def run_case(case):
 
 
 def main():
+    only = set(sys.argv[1:])
+    unknown = only - {c[0] for c in CASES}
+    if unknown:
+        raise SystemExit(f"unknown cases: {sorted(unknown)}")
+    cases = [c for c in CASES if not only or c[0] in only]
     out = {}
-    with cf.ThreadPoolExecutor(max_workers=len(CASES)) as ex:
-        for r in ex.map(run_case, CASES):
+    if only and os.path.exists(OUT):
+        old = np.load(OUT)
+        out = {k: old[k] for k in old.files if k.split("/")[0] not in only}
+    with cf.ThreadPoolExecutor(max_workers=len(cases)) as ex:
+        for r in ex.map(run_case, cases):
             out.update(r)
     np.savez_compressed(OUT, **out)
     print("wrote", OUT, os.path.getsize(OUT), "bytes")

@@ -13,7 +13,7 @@ import pytest
 import oracle
 from paper_2004_09084_amd import qcmet as Q
 from paper_2004_09084_amd import workload as W
-from tests.gpu_util import APP_TOL, compare, say, to_dev
+from tests.gpu_util import APP_TOL, FP16_EXTRA, compare, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -22,11 +22,11 @@ SPECS = {"r0.1": W.RATE01, "r0.05": W.RATE005, "r0.02": W.RATE002}
 F = 128
 
 
-def _decode(spec, snr, T):
+def _decode(spec, snr, T, flags=0):
     import torch
     wl = W.build(spec, F, graph_seed=0, frame_seed=0, snr=snr)
     code = Q.Code(wl.shifts, spec.Z)
-    dec = Q.Decoder([code], [F])
+    dec = Q.Decoder([code], [F], flags=flags)
     hard, app, fl = dec.decode(to_dev(wl.llr), to_dev(wl.s), T)
     torch.cuda.synchronize()
     out = hard.cpu().numpy().reshape(F, -1), app.cpu().numpy().reshape(F, -1), fl.cpu().numpy()
@@ -63,8 +63,10 @@ def test_fullsize_against_stored_oracle(case):
     frames = [int(f) for f in g[f"{case}/meta"][3:]]
     spec = SPECS[case.split("_")[0]]
     assert int(Z) == spec.Z
+    fp16 = case.endswith("_fp16")
     say(f"{case}: SNR {snr} T {int(T)} frames {frames}")
-    wl, (hard, app, fl) = _decode(spec, float(snr), int(T))
+    wl, (hard, app, fl) = _decode(spec, float(snr), int(T), flags=Q.QM_MSG_FP16 if fp16 else 0)
+    extra = FP16_EXTRA if fp16 else 0.0
     for f in frames:
         p = f"{case}/f{f}/"
         flag_o = int(g[p + "flag"])
@@ -72,7 +74,7 @@ def test_fullsize_against_stored_oracle(case):
         same_hash = hashlib.sha256(hard[f].tobytes()).digest() == g[p + "hard_sha256"].tobytes()
         o = g[p + "app_at"]
         a = app[f][pos].astype(np.float64)
-        viol = int((np.abs(a - o) > APP_TOL * np.maximum(np.abs(o), 1.0)).sum())
+        viol = int((np.abs(a - o) > APP_TOL * np.maximum(np.abs(o), 1.0) + extra).sum())
         bits_at = int((hard[f][pos] != g[p + "hard_at"]).sum())
         errors_g = int((hard[f] != wl.x[f]).sum())
         say(dict(frame=f, flag_o=flag_o, flag_g=int(fl[f]), errors_o=int(g[p + "errors"]), errors_g=errors_g,
@@ -82,6 +84,86 @@ def test_fullsize_against_stored_oracle(case):
         # T2: frames the oracle decodes to a valid word are bit-identical
         if flag_o:
             assert same_hash and viol == 0
+
+
+@pytest.mark.parametrize("snr,sweeps", [(0.161, (1, 2)), (0.3, (5,))])
+def test_fullsize_minsum_first_sweeps(snr, sweeps):
+    # the learned decoder's forward (normalized/offset min-sum, random
+    # weights) over the 128-frame rate-0.1 batch against the oracle on
+    # sampled frames, decoded alone.  At SNR 0.161 min-sum amplifies
+    # rounding differences about 8x per sweep: in the oracle alone, LLRs
+    # moved by 2e-6 relative move the APPs by up to 9e-5, 7e-4, 4.9e-3 and
+    # 0.25 (relative) after 1, 2, 3 and 5 sweeps, so float32 against FP64
+    # is held to 1e-3 for two sweeps there, and for five at SNR 0.3, where
+    # the sweeps settle instead
+    import torch
+    spec = W.RATE01
+    frames = [0, 77]
+    wl = W.build(spec, F, graph_seed=0, frame_seed=0, snr=snr)
+    code = Q.Code(wl.shifts, spec.Z)
+    dec = Q.Decoder([code], [F])
+    dec.nms_bind(max(sweeps), train=False)
+    L, S = to_dev(wl.llr), to_dev(wl.s)
+    rng = np.random.default_rng(5)
+    for T in sweeps:
+        w = np.stack([rng.uniform(0.6, 1.0, (T, spec.mb, 2)), rng.uniform(0.0, 0.3, (T, spec.mb, 2))],
+                     axis=-1).astype(np.float32)
+        say(f"full-size min-sum SNR {snr} T={T}")
+        hard, app, fl, it = dec.nms_decode(to_dev(w), L, S, T)
+        torch.cuda.synchronize()
+        hard = hard.cpu().numpy().reshape(F, -1)
+        app = app.cpu().numpy().reshape(F, -1)
+        fl = fl.cpu().numpy()
+        appo, hardo, flo, _ = oracle.nms_decode(wl.shifts, spec.Z, wl.llr[frames], wl.s[frames], T,
+                                                w[..., 0].astype(np.float64), w[..., 1].astype(np.float64),
+                                                threads=2)
+        rows = compare(app[frames], hard[frames], fl[frames], appo, hardo, flo)
+        say(rows)
+        for r in rows:
+            assert r["app_viol"] == 0 and r["bits_diff_confident"] == 0 and r["flag_o"] == r["flag_g"], r
+    del dec
+    torch.cuda.empty_cache()
+
+
+def test_fullsize_mixed_fp16_batch():
+    # the mixed batch (64 rate-0.1 + 32 rate-0.05 + 32 rate-0.02 frames,
+    # frame seed 1) with binary16 messages: after one and two sweeps each
+    # code's first frame against the oracle's binary16 mode, and after 200
+    # sweeps each code's slice bit-identical to a decoder of that code alone
+    import torch
+    specs, Fs = [W.RATE01, W.RATE005, W.RATE002], [64, 32, 32]
+    wls = [W.build(s, Fc, graph_seed=0, frame_seed=1) for s, Fc in zip(specs, Fs)]
+    codes = [Q.Code(w.shifts, s.Z) for w, s in zip(wls, specs)]
+    L = to_dev(np.concatenate([w.llr.reshape(-1) for w in wls]))
+    S = to_dev(np.concatenate([w.s.reshape(-1) for w in wls]))
+    dec = Q.Decoder(codes, Fs, flags=Q.QM_MSG_FP16)
+    for T in (1, 2):
+        say(f"mixed FP16 T={T}")
+        h, a, f = (x.cpu().numpy() for x in dec.decode(L, S, T))
+        on = of = 0
+        for w, s, Fc in zip(wls, specs, Fs):
+            appo, hardo, flo, _ = oracle.decode_sp(w.shifts, s.Z, w.llr[:1], w.s[:1], T, fp16_messages=True)
+            rows = compare(a[on:on + s.n][None], h[on:on + s.n][None], f[of:of + 1], appo, hardo, flo,
+                           extra=FP16_EXTRA)
+            say(s.name, rows)
+            for r in rows:
+                assert r["app_viol"] == 0 and r["bits_diff_confident"] == 0 and r["flag_o"] == r["flag_g"], r
+            on += Fc * s.n
+            of += Fc
+    say("mixed FP16 T=200 against single-code decoders")
+    h, a, f = (x.cpu().numpy() for x in dec.decode(L, S, 200))
+    del dec
+    on = of = 0
+    for w, s, Fc, c in zip(wls, specs, Fs, codes):
+        one = Q.Decoder([c], [Fc], flags=Q.QM_MSG_FP16)
+        h1, a1, f1 = (x.cpu().numpy() for x in one.decode(to_dev(w.llr), to_dev(w.s), 200))
+        del one
+        assert np.array_equal(h[on:on + Fc * s.n], h1), s.name
+        assert np.array_equal(a[on:on + Fc * s.n].view(np.uint32), a1.view(np.uint32)), s.name
+        assert np.array_equal(f[of:of + Fc], f1), s.name
+        on += Fc * s.n
+        of += Fc
+    torch.cuda.empty_cache()
 
 
 def test_default_frame_batches_at_1024_frames():

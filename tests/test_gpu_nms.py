@@ -264,6 +264,31 @@ def _plain_weights(T):
     return w
 
 
+def test_training_over_every_sweep_lowers_the_bit_error_rate():
+    # what the learned weights gain over plain min-sum in decoded bits: a
+    # short run of the default objective (BCE of every sweep's APPs, one-sweep
+    # backprop window) on the small rate-0.1 code at SNR 0.161 / 0.15, then
+    # min-sum alone on frames of another seed at SNR 0.161.  The FP64 oracle
+    # running the same recipe (its own frames, 20 sweeps) gets BER 0.096
+    # against 0.351 for plain min-sum and 0.068 for 40 sum-product sweeps.
+    import torch
+    from paper_2004_09084_amd import train_nms as TN
+    H = W.make_code(SMALL, 0)
+    T, F = 20, 64
+    w, hist, _, clamped = TN.train(SMALL, H, steps=150, frames=16, T=T, lr=1e-2, seed=5, log_every=1000,
+                                   log=lambda *_: None, every_sweep=True, window=1)
+    assert clamped == 0
+    wl = W.build(SMALL, F, snr=0.161, frame_seed=11)
+    code, dec = _dec(H, SMALL.Z, F, T)
+    ber = {}
+    for name, wt in (("trained", w), ("plain", torch.from_numpy(_plain_weights(T)).cuda())):
+        hard, _, _, _ = dec.nms_decode(wt.contiguous(), to_dev(wl.llr), to_dev(wl.s), T)
+        torch.cuda.synchronize()
+        ber[name] = float((hard.cpu().numpy().reshape(F, -1) != wl.x).mean())
+    say("min-sum BER at SNR 0.161: trained", ber["trained"], "plain", ber["plain"])
+    assert ber["trained"] < 0.5 * ber["plain"]
+
+
 def test_nms_requires_one_float32_code():
     H = W.make_code(SMALL, 0)
     code = Q.Code(H, SMALL.Z)

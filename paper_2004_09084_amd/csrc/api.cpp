@@ -375,7 +375,7 @@ struct ProfScope {
 };
 
 // early: an early-terminating decode, whose layer kernel forms K itself
-int enqueue_init(qm_decoder &d, const float *llr, const uint8_t *syn, hipStream_t st, bool early = false) {
+int enqueue_init(qm_decoder &d, const float *llr, const uint8_t *syn, hipStream_t st) {
     size_t on = 0, om = 0;
     const size_t msg = msg_bytes(d);
     for (Slot &s : d.slots) {
@@ -385,7 +385,7 @@ int enqueue_init(qm_decoder &d, const float *llr, const uint8_t *syn, hipStream_
         const SlotBufs b = slot_bufs(d, s);
         QM_HIP(qm_launch_to_tiles_f32(llr + on, b.A, s.F, s.n, g.ft_log2, g.ntiles, st));
         QM_HIP(qm_launch_to_tiles_u8(syn + om, b.S, s.F, s.m, g.ft_log2, g.ntiles, st));
-        if (!early) QM_HIP(qm_launch_kappa(b.A, b.S, b.K, b.rows, c.mb, g, st));
+        QM_HIP(qm_launch_kappa(b.A, b.S, b.K, b.rows, c.mb, g, st));
         const size_t rbytes = align_up((size_t)s.Fpad * c.nent1 * c.Z * msg);
         QM_HIP(qm_launch_fill_u32(reinterpret_cast<uint32_t *>(b.R), 0u, rbytes / 4, st));
         QM_HIP(qm_launch_fill_u32(b.fail, 0u, (size_t)s.Fpad, st));
@@ -900,7 +900,7 @@ int enqueue_early_slot(qm_decoder &d, Slot &s, int32_t T, uint8_t *hard, float *
     // bounds it); grids cover those tiles alone.
     TileGeom g = g0;
     int Fpad = s.Fpad;
-    float *A = b.A, *Ad = Ad0;
+    float *A = b.A, *Ad = Ad0, *K = b.K;
     char *R = static_cast<char *>(b.R);
     uint8_t *S = b.S;
     int region = 0;  // tile of the original layout that holds the state once narrowed
@@ -920,13 +920,13 @@ int enqueue_early_slot(qm_decoder &d, Slot &s, int32_t T, uint8_t *hard, float *
     QM_HIP(qm_launch_pack_signs(Ad, Pd, s.m, la.fpl, g, st));
     QM_HIP(qm_launch_pack_syndrome(S, PS, nullptr, 0, la.fpl, g, st));
     auto test = [&](int t) -> int {
-        // the per-node state of a decoding frame (K is not used: the layer
-        // kernel forms it from Ad and the syndrome bits)
-        const CompactArray arr[] = {{A, s.n, 4}, {R, nR, (int32_t)msg}, {S, s.m, 1}, {Ad, s.m, 4}};
+        // the per-node state of a decoding frame
+        const CompactArray arr[] = {{A, s.n, 4}, {R, nR, (int32_t)msg}, {S, s.m, 1}, {Ad, s.m, 4}, {K, s.m, 4}};
         const int narr = (int)(sizeof(arr) / sizeof(arr[0]));
         QM_HIP(qm_launch_pack_cols(A, PA, cols1, (int)s.cols1.size(), ctl, la.fpl, g, st));
         QM_HIP(qm_launch_syndrome_packed(PA, Pd, PS, b.rows, c.mb, b.fail, ctl, la.fpl, g, st));
         QM_HIP(qm_launch_et_plan(b.fail, act, tmask, map, perm, it, emit, flags, s.F, ctl, Fpad, g.ft_log2, t, 0, st));
+        QM_HIP(qm_launch_emit_d1(A, Ad, emit, ctl, it, b.rows, c.mb, msgk, g, st));
         QM_HIP(qm_launch_emit(A, emit, ctl, app, hard, g, st));
         if (g.ntiles > 1) {  // with one tile left no compaction can be planned
             QM_HIP(qm_launch_compact(arr, narr, perm, ctl, g.ft_log2, st));
@@ -943,21 +943,25 @@ int enqueue_early_slot(qm_decoder &d, Slot &s, int32_t T, uint8_t *hard, float *
         char *R2 = static_cast<char *>(b.R) + (int64_t)region * (nR << g0.ft_log2) * (int64_t)msg;
         uint8_t *S2 = b.S + (int64_t)region * (s.m << g0.ft_log2);
         float *Ad2 = Ad0 + (int64_t)region * (s.m << g0.ft_log2);
+        float *K2 = b.K + (int64_t)region * (s.m << g0.ft_log2);
         QM_HIP(qm_launch_et_narrow_plan(act, tmask, map, perm, ctl, g.ft_log2, ftl, st));
         QM_HIP(qm_launch_narrow(A, A2, perm, s.n, 4, g.ft_log2, ftl, st));
         QM_HIP(qm_launch_narrow(R, R2, perm, nR, (int)msg, g.ft_log2, ftl, st));
         QM_HIP(qm_launch_narrow(S, S2, perm, s.m, 1, g.ft_log2, ftl, st));
         QM_HIP(qm_launch_narrow(Ad, Ad2, perm, s.m, 4, g.ft_log2, ftl, st));
+        QM_HIP(qm_launch_narrow(K, K2, perm, s.m, 4, g.ft_log2, ftl, st));
         A = A2;
         R = R2;
         S = S2;
         Ad = Ad2;
+        K = K2;
         g.ft_log2 = ftl;
         g.ntiles = 1;
         Fpad = 1 << ftl;
         la.A = A;
         la.R = R;
         la.Ad = Ad;
+        la.K = K;
         la.ft_log2 = ftl;
         la.fpl = std::min(la.fpl, Fpad);
         la.chunks = ((c.Z << ftl) / la.fpl + d.tun.block - 1) / d.tun.block;
@@ -1018,6 +1022,7 @@ int enqueue_early_slot(qm_decoder &d, Slot &s, int32_t T, uint8_t *hard, float *
     }
     // frames still decoding ran all T sweeps and failed the last test
     QM_HIP(qm_launch_et_plan(b.fail, act, tmask, map, perm, it, emit, flags, s.F, ctl, Fpad, g.ft_log2, T, 1, st));
+    QM_HIP(qm_launch_emit_d1(A, Ad, emit, ctl, it, b.rows, c.mb, msgk, g, st));
     QM_HIP(qm_launch_emit(A, emit, ctl, app, hard, g, st));
     if (iters_out && s.F > 0)
         QM_HIP(hipMemcpyAsync(iters_out, it, (size_t)s.F * 4, hipMemcpyDeviceToDevice, st));
@@ -1569,7 +1574,7 @@ int qm_decode_early(qm_decoder *d, const float *llr, const uint8_t *syn, int32_t
         QM_HIP(hipEventCreateWithFlags(&d->poll_ev[0], hipEventDisableTiming));
         QM_HIP(hipEventCreateWithFlags(&d->poll_ev[1], hipEventDisableTiming));
     }
-    int rc = enqueue_init(*d, llr, syn, st, true);
+    int rc = enqueue_init(*d, llr, syn, st);
     if (rc != QM_OK) return rc;
     size_t on = 0, of = 0;
     for (Slot &s : d->slots) {

@@ -180,7 +180,9 @@ __global__ void __launch_bounds__(256) k_syndrome(const float *__restrict__ A, c
         }
     }
     __syncthreads();
-    if (tid < FT && lf[tid]) atomicOr(&fail[tile * FT + tid], 1u);
+    // skip the atomic where the word already reads 1 (see k_syndrome_packed)
+    if (tid < FT && lf[tid] && reinterpret_cast<volatile uint32_t *>(fail)[tile * FT + tid] == 0u)
+        atomicOr(&fail[tile * FT + tid], 1u);
 }
 
 // Variable half of a flooding iteration: APP = LLR + the messages of the
@@ -261,26 +263,54 @@ __global__ void __launch_bounds__(256) k_syndrome_packed(const uint8_t *__restri
     __syncthreads();
     const RowDesc *rd = rows + rs;
     const int k = chunk * (int)blockDim.x + tid;
+    uint64_t par = 0;
     if (k < Z) {
         const int esz = qm_pack_bytes(ftl);
         const int64_t chk = (int64_t)rd->row * Z + k;
-        uint64_t par = load_packed(PS + (int64_t)tile * m * esz, chk, esz);
+        par = load_packed(PS + (int64_t)tile * m * esz, chk, esz);
         const uint8_t *pa = PA + (int64_t)tile * n * esz;
-        for (int j = 0; j < rd->d; ++j) {
+        // the first 8 entries' loads are all issued before any is used (an
+        // entry past the row's degree re-reads entry 0 and is dropped), so
+        // they are in flight together; wider rows take the rest in a loop
+        const int d = rd->d;
+        uint64_t w[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int jj = j < d ? j : 0;
+            int v = k + rd->shift[jj];
+            v = v >= Z ? v - Z : v;
+            w[j] = load_packed(pa, (int64_t)rd->col[jj] * Z + v, esz);
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) par ^= j < d ? w[j] : 0ull;
+        for (int j = 8; j < d; ++j) {
             int v = k + rd->shift[j];
             v = v >= Z ? v - Z : v;
             par ^= load_packed(pa, (int64_t)rd->col[j] * Z + v, esz);
         }
         if (rd->d1col >= 0) par ^= load_packed(Pd + (int64_t)tile * m * esz, chk, esz);
-        if (par) {
-            atomicOr(&lm[0], (uint32_t)par);
-            atomicOr(&lm[1], (uint32_t)(par >> 32));
-        }
+    }
+    // OR over the wave first (most checks fail while frames decode, so a
+    // per-lane LDS atomic would serialise), then one atomic per wave
+    uint32_t lo = (uint32_t)par, hi = (uint32_t)(par >> 32);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        lo |= __shfl_xor(lo, o, 64);
+        hi |= __shfl_xor(hi, o, 64);
+    }
+    if ((tid & 63) == 0 && (lo | hi)) {
+        atomicOr(&lm[0], lo);
+        atomicOr(&lm[1], hi);
     }
     __syncthreads();
     if (tid < FT) {
+        // every workgroup of a tile reports to the same FT words, and while
+        // frames decode nearly all of them fail: skip the atomic when the
+        // word already reads 1 (it only ever goes from 0 to 1 in a test)
         const int bit = qm_pack_bit(tid, ftl, fpl);
-        if ((bit < 32 ? lm[0] >> bit : lm[1] >> (bit - 32)) & 1u) atomicOr(&fail[tile * FT + tid], 1u);
+        if (((bit < 32 ? lm[0] >> bit : lm[1] >> (bit - 32)) & 1u) &&
+            reinterpret_cast<volatile uint32_t *>(fail)[tile * FT + tid] == 0u)
+            atomicOr(&fail[tile * FT + tid], 1u);
     }
 }
 
@@ -327,9 +357,9 @@ __device__ __forceinline__ void pack_wave(const T *__restrict__ X, uint8_t *__re
     }
 }
 
-// first node of this wave's kPackU passes
-__device__ __forceinline__ int64_t pack_node0(int ftl) {
-    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+// first node of this wave's kPackU passes in block bx
+__device__ __forceinline__ int64_t pack_node0(int ftl, int64_t bx = -1) {
+    const int64_t wave = (bx < 0 ? (int64_t)blockIdx.x : bx) * (blockDim.x >> 6) + (threadIdx.x >> 6);
     return wave * kPackU * (64 >> ftl);
 }
 
@@ -360,8 +390,13 @@ __global__ void __launch_bounds__(256) k_pack_syndrome(const uint8_t *__restrict
                                                        int after_compaction) {
     const int64_t tile = blockIdx.y;
     if (ctl && (tile >= ctl[1] || (after_compaction && ctl[2] == 0))) return;
-    pack_wave<kPackU, uint8_t, LowBit>(Sil + ((tile * m) << ftl), PS + tile * m * qm_pack_bytes(ftl), pack_node0(ftl),
-                                       m, ftl, fpl);
+    // grid-stride over the blocks of the tile: the call after every test
+    // (which repacks only when a compaction moved frames) launches few
+    const int64_t per_block = 4LL * kPackU * (64 >> ftl);
+    const int64_t nb = (m + per_block - 1) / per_block;
+    for (int64_t bx = blockIdx.x; bx < nb; bx += gridDim.x)
+        pack_wave<kPackU, uint8_t, LowBit>(Sil + ((tile * m) << ftl), PS + tile * m * qm_pack_bytes(ftl),
+                                           pack_node0(ftl, bx), m, ftl, fpl);
 }
 
 // ---------------------------------------------------------------------------
@@ -573,6 +608,47 @@ __global__ void __launch_bounds__(256) k_emit(const float *__restrict__ A, const
                 hard[(int64_t)f * N + v] = x < 0.0f ? 1 : 0;
             }
         }
+    }
+}
+
+// Degree-1 APPs of the frames that stopped in the last planning call, before
+// k_emit copies them out.  While a frame decodes, A's slot of each degree-1
+// variable holds clip(S) with the sign of r_d (S the check's Phi-sum over its
+// degree>=2 edges in the frame's last sweep; k_layer_sp_et); here it becomes
+// APP_d = LLR_d + r_d, |r_d| = Phi(clip S) rounded to the message type: the
+// arithmetic the fixed-sweep layer kernel applies in its last sweep, so the
+// outputs are the same bits.  Frames that stop before any sweep keep the
+// channel LLR.  Grid-stride over (tile, row, chunk of 256 (check, frame)
+// pairs) items; a lane works only for a listed slot, and a call that lists
+// no slot (most of them) exits at once.
+template <typename MsgT>
+__global__ void __launch_bounds__(256) k_emit_d1(float *__restrict__ A, const float *__restrict__ Ad,
+                                                 const int32_t *__restrict__ emit, const int32_t *ctl,
+                                                 const int32_t *__restrict__ iters, const RowDesc *rows, int Z,
+                                                 int ftl, int ntiles, int chunks, int mb, int64_t strideA,
+                                                 int64_t strideM) {
+    if (ctl[4] == 0) return;
+    const int64_t items = (int64_t)ntiles * chunks * mb;
+    for (int64_t b = blockIdx.x; b < items; b += gridDim.x) {
+        const int tile = (int)(b % ntiles);
+        const int64_t rest = b / ntiles;
+        const int chunk = (int)(rest % chunks);
+        const int rs = (int)(rest / chunks);
+        const int idx = chunk * (int)blockDim.x + (int)threadIdx.x;
+        if (idx >= (Z << ftl)) continue;
+        const int k = idx >> ftl;
+        const int fl = idx & ((1 << ftl) - 1);
+        const int f = emit[(tile << ftl) + fl];
+        if (f < 0 || iters[f] == 0) continue;
+        ConstRowDesc *rd = as_const(rows + rs);
+        if (rd->d1col < 0) continue;
+        int v = k + rd->d1shift;
+        v = v >= Z ? v - Z : v;
+        const int64_t oa = (int64_t)tile * strideA + (((int64_t)rd->d1col * Z + v) << ftl) + fl;
+        const int64_t od = (int64_t)tile * strideM + (((int64_t)rd->row * Z + k) << ftl) + fl;
+        const float sd = A[oa];
+        const float mag = qm_phi(qm_clip(fabsf(sd)));
+        A[oa] = Ad[od] + MsgIO<MsgT>::round(sd < 0.0f ? -mag : mag);
     }
 }
 
@@ -874,7 +950,8 @@ hipError_t qm_launch_pack_syndrome(const uint8_t *Sil, uint8_t *PS, const int32_
                                    const TileGeom &g, hipStream_t s) {
     if ((1 << g.ft_log2) > 64 || fpl < 1 || fpl > (1 << g.ft_log2)) return hipErrorInvalidValue;
     if (g.m == 0 || g.ntiles == 0) return hipSuccess;
-    dim3 grid(pack_blocks(g.m, g.ft_log2), (unsigned)g.ntiles);
+    const unsigned bx = after_compaction ? std::min(pack_blocks(g.m, g.ft_log2), 512u) : pack_blocks(g.m, g.ft_log2);
+    dim3 grid(bx, (unsigned)g.ntiles);
     hipLaunchKernelGGL(k_pack_syndrome, grid, dim3(256), 0, s, Sil, PS, g.m, g.ft_log2, fpl, ctl, after_compaction);
     return hipGetLastError();
 }
@@ -896,6 +973,27 @@ hipError_t qm_launch_et_plan(uint32_t *fail, uint32_t *act, uint64_t *tmask, int
         return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_et_plan, dim3(1), dim3(256), 0, s, fail, act, tmask, map, perm, iters, emit, flags, F, ctl,
                        Fpad, ft_log2, t, final_pass);
+    return hipGetLastError();
+}
+
+hipError_t qm_launch_emit_d1(float *A, const float *Ad, const int32_t *emit, const int32_t *ctl, const int32_t *iters,
+                            const RowDesc *rows, int mb, int msgk, const TileGeom &g, hipStream_t s) {
+    if ((1 << g.ft_log2) > 64) return hipErrorInvalidValue;
+    const int chunks = ((g.Z << g.ft_log2) + 255) / 256;
+    const int64_t items = (int64_t)g.ntiles * mb * chunks;
+    if (items == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)std::min<int64_t>(items, 2048);
+    const int64_t sA = (int64_t)g.n << g.ft_log2, sM = (int64_t)g.m << g.ft_log2;
+#define QM_ED(T)                                                                                                   \
+    hipLaunchKernelGGL(k_emit_d1<T>, dim3(blocks), dim3(256), 0, s, A, Ad, emit, ctl, iters, rows, g.Z, g.ft_log2, \
+                       g.ntiles, chunks, mb, sA, sM)
+    switch (msgk) {
+        case QM_MSGK_F32: QM_ED(float); break;
+        case QM_MSGK_F16: QM_ED(_Float16); break;
+        case QM_MSGK_F8: QM_ED(Fp8Msg); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef QM_ED
     return hipGetLastError();
 }
 

@@ -80,6 +80,83 @@ __device__ __forceinline__ void store_live(__amdgpu_buffer_rsrc_t r, uint32_t vo
     }
 }
 
+// Relative half-width of the band around |K| = clip(S) inside which the
+// degree-1 hard decision of an early-terminating sweep takes the exact sum
+// (d1_early), per message type.  Phi is decreasing and its own inverse,
+// so |LLR_d| > |r_d| = Phi(clip S) exactly when Phi(clip|LLR_d|) < clip S.
+// The float32 Phi is within eps = 1.5e-6 relative of Phi, the stored
+// message within rho of the float32 one (0 for float32, 2^-11 for binary16
+// normals), and ln Phi falls with ln x at a rate g(x) = x / (sinh(x) Phi(x))
+// >= 1/29.9 on the clip interval (smallest at Phi(30)); a band of
+// eps + 29.9 (eps + rho) therefore separates the two cases.  float32:
+// 4.6e-5, taken as 2^-12; binary16: 0.015, taken as 2^-5, and only where
+// the message stays a binary16 normal (clip S <= 9: Phi(9) = 2.5e-4 >
+// 2^-14).  8-bit messages (rho = 1/16) always take the exact sum.
+template <typename MsgT>
+struct D1Band {
+    static constexpr bool fast = false;
+    static constexpr float lo = 0.0f, hi = 0.0f, smax = 0.0f;
+};
+template <>
+struct D1Band<float> {
+    static constexpr bool fast = true;
+    static constexpr float lo = 1.0f - 0x1p-12f, hi = 1.0f + 0x1p-12f, smax = 1e30f;
+};
+template <>
+struct D1Band<_Float16> {
+    static constexpr bool fast = true;
+    static constexpr float lo = 1.0f - 0x1p-5f, hi = 1.0f + 0x1p-5f, smax = 9.0f;
+};
+
+// Degree-1 variable of an early-terminating sweep: every sweep may be a
+// frame's last, so every sweep needs the hard decision [APP_d < 0] of
+// APP_d = LLR_d + r_d (|r_d| = Phi(clip S), S the check's Phi-sum over its
+// degree>=2 edges; sign(r_d) = s ^ xor_j [q_j < 0]).  Outside the band of
+// D1Band the comparison of |K| with clip(S) decides it (no Phi); inside,
+// the exact sum is formed from LLR_d (kept per check in Ad).  The APP
+// itself is formed only for the frames that stop (qm_launch_emit_d1, with
+// the same arithmetic): A's degree-1 slot keeps clip(S) with r_d's sign.
+template <typename MsgT, int FPL, bool MASKED>
+__device__ __forceinline__ void d1_early(const LaneCtx &c, ConstRowDesc *rd, const EtLane<FPL> &et,
+                                         const float (&kap)[FPL], const bool (&neg)[FPL], const float (&acc)[FPL],
+                                         uint64_t sw, uint32_t row_so, uint32_t col_bytes) {
+    typedef MsgIO<MsgT> IO;
+    typedef D1Band<MsgT> B;
+    float sd[FPL], bits[FPL];
+    bool nd[FPL], exact[FPL];
+    bool any = false;
+#pragma unroll
+    for (int f = 0; f < FPL; ++f) {
+        const bool sb = ((sw >> ((f << et.lpl) + et.jl)) & 1ull) != 0ull;
+        const bool lneg = ((int32_t)__float_as_uint(kap[f]) < 0) != sb;  // [LLR_d < 0]
+        nd[f] = neg[f] != lneg;
+        const float mc = qm_clip(acc[f]);
+        const float a = fabsf(kap[f]);
+        sd[f] = nd[f] ? -mc : mc;
+        const bool ok = B::fast && mc <= B::smax;
+        const bool lam_wins = ok && a < mc * B::lo;
+        const bool msg_wins = ok && a > mc * B::hi;
+        bits[f] = (lam_wins ? lneg : nd[f]) ? -1.0f : 1.0f;
+        exact[f] = !(lam_wins || msg_wins);
+        any = any || exact[f];
+    }
+    if (any) {
+        float lam[FPL];
+        bload_f32<FPL>(et.rAd, c.node * 4u, row_so, lam);
+#pragma unroll
+        for (int f = 0; f < FPL; ++f) {
+            if (!exact[f]) continue;
+            const float mag = qm_phi(qm_clip(acc[f]));
+            const float out = lam[f] + IO::round(nd[f] ? -mag : mag);
+            bits[f] = out < 0.0f ? -1.0f : 1.0f;
+        }
+    }
+    const uint32_t off = shifted_off(c, rd->d1shift);
+    store_live<MsgIO<float>, FPL, 0, MASKED>(c.rA, off, (uint32_t)rd->d1col * col_bytes, sd, et);
+    const uint64_t w = group_signs<FPL>(bits, et.lpl);
+    if (et.leader) store_packed(et.Pd, (int64_t)rd->row * c.Z + c.k, et.esz, w);
+}
+
 // Update modes of the check kernel.
 constexpr int kLayered = 0;  // layered sweep (fixed iterations)
 constexpr int kEarly = 1;    // layered sweep with early termination (EtLane)
@@ -109,27 +186,14 @@ __device__ __forceinline__ void check_update(const LaneCtx &c, ConstRowDesc *rd,
     }
 
     // kap = K (|K| = Phi(clip|LLR_d|), sign s ^ [LLR_d < 0]; |K| = 0 and sign
-    // s without a degree-1 variable).  Early termination: every sweep may be
-    // a frame's last, so every sweep forms the degree-1 APPs in A, from the
-    // channel LLRs of the degree-1 variables kept per check in Ad; with
-    // those at hand K is formed here from them and the packed syndrome bits
-    // (the same arithmetic as the kernel that fills K) instead of being read.
-    // The Ad load is unconditional (Ad has an entry for every check), so no
-    // branch on the row waits for its descriptor before the first load.
+    // s without a degree-1 variable).  Early termination also reads the
+    // check's packed syndrome bits: with the sign of K they give the sign of
+    // LLR_d, which the degree-1 hard decision needs every sweep.
     float kap[FPL];
     float lam[FPL];
-    if constexpr (ET) {
-        bload_f32<FPL>(et.rAd, vo4, row_so, lam);
-        const uint64_t sw = load_packed(et.PS, (int64_t)rd->row * c.Z + c.k, et.esz);
-#pragma unroll
-        for (int f = 0; f < FPL; ++f) {
-            const uint32_t sb = (uint32_t)(sw >> ((f << et.lpl) + et.jl)) & 1u;
-            const float mag = d1col >= 0 ? qm_phi(qm_clip(fabsf(lam[f]))) : 0.0f;
-            kap[f] = with_sign(mag, sb ^ (uint32_t)(d1col >= 0 && lam[f] < 0.0f));
-        }
-    } else {
-        bload_f32<FPL, AUX>(c.rK, vo4, row_so, kap);
-    }
+    bload_f32<FPL, AUX>(c.rK, vo4, row_so, kap);
+    uint64_t sw = 0;
+    if constexpr (ET) sw = load_packed(et.PS, (int64_t)rd->row * c.Z + c.k, et.esz);
     // sign parities are per-lane booleans (lane masks in scalar registers)
     bool neg[FPL];
 #pragma unroll
@@ -180,11 +244,13 @@ __device__ __forceinline__ void check_update(const LaneCtx &c, ConstRowDesc *rd,
         if constexpr (MODE != kFlood) store_live<MsgIO<float>, FPL, 0, MASKED>(c.rA, aoff[j], col_so[j], an, et);
 
     }
-    if ((ET || last) && d1col >= 0) {
+    if constexpr (ET) {
+        if (d1col >= 0) d1_early<MsgT, FPL, MASKED>(c, rd, et, kap, neg, acc, sw, row_so, col_bytes);
+    } else if (last && d1col >= 0) {
         const uint32_t off = shifted_off(c, d1shift);
         const uint32_t so = (uint32_t)d1col * col_bytes;
         float out[FPL];
-        if constexpr (!ET) bload_f32<FPL>(c.rA, off, so, lam);
+        bload_f32<FPL>(c.rA, off, so, lam);
 #pragma unroll
         for (int f = 0; f < FPL; ++f) {
             // neg = s ^ [lam < 0] ^ xor_j [q_j < 0]; the degree-1 target
@@ -194,10 +260,6 @@ __device__ __forceinline__ void check_update(const LaneCtx &c, ConstRowDesc *rd,
             out[f] = lam[f] + IO::round(nd ? -mag : mag);
         }
         store_live<MsgIO<float>, FPL, 0, MASKED>(c.rA, off, so, out, et);
-        if constexpr (ET) {
-            const uint64_t w = group_signs<FPL>(out, et.lpl);
-            if (et.leader) store_packed(et.Pd, (int64_t)rd->row * c.Z + c.k, et.esz, w);
-        }
     }
 }
 
@@ -287,8 +349,17 @@ __global__ void __launch_bounds__(256) k_layer_sp(const LayerArgs a) {
 }
 
 // The same layer update for an early-terminating decode (see EtLane).
+// Its register budget is set per maximum degree: left to itself the
+// scheduler packs the degree-1 comparison's extra values into the widest
+// body and falls to 5 waves per SIMD at degree 5, which costs more than
+// the arithmetic the comparison saves.
+template <int MAXD>
+struct EtWaves {
+    static constexpr int v = MAXD <= 5 ? 8 : MAXD <= 8 ? 6 : 1;
+};
 template <typename MsgT, int MAXD, int FPL, int AUX>
-__global__ void __launch_bounds__(256) k_layer_sp_et(const LayerArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EtWaves<MAXD>::v)))
+k_layer_sp_et(const LayerArgs a) {
     layer_body<MsgT, MAXD, FPL, AUX, kEarly>(a, (int)blockIdx.x);
 }
 

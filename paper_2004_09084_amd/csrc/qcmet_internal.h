@@ -54,8 +54,10 @@ struct LayerArgs {
     int32_t last;             // 1 in the last sweep: also form the degree-1 APPs
     int64_t strideA, strideR, strideK;  // per-tile strides (elements)
     // early termination (null otherwise): every sweep forms the degree-1
-    // APPs in A, reading the channel LLRs of the degree-1 variables from Ad;
-    // frames whose tmask bit is 0 are left untouched; tiles at or past ctl[1] are
+    // hard decisions and keeps in A's degree-1 slots clip(S) with r_d's sign
+    // (the APP is formed when the frame stops), reading the channel LLRs of
+    // the degree-1 variables from Ad where the exact sum decides; frames
+    // whose tmask bit is 0 are left untouched; tiles at or past ctl[1] are
     // skipped, and the grid may cover fewer than ntiles tiles (any count
     // >= ctl[1])
     const float *Ad;          // [ntiles][m][FT] LLR of each check's degree-1 variable
@@ -63,8 +65,7 @@ struct LayerArgs {
     const int32_t *ctl;       // EtCtl
     uint8_t *Pd;              // [ntiles][m] hard decisions of the FT frames of each check's degree-1
                               // variable (bit = frame), max(FT, 8) bits each
-    const uint8_t *PS;        // [ntiles][m] syndrome bits, packed the same way (K is formed from
-                              // them and Ad; the K array is not read)
+    const uint8_t *PS;        // [ntiles][m] syndrome bits, packed the same way
     uint32_t shmem;           // dynamic LDS bytes requested per workgroup; the kernels do not use
                               // it, it only caps how many workgroups a compute unit holds
 };
@@ -206,6 +207,8 @@ hipError_t qm_launch_et_plan(uint32_t *fail, uint32_t *act, uint64_t *tmask, int
                              int t, int final_pass, hipStream_t s);
 // frame-major APPs and hard decisions of the frames the planning kernel
 // stopped (emit[slot] = frame or -1), from the first g.ntiles tiles
+hipError_t qm_launch_emit_d1(float *A, const float *Ad, const int32_t *emit, const int32_t *ctl, const int32_t *iters,
+                            const RowDesc *rows, int mb, int msgk, const TileGeom &g, hipStream_t s);
 hipError_t qm_launch_emit(const float *A, const int32_t *emit, const int32_t *ctl, float *app, uint8_t *hard,
                           const TileGeom &g, hipStream_t s);
 // move the planned frames (slot perm[s] into slot s) in every per-node array

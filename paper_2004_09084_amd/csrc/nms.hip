@@ -320,13 +320,6 @@ __global__ void k_et_final(const uint32_t *act, int32_t *iters, int Fpad, int T)
 }
 
 // ------------------------------------------------------------------ loss --
-__device__ __forceinline__ float softplusf(float u) { return fmaxf(u, 0.0f) + log1pf(expf(-fabsf(u))); }
-__device__ __forceinline__ float sigmoidf(float u) {
-    if (u >= 0.0f) return 1.0f / (1.0f + expf(-u));
-    const float e = expf(u);
-    return e / (1.0f + e);
-}
-
 // deterministic block sum of one float (wave shuffles, then LDS in wave order)
 __device__ __forceinline__ float block_sum(float v, float *lds) {
 #pragma unroll
@@ -344,8 +337,19 @@ __device__ __forceinline__ float block_sum(float v, float *lds) {
 // binary cross-entropy of the current APPs: loss = sum softplus(-(1-2x) APP)
 // (scaled by inv_norm at the end: 1/(F n), divided by T for one term of a
 // loss over T sweeps); dL/dAPP = -(1-2x) sigmoid(-(1-2x) APP) * inv_norm.
-// part 0: variables of columns in `cols` (APP in A); part 1: degree-1
-// variables (APP in Ad, by check).  One partial sum per workgroup.
+// Items: (tile, unit, chunk of 256 (node, frame) pairs), unit < ncols a
+// column whose APPs are in A, else a row whose degree-1 APPs are in Ad.  A
+// bounded grid strides over the items in a fixed assignment and each
+// workgroup leaves one partial sum, so the loss is run-to-run identical.
+// softplus(u) and sigmoid(u) share one exponential e^-|u|.
+__device__ __forceinline__ void bce_term(float app, bool bit, float inv, float &l, float &g) {
+    const float u = bit ? app : -app;     // -(1 - 2x) APP
+    const float e = expf(-fabsf(u));
+    l = fmaxf(u, 0.0f) + log1pf(e);       // softplus(u)
+    const float sg = u >= 0.0f ? 1.0f / (1.0f + e) : e / (1.0f + e);  // sigmoid(u)
+    g = (bit ? sg : -sg) * inv;           // d softplus(u) / d APP
+}
+
 __global__ void __launch_bounds__(256) k_bce(const float *__restrict__ A, const float *__restrict__ Ad,
                                              const uint8_t *__restrict__ X, float *__restrict__ gA,
                                              float *__restrict__ gAd, float *__restrict__ part,
@@ -353,40 +357,39 @@ __global__ void __launch_bounds__(256) k_bce(const float *__restrict__ A, const 
                                              int ftl, int ntiles, int chunks, int64_t strideA, int64_t strideM,
                                              int F, float inv_norm) {
     __shared__ float lds[8];
-    const int b = blockIdx.x;
-    const int tile = b % ntiles;
-    const int rest = b / ntiles;
-    const int chunk = rest % chunks;
-    const int unit = rest / chunks;  // < ncols: a column; else a row (degree-1 part)
-    const int idx = chunk * (int)blockDim.x + (int)threadIdx.x;
     const int FT = 1 << ftl;
+    const int64_t items = (int64_t)ntiles * chunks * (ncols + mb);
     float l = 0.0f;
-    if (idx < (Z << ftl)) {
+#pragma unroll 2
+    for (int64_t b = blockIdx.x; b < items; b += gridDim.x) {
+        const int tile = (int)(b % ntiles);
+        const int64_t rest = b / ntiles;
+        const int chunk = (int)(rest % chunks);
+        const int unit = (int)(rest / chunks);
+        const int idx = chunk * (int)blockDim.x + (int)threadIdx.x;
+        if (idx >= (Z << ftl)) continue;
         const int k = idx >> ftl;
         const int fl = idx & (FT - 1);
         const bool real = tile * FT + fl < F;
+        float li, gi;
         if (unit < ncols) {
             const int64_t o = (int64_t)tile * strideA + ((((int64_t)cols[unit] * Z + k) << ftl) + fl);
-            const float app = A[o];
-            const float sg = X[o] ? -1.0f : 1.0f;
-            if (real) l = softplusf(-sg * app);
-            gA[o] = real ? -sg * sigmoidf(-sg * app) * inv_norm : 0.0f;
+            bce_term(A[o], X[o] != 0, inv_norm, li, gi);
+            gA[o] = real ? gi : 0.0f;
         } else {
             ConstRowDesc *rd = as_const(rows + (unit - ncols));
-            if (rd->d1col >= 0) {
-                int v = k + rd->d1shift;
-                v = v >= Z ? v - Z : v;
-                const int64_t od = (int64_t)tile * strideM + ((((int64_t)rd->row * Z + k) << ftl) + fl);
-                const int64_t ox = (int64_t)tile * strideA + ((((int64_t)rd->d1col * Z + v) << ftl) + fl);
-                const float app = Ad[od];
-                const float sg = X[ox] ? -1.0f : 1.0f;
-                if (real) l = softplusf(-sg * app);
-                gAd[od] = real ? -sg * sigmoidf(-sg * app) * inv_norm : 0.0f;
-            }
+            if (rd->d1col < 0) continue;
+            int v = k + rd->d1shift;
+            v = v >= Z ? v - Z : v;
+            const int64_t od = (int64_t)tile * strideM + ((((int64_t)rd->row * Z + k) << ftl) + fl);
+            const int64_t ox = (int64_t)tile * strideA + ((((int64_t)rd->d1col * Z + v) << ftl) + fl);
+            bce_term(Ad[od], X[ox] != 0, inv_norm, li, gi);
+            gAd[od] = real ? gi : 0.0f;
         }
+        if (real) l += li;
     }
     const float s = block_sum(l, lds);
-    if (threadIdx.x == 0) part[b] = s;
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
 // *out = sum(part) * scale, or *out += that (accumulate: a loss with one term
@@ -704,16 +707,17 @@ hipError_t qm_launch_et_final(const uint32_t *act, int32_t *iters, int Fpad, int
     return hipGetLastError();
 }
 
+// workgroups of the loss kernel (its grid strides over the items)
 int qm_bce_blocks(int ncols, int mb, const TileGeom &g) {
     const int chunks = ((g.Z << g.ft_log2) + 255) / 256;
-    return g.ntiles * (ncols + mb) * chunks;
+    return (int)std::min<int64_t>((int64_t)g.ntiles * (ncols + mb) * chunks, 8192);
 }
 
 hipError_t qm_launch_bce(const float *A, const float *Ad, const uint8_t *X, float *gA, float *gAd, float *part,
                          const int32_t *cols, int ncols, const RowDesc *rows, int mb, const TileGeom &g, int F,
                          float weight, int accumulate, float *loss, hipStream_t s) {
     const int chunks = ((g.Z << g.ft_log2) + 255) / 256;
-    const int blocks = g.ntiles * (ncols + mb) * chunks;
+    const int blocks = qm_bce_blocks(ncols, mb, g);
     const float inv = weight / ((float)F * (float)g.n);
     hipLaunchKernelGGL(k_bce, dim3((unsigned)blocks), dim3(256), 0, s, A, Ad, X, gA, gAd, part, cols, ncols, rows,
                        mb, g.Z, g.ft_log2, g.ntiles, chunks, (int64_t)g.n << g.ft_log2, (int64_t)g.m << g.ft_log2,

@@ -289,6 +289,40 @@ def test_training_over_every_sweep_lowers_the_bit_error_rate():
     assert ber["trained"] < 0.5 * ber["plain"]
 
 
+def test_evaluation_composes_minsum_and_fallback():
+    # train_nms.evaluate: frames the min-sum decoder brings to a valid word
+    # keep its hard decisions, the others take sum-product's from their
+    # channel LLRs; every reported figure is recomputed here from separate
+    # decoder calls on the same frames
+    import torch
+    from paper_2004_09084_amd import train_nms as TN
+    H = W.make_code(SMALL, 0)
+    T_nms, T_sp, F, snr = 12, 30, 32, 0.35
+    rng = np.random.default_rng(21)
+    w = np.stack([rng.uniform(0.7, 1.0, (T_nms, SMALL.mb, 2)), rng.uniform(0.0, 0.2, (T_nms, SMALL.mb, 2))],
+                 axis=-1).astype(np.float32)
+    wt = torch.from_numpy(w).cuda()
+    res = TN.evaluate(SMALL, H, wt, T_nms=T_nms, T_sp=T_sp, frames=F, frame_seed=4, snr=snr, log=lambda *_: None)
+    wl = W.build(SMALL, F, graph_seed=0, frame_seed=4, snr=snr)
+    code, dec = _dec(H, SMALL.Z, F, T_nms)
+    hn, _, fn, it = dec.nms_decode(wt, to_dev(wl.llr), to_dev(wl.s), T_nms, early_stop=True)
+    sp = Q.Decoder([code], [F])
+    hs, _, fs = sp.decode(to_dev(wl.llr), to_dev(wl.s), T_sp)
+    torch.cuda.synchronize()
+    ok = fn.cpu().numpy().astype(bool)
+    hard = np.where(ok[:, None], hn.cpu().numpy().reshape(F, -1), hs.cpu().numpy().reshape(F, -1))
+    r = res["trained_minsum"]
+    say("evaluation:", {k: r[k] for k in ("converged", "fallback_frames", "ber_with_fallback", "mean_iterations")})
+    assert 0 < r["converged"] < F, r                      # both paths exercised
+    assert r["converged"] == int(ok.sum()) and r["fallback_frames"] == F - int(ok.sum())
+    assert r["mean_iterations"] == pytest.approx(float(it.cpu().numpy().mean()))
+    assert r["ber_with_fallback"] == pytest.approx(float((hard != wl.x).mean()))
+    assert r["fer_with_fallback"] == pytest.approx(float((hard != wl.x).any(axis=1).mean()))
+    assert r["syndrome_fail_minsum_only"] == pytest.approx(1.0 - ok.mean())
+    assert res["sum_product"]["syndrome_fail"] == pytest.approx(1.0 - fs.cpu().numpy().mean())
+    assert r["mbit_s_with_fallback"] > 0 and res["plain_minsum"]["mbit_s_with_fallback"] > 0
+
+
 def test_nms_requires_one_float32_code():
     H = W.make_code(SMALL, 0)
     code = Q.Code(H, SMALL.Z)

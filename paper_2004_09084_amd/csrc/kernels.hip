@@ -242,6 +242,9 @@ __global__ void __launch_bounds__(256) k_copy_cols(const float *__restrict__ A, 
 // one lane per check and tile XORs the packed words of the row's variables
 // (PA), of its degree-1 variable (Pd) and of its syndrome bits (PS); failing
 // frames are OR-ed in LDS, then one atomic per failing frame and workgroup.
+// W: the packed field's word type (one field per node, max(FT, 8) bits), a
+// template parameter so that every load is one plain load of that width.
+template <typename W>
 __global__ void __launch_bounds__(256) k_syndrome_packed(const uint8_t *__restrict__ PA,
                                                          const uint8_t *__restrict__ Pd,
                                                          const uint8_t *__restrict__ PS, const RowDesc *rows,
@@ -265,10 +268,11 @@ __global__ void __launch_bounds__(256) k_syndrome_packed(const uint8_t *__restri
     const int k = chunk * (int)blockDim.x + tid;
     uint64_t par = 0;
     if (k < Z) {
-        const int esz = qm_pack_bytes(ftl);
         const int64_t chk = (int64_t)rd->row * Z + k;
-        par = load_packed(PS + (int64_t)tile * m * esz, chk, esz);
-        const uint8_t *pa = PA + (int64_t)tile * n * esz;
+        const W *ps = reinterpret_cast<const W *>(PS) + (int64_t)tile * m;
+        const W *pa = reinterpret_cast<const W *>(PA) + (int64_t)tile * n;
+        const W *pd = reinterpret_cast<const W *>(Pd) + (int64_t)tile * m;
+        par = ps[chk];
         // the first 8 entries' loads are all issued before any is used (an
         // entry past the row's degree re-reads entry 0 and is dropped), so
         // they are in flight together; wider rows take the rest in a loop
@@ -279,16 +283,16 @@ __global__ void __launch_bounds__(256) k_syndrome_packed(const uint8_t *__restri
             const int jj = j < d ? j : 0;
             int v = k + rd->shift[jj];
             v = v >= Z ? v - Z : v;
-            w[j] = load_packed(pa, (int64_t)rd->col[jj] * Z + v, esz);
+            w[j] = pa[(int64_t)rd->col[jj] * Z + v];
         }
 #pragma unroll
         for (int j = 0; j < 8; ++j) par ^= j < d ? w[j] : 0ull;
         for (int j = 8; j < d; ++j) {
             int v = k + rd->shift[j];
             v = v >= Z ? v - Z : v;
-            par ^= load_packed(pa, (int64_t)rd->col[j] * Z + v, esz);
+            par ^= pa[(int64_t)rd->col[j] * Z + v];
         }
-        if (rd->d1col >= 0) par ^= load_packed(Pd + (int64_t)tile * m * esz, chk, esz);
+        if (rd->d1col >= 0) par ^= pd[chk];
     }
     // OR over the wave first (most checks fail while frames decode, so a
     // per-lane LDS atomic would serialise), then one atomic per wave
@@ -918,8 +922,16 @@ hipError_t qm_launch_syndrome_packed(const uint8_t *PA, const uint8_t *Pd, const
     const int chunks = (g.Z + 255) / 256;
     const int64_t blocks = (int64_t)g.ntiles * mb * chunks;
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_syndrome_packed, dim3((unsigned)blocks), dim3(256), 0, s, PA, Pd, PS, rows, fail, g.Z,
-                       g.ft_log2, mb, chunks, g.n, g.m, ctl, fpl);
+    switch (qm_pack_bytes(g.ft_log2)) {
+#define QM_SP(W)                                                                                                    \
+    hipLaunchKernelGGL(k_syndrome_packed<W>, dim3((unsigned)blocks), dim3(256), 0, s, PA, Pd, PS, rows, fail, g.Z, \
+                       g.ft_log2, mb, chunks, g.n, g.m, ctl, fpl)
+        case 1: QM_SP(uint8_t); break;
+        case 2: QM_SP(uint16_t); break;
+        case 4: QM_SP(uint32_t); break;
+        default: QM_SP(uint64_t); break;
+#undef QM_SP
+    }
     return hipGetLastError();
 }
 

@@ -239,12 +239,15 @@ __global__ void __launch_bounds__(256) k_copy_cols(const float *__restrict__ A, 
 }
 
 // Syndrome test of an early-terminating decode from packed hard decisions:
-// one lane per check and tile XORs the packed words of the row's variables
-// (PA), of its degree-1 variable (Pd) and of its syndrome bits (PS); failing
-// frames are OR-ed in LDS, then one atomic per failing frame and workgroup.
-// W: the packed field's word type (one field per node, max(FT, 8) bits), a
-// template parameter so that every load is one plain load of that width.
-template <typename W>
+// each lane takes C checks of one row and tile (256 apart, so that every
+// load of a wave is contiguous) and XORs the packed words of the row's
+// variables (PA), of its degree-1 variable (Pd) and of its syndrome bits
+// (PS); failing frames are OR-ed over the wave and in LDS, then one atomic
+// per failing frame and workgroup.  W: the packed field's word type (one
+// field per node, max(FT, 8) bits), so that every load is one plain load of
+// that width.
+constexpr int kSynChecks = 4;  // checks per lane of the packed syndrome test
+template <typename W, int C>
 __global__ void __launch_bounds__(256) k_syndrome_packed(const uint8_t *__restrict__ PA,
                                                          const uint8_t *__restrict__ Pd,
                                                          const uint8_t *__restrict__ PS, const RowDesc *rows,
@@ -265,34 +268,52 @@ __global__ void __launch_bounds__(256) k_syndrome_packed(const uint8_t *__restri
     if (tid < 2) lm[tid] = 0u;
     __syncthreads();
     const RowDesc *rd = rows + rs;
-    const int k = chunk * (int)blockDim.x + tid;
+    const int d = rd->d;
+    const int64_t rowb = (int64_t)rd->row * Z;
+    const bool has_d1 = rd->d1col >= 0;
+    const W *ps = reinterpret_cast<const W *>(PS) + (int64_t)tile * m + rowb;
+    // a row without a degree-1 variable re-reads its syndrome word instead
+    const W *p1 = has_d1 ? reinterpret_cast<const W *>(Pd) + (int64_t)tile * m + rowb : ps;
+    const W *pa = reinterpret_cast<const W *>(PA) + (int64_t)tile * n;
+    // every load of the lane's checks is issued before any word is used: a
+    // check past Z re-reads check Z-1 and an entry past the row's degree
+    // re-reads entry 0, and their words are dropped
+    int kk[C];
+    bool ok[C];
+    W sv[C], dv[C], w[C][8];
+#pragma unroll
+    for (int i = 0; i < C; ++i) {
+        const int k = chunk * (256 * C) + i * 256 + tid;
+        ok[i] = k < Z;
+        kk[i] = ok[i] ? k : Z - 1;
+        sv[i] = ps[kk[i]];
+        dv[i] = p1[kk[i]];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int jj = j < d ? j : 0;
+        const W *pc = pa + (int64_t)rd->col[jj] * Z;
+        const int sh = rd->shift[jj];
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            int v = kk[i] + sh;
+            v = v >= Z ? v - Z : v;
+            w[i][j] = pc[v];
+        }
+    }
     uint64_t par = 0;
-    if (k < Z) {
-        const int64_t chk = (int64_t)rd->row * Z + k;
-        const W *ps = reinterpret_cast<const W *>(PS) + (int64_t)tile * m;
-        const W *pa = reinterpret_cast<const W *>(PA) + (int64_t)tile * n;
-        const W *pd = reinterpret_cast<const W *>(Pd) + (int64_t)tile * m;
-        par = ps[chk];
-        // the first 8 entries' loads are all issued before any is used (an
-        // entry past the row's degree re-reads entry 0 and is dropped), so
-        // they are in flight together; wider rows take the rest in a loop
-        const int d = rd->d;
-        uint64_t w[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int jj = j < d ? j : 0;
-            int v = k + rd->shift[jj];
-            v = v >= Z ? v - Z : v;
-            w[j] = pa[(int64_t)rd->col[jj] * Z + v];
-        }
+    for (int i = 0; i < C; ++i) {
+        W x = sv[i] ^ (has_d1 ? dv[i] : (W)0);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) par ^= j < d ? w[j] : 0ull;
+        for (int j = 0; j < 8; ++j) x ^= j < d ? w[i][j] : (W)0;
+        // rows wider than 8 take the rest one entry at a time
         for (int j = 8; j < d; ++j) {
-            int v = k + rd->shift[j];
+            int v = kk[i] + rd->shift[j];
             v = v >= Z ? v - Z : v;
-            par ^= pa[(int64_t)rd->col[j] * Z + v];
+            x ^= pa[(int64_t)rd->col[j] * Z + v];
         }
-        if (rd->d1col >= 0) par ^= pd[chk];
+        par |= ok[i] ? (uint64_t)x : 0ull;
     }
     // OR over the wave first (most checks fail while frames decode, so a
     // per-lane LDS atomic would serialise), then one atomic per wave
@@ -300,11 +321,11 @@ __global__ void __launch_bounds__(256) k_syndrome_packed(const uint8_t *__restri
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         lo |= __shfl_xor(lo, o, 64);
-        hi |= __shfl_xor(hi, o, 64);
+        if constexpr (sizeof(W) == 8) hi |= __shfl_xor(hi, o, 64);
     }
     if ((tid & 63) == 0 && (lo | hi)) {
         atomicOr(&lm[0], lo);
-        atomicOr(&lm[1], hi);
+        if constexpr (sizeof(W) == 8) atomicOr(&lm[1], hi);
     }
     __syncthreads();
     if (tid < FT) {
@@ -330,7 +351,8 @@ struct NegBit {
 struct LowBit {
     __device__ bool operator()(uint8_t x) const { return (x & 1u) != 0u; }
 };
-constexpr int kPackU = 4;
+constexpr int kPackU = 4;      // passes per wave of the one-off packing passes
+constexpr int kPackColsU = 8;  // passes per wave of the packing before every test
 
 template <int U, typename T, typename Bit>
 __device__ __forceinline__ void pack_wave(const T *__restrict__ X, uint8_t *__restrict__ P, int64_t node0,
@@ -361,10 +383,11 @@ __device__ __forceinline__ void pack_wave(const T *__restrict__ X, uint8_t *__re
     }
 }
 
-// first node of this wave's kPackU passes in block bx
+// first node of this wave's U passes in block bx
+template <int U = kPackU>
 __device__ __forceinline__ int64_t pack_node0(int ftl, int64_t bx = -1) {
     const int64_t wave = (bx < 0 ? (int64_t)blockIdx.x : bx) * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    return wave * kPackU * (64 >> ftl);
+    return wave * U * (64 >> ftl);
 }
 
 // Packed hard decisions of every node of the tiles.
@@ -383,8 +406,8 @@ __global__ void __launch_bounds__(256) k_pack_cols(const float *__restrict__ A, 
     const int64_t tile = blockIdx.z;
     if (tile >= ctl[1]) return;
     const int64_t base = (int64_t)cols1[blockIdx.y] * Z;
-    pack_wave<kPackU, float, NegBit>(A + ((tile * n) << ftl), P + tile * n * qm_pack_bytes(ftl),
-                                     base + pack_node0(ftl), base + Z, ftl, fpl);
+    pack_wave<kPackColsU, float, NegBit>(A + ((tile * n) << ftl), P + tile * n * qm_pack_bytes(ftl),
+                                         base + pack_node0<kPackColsU>(ftl), base + Z, ftl, fpl);
 }
 
 // Packed syndrome bits (same order) of the tiles below ctl[1] (all tiles if
@@ -919,13 +942,13 @@ hipError_t qm_launch_syndrome_packed(const uint8_t *PA, const uint8_t *Pd, const
                                      int mb, uint32_t *fail, const int32_t *ctl, int fpl, const TileGeom &g,
                                      hipStream_t s) {
     if ((1 << g.ft_log2) > 64 || !ctl || fpl < 1) return hipErrorInvalidValue;
-    const int chunks = (g.Z + 255) / 256;
+    const int chunks = (g.Z + 256 * kSynChecks - 1) / (256 * kSynChecks);
     const int64_t blocks = (int64_t)g.ntiles * mb * chunks;
     if (blocks == 0) return hipSuccess;
     switch (qm_pack_bytes(g.ft_log2)) {
-#define QM_SP(W)                                                                                                    \
-    hipLaunchKernelGGL(k_syndrome_packed<W>, dim3((unsigned)blocks), dim3(256), 0, s, PA, Pd, PS, rows, fail, g.Z, \
-                       g.ft_log2, mb, chunks, g.n, g.m, ctl, fpl)
+#define QM_SP(W)                                                                                                  \
+    hipLaunchKernelGGL((k_syndrome_packed<W, kSynChecks>), dim3((unsigned)blocks), dim3(256), 0, s, PA, Pd, PS,  \
+                       rows, fail, g.Z, g.ft_log2, mb, chunks, g.n, g.m, ctl, fpl)
         case 1: QM_SP(uint8_t); break;
         case 2: QM_SP(uint16_t); break;
         case 4: QM_SP(uint32_t); break;
@@ -936,8 +959,8 @@ hipError_t qm_launch_syndrome_packed(const uint8_t *PA, const uint8_t *Pd, const
 }
 
 // blocks of 256 lanes for a packing pass over N nodes
-static unsigned pack_blocks(int64_t N, int ftl) {
-    const int64_t per_block = 4LL * kPackU * (64 >> ftl);
+static unsigned pack_blocks(int64_t N, int ftl, int U = kPackU) {
+    const int64_t per_block = 4LL * U * (64 >> ftl);
     return (unsigned)((N + per_block - 1) / per_block);
 }
 
@@ -953,7 +976,7 @@ hipError_t qm_launch_pack_cols(const float *A, uint8_t *P, const int32_t *cols1,
                                const TileGeom &g, hipStream_t s) {
     if ((1 << g.ft_log2) > 64 || fpl < 1 || fpl > (1 << g.ft_log2) || !ctl) return hipErrorInvalidValue;
     if (ncols1 == 0 || g.ntiles == 0) return hipSuccess;
-    dim3 grid(pack_blocks(g.Z, g.ft_log2), (unsigned)ncols1, (unsigned)g.ntiles);
+    dim3 grid(pack_blocks(g.Z, g.ft_log2, kPackColsU), (unsigned)ncols1, (unsigned)g.ntiles);
     hipLaunchKernelGGL(k_pack_cols, grid, dim3(256), 0, s, A, P, cols1, g.Z, g.n, g.ft_log2, fpl, ctl);
     return hipGetLastError();
 }

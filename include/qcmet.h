@@ -309,7 +309,9 @@ int qm_decoder_get_profile(qm_decoder *dec, qm_profile *out, int32_t reset);
  * reaches APP_d = LLR_d + r_d.  The decoder must hold exactly one code with
  * float32 messages (QM_ERR_UNSUPPORTED otherwise).
  * Workspace: a second device buffer, sized for at most T sweeps; train = 1
- * adds the per-sweep records of q (T x messages) and the adjoints. */
+ * adds the per-sweep records of q (T x messages) and two sets of adjoints
+ * and gradient partial sums (qm_nms_train_grad runs two loss terms'
+ * reverse sweeps at once). */
 size_t qm_nms_workspace_bytes(const qm_decoder *dec, int32_t T, int32_t train);
 int qm_nms_bind_workspace(qm_decoder *dec, void *device_ptr, size_t bytes, int32_t T, int32_t train);
 
@@ -339,8 +341,11 @@ int qm_nms_decode(qm_decoder *dec, const float *weights, const float *llr, const
  * per sweep on the workload codes); each is bounded at 1e30, so nothing
  * becomes inf or NaN, and `clamped` (device int32, or NULL) receives how
  * many adjoint components reached the bound: 0 means the gradient is exact.
- * Gradient sums over workgroups are reduced in a fixed order (run-to-run
- * identical).
+ * With every_sweep = 1 consecutive terms' reverse sweeps run on two streams
+ * of the decoder, forked from and joined back to `stream` inside the call
+ * (the terms alternate between two sets of adjoints and partial sums), beside
+ * the forward sweeps.  Gradient sums over workgroups and sets are reduced in
+ * a fixed order (run-to-run identical).
  *   x: device uint8 [F][n]; loss: device float scalar; grad: device float,
  *   same layout as weights (first T sweeps).  Needs a train workspace bound
  *   for at least T sweeps. */

@@ -171,6 +171,11 @@ struct qm_decoder {
     int32_t nT = 0, ntrain = 0;
     size_t oAd = 0, oAct = 0, oTmask = 0, oIt = 0, oCols = 0, oLossP = 0, oLoss = 0, oX = 0, ogA = 0, ogAd = 0,
            ogR = 0, oQ = 0, oPart = 0, oClamp = 0, nTotal = 0;
+    size_t adjSet = 0, partSet = 0;  // bytes of one adjoint set (gA, gAd, gR) and of one partial-sum set
+    // training: events of the loss terms' reverse sweeps (one per term,
+    // cycled) and of each term's forward part, for the reverse streams
+    std::vector<hipEvent_t> term_done;
+    hipEvent_t term_fwd = nullptr;
     std::vector<int32_t> acols;  // columns whose APP lives in A (degree != 1)
     int64_t lds_limit = 0;      // LDS bytes one workgroup may use (queried at bind)
     int64_t lds_per_cu = 0;     // LDS bytes of one compute unit (queried at bind)
@@ -1064,6 +1069,12 @@ int nms_slot(qm_decoder &d, Slot **out) {
     return QM_OK;
 }
 
+// Loss terms of a training call whose reverse sweeps may run at once, each
+// on its own stream with its own adjoints and partial sums (the reverse
+// sweeps of a term read only K, the degree-1 LLRs, the weights and the
+// recorded q's, none of which a later forward sweep changes).
+constexpr int kAdjSets = 2;
+
 void nms_layout(qm_decoder &d, const Slot &s, int32_t T, int32_t train) {
     const size_t fp = (size_t)s.Fpad, n = (size_t)s.n, m = (size_t)s.m;
     const size_t e = (size_t)s.code->nent1 * s.code->Z;
@@ -1079,15 +1090,20 @@ void nms_layout(qm_decoder &d, const Slot &s, int32_t T, int32_t train) {
     d.oLoss = off; off = align_up(off + 4);
     if (train) {
         d.oX = off; off = align_up(off + fp * n);
-        d.ogA = off; off = align_up(off + fp * n * 4);
-        d.ogAd = off; off = align_up(off + fp * m * 4);
-        d.ogR = off; off = align_up(off + fp * e * 4);
+        // kAdjSets sets of adjoints (gA, gAd, gR), one per loss term whose
+        // reverse sweeps may run at once
+        d.ogA = off;
+        d.ogAd = d.ogA + align_up(fp * n * 4);
+        d.ogR = d.ogAd + align_up(fp * m * 4);
+        d.adjSet = d.ogR + align_up(fp * e * 4) - d.ogA;
+        off += kAdjSets * d.adjSet;
         // the q's of every sweep inside a backward window (at most T),
         // recorded by the forward sweeps: the reverse sweeps need nothing else
         d.oQ = off; off = align_up(off + (size_t)T * fp * e * 4);
         // per-workgroup gradient sums of the reverse sweep: at most
         // Fpad*Z/64 + Fpad workgroups per (sweep, row)
-        d.oPart = off; off = align_up(off + (size_t)T * s.code->mb * (fp * s.code->Z / 64 + fp + 1) * 16);
+        d.partSet = align_up((size_t)T * s.code->mb * (fp * s.code->Z / 64 + fp + 1) * 16);
+        d.oPart = off; off += kAdjSets * d.partSet;
         d.oClamp = off; off = align_up(off + 4);
     }
     d.nTotal = off;
@@ -1348,6 +1364,8 @@ int qm_decoder_destroy(qm_decoder *d) {
     for (hipStream_t g : d->gstreams) (void)hipStreamDestroy(g);
     for (hipEvent_t e : d->gjoin) (void)hipEventDestroy(e);
     if (d->gfork) (void)hipEventDestroy(d->gfork);
+    for (hipEvent_t e : d->term_done) (void)hipEventDestroy(e);
+    if (d->term_fwd) (void)hipEventDestroy(d->term_fwd);
     if (d->ev_fork) (void)hipEventDestroy(d->ev_fork);
     if (d->ev_join) (void)hipEventDestroy(d->ev_join);
     if (d->side) (void)hipStreamDestroy(d->side);
@@ -1719,10 +1737,30 @@ int qm_nms_train_grad(qm_decoder *d, const float *W, const float *llr, const uin
     const size_t fp = (size_t)s->Fpad;
     const size_t qsz = fp * (size_t)c.nent1 * c.Z;  // floats of one sweep's q record
     float *Ad = nws_ptr<float>(*d, d->oAd), *Q = nws_ptr<float>(*d, d->oQ);
-    float *gA = nws_ptr<float>(*d, d->ogA), *gAd = nws_ptr<float>(*d, d->ogAd), *gR = nws_ptr<float>(*d, d->ogR);
-    float *part = nws_ptr<float>(*d, d->oPart);
     int32_t *clamps = nws_ptr<int32_t>(*d, d->oClamp);
     uint8_t *X = nws_ptr<uint8_t>(*d, d->oX);
+    // With a loss term in every sweep, consecutive terms' reverse sweeps run
+    // on kAdjSets streams at once (term t on set t % kAdjSets), beside the
+    // forward sweeps on the caller's stream.  Forward sweep t records its
+    // q's in slot t % nq of a ring of nq = window + kAdjSets slots, so it
+    // first waits for the last term that reads the slot it overwrites (term
+    // t - kAdjSets - 1); term t's loss kernel writes set t % kAdjSets after
+    // term t - kAdjSets is done with it.
+    const int nsets = (every_sweep && T > 1) ? kAdjSets : 1;
+    const int nq = nsets > 1 ? std::min(T, window + nsets) : window;
+    const int nev = nsets + 2;  // term events, cycled: a wait never names a re-recorded one
+    if (nsets > 1) {
+        if ((rc = ensure_group_streams(*d, nsets + 1)) != QM_OK) return rc;
+        while ((int)d->term_done.size() < nev) {
+            hipEvent_t e = nullptr;
+            QM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            d->term_done.push_back(e);
+        }
+        if (!d->term_fwd) QM_HIP(hipEventCreateWithFlags(&d->term_fwd, hipEventDisableTiming));
+    }
+    auto gA_of = [&](int k) { return nws_ptr<float>(*d, d->ogA + (size_t)k * d->adjSet); };
+    auto gAd_of = [&](int k) { return nws_ptr<float>(*d, d->ogAd + (size_t)k * d->adjSet); };
+    auto gR_of = [&](int k) { return nws_ptr<float>(*d, d->ogR + (size_t)k * d->adjSet); };
 
     if ((rc = nms_init(*d, *s, llr, syn, st)) != QM_OK) return rc;
     QM_HIP(qm_launch_to_tiles_u8(x, X, s->F, s->n, g.ft_log2, g.ntiles, st));
@@ -1730,46 +1768,67 @@ int qm_nms_train_grad(qm_decoder *d, const float *W, const float *llr, const uin
     NmsBwdArgs ba;
     std::memset(&ba, 0, sizeof(ba));
     ba.L = layer_args(*d, *s);
-    ba.gA = gA;
-    ba.gR = gR;
-    ba.gAd = gAd;
-    ba.part = part;
     ba.clamps = clamps;
     ba.mb = c.mb;
     const int per_row = ba.L.ntiles * ba.L.chunks;
-    QM_HIP(qm_launch_fill_u32(reinterpret_cast<uint32_t *>(part), 0u, (size_t)T * c.mb * per_row * 4, st));
+    const size_t part_floats = (size_t)T * c.mb * per_row * 4;  // one set's partial sums
+    float *part = nws_ptr<float>(*d, d->oPart);
+    QM_HIP(qm_launch_fill_u32(reinterpret_cast<uint32_t *>(part), 0u, (size_t)nsets * part_floats, st));
     QM_HIP(qm_launch_fill_u32(reinterpret_cast<uint32_t *>(clamps), 0u, 1, st));
+    if (nsets > 1) {
+        QM_HIP(hipEventRecord(d->term_fwd, st));
+        for (int k = 0; k < nsets; ++k) QM_HIP(hipStreamWaitEvent(d->gstreams[k], d->term_fwd, 0));
+    }
     const int G = (int)s->gptr.size() - 1;
     const float weight = every_sweep ? 1.0f / (float)T : 1.0f;
     bool first_term = true;
     for (int t = 0; t < T; ++t) {
-        // forward sweep t, recording its q's in the window's ring of records;
-        // the degree-1 APPs are formed in every sweep that ends a loss term
+        // forward sweep t, recording its q's in the ring; the degree-1 APPs
+        // are formed in every sweep that ends a loss term
+        if (nsets > 1 && t - nsets - 1 >= 0)
+            QM_HIP(hipStreamWaitEvent(st, d->term_done[(t - nsets - 1) % nev], 0));
         const bool term = every_sweep || t == T - 1;
-        if ((rc = nms_sweep(*d, *s, W, t, term ? 1 : 0, nullptr, Q + (size_t)(t % window) * qsz, st)) != QM_OK)
+        if ((rc = nms_sweep(*d, *s, W, t, term ? 1 : 0, nullptr, Q + (size_t)(t % nq) * qsz, st)) != QM_OK)
             return rc;
         if (!term) continue;
+        const int k = t % nsets;
+        float *gA = gA_of(k), *gAd = gAd_of(k), *gR = gR_of(k);
+        if (nsets > 1 && t - nsets >= 0) QM_HIP(hipStreamWaitEvent(st, d->term_done[(t - nsets) % nev], 0));
         // this sweep's loss term and dL/dAPP; nothing flows back through
         // the messages it wrote
         QM_HIP(qm_launch_bce(b.A, Ad, X, gA, gAd, nws_ptr<float>(*d, d->oLossP), nws_ptr<int32_t>(*d, d->oCols),
                              (int)d->acols.size(), b.rows, c.mb, g, s->F, weight, first_term ? 0 : 1, loss, st));
         first_term = false;
-        QM_HIP(qm_launch_fill_u32(reinterpret_cast<uint32_t *>(gR), 0u, qsz, st));
+        hipStream_t bs = st;
+        if (nsets > 1) {
+            bs = d->gstreams[k];
+            QM_HIP(hipEventRecord(d->term_fwd, st));
+            QM_HIP(hipStreamWaitEvent(bs, d->term_fwd, 0));
+        }
+        ba.gA = gA;
+        ba.gR = gR;
+        ba.gAd = gAd;
+        ba.part = part + (size_t)k * part_floats;
         // reverse sweeps t, t-1, ... down to the window's first, each from
         // its recorded q's; the degree-1 edges are targets only in sweep t
         for (int u = t; u >= 0 && u > t - window; --u) {
             ba.t = u;
-            ba.Q = Q + (size_t)(u % window) * qsz;
+            ba.Q = Q + (size_t)(u % nq) * qsz;
             ba.L.last = (u == t) ? 1 : 0;
             ba.W = W + (size_t)u * c.mb * 4;
             for (int gi = G - 1; gi >= 0; --gi) {
                 ba.L.rows = rows + s->gptr[gi];
                 ba.L.nrows = s->gptr[gi + 1] - s->gptr[gi];
-                QM_HIP(qm_launch_nms_bwd(ba, s->maxd_t, ba.L.fpl, d->tun.block, st));
+                QM_HIP(qm_launch_nms_bwd(ba, s->maxd_t, ba.L.fpl, d->tun.block, bs));
             }
         }
+        if (nsets > 1) QM_HIP(hipEventRecord(d->term_done[t % nev], bs));
     }
-    QM_HIP(qm_launch_grad_reduce(part, grad, T, c.mb, per_row, st));
+    // join the reverse streams (their last terms), then sum the sets'
+    // partials per (sweep, row, component)
+    for (int t = std::max(0, T - nsets); nsets > 1 && t < T; ++t)
+        QM_HIP(hipStreamWaitEvent(st, d->term_done[t % nev], 0));
+    QM_HIP(qm_launch_grad_reduce(part, grad, T, c.mb, per_row, nsets, part_floats, st));
     if (clamped) QM_HIP(hipMemcpyAsync(clamped, clamps, 4, hipMemcpyDeviceToDevice, st));
     return QM_OK;
 }

@@ -337,19 +337,52 @@ __device__ __forceinline__ float block_sum(float v, float *lds) {
 // binary cross-entropy of the current APPs: loss = sum softplus(-(1-2x) APP)
 // (scaled by inv_norm at the end: 1/(F n), divided by T for one term of a
 // loss over T sweeps); dL/dAPP = -(1-2x) sigmoid(-(1-2x) APP) * inv_norm.
-// Items: (tile, unit, chunk of 256 (node, frame) pairs), unit < ncols a
-// column whose APPs are in A, else a row whose degree-1 APPs are in Ad.  A
-// bounded grid strides over the items in a fixed assignment and each
-// workgroup leaves one partial sum, so the loss is run-to-run identical.
-// softplus(u) and sigmoid(u) share one exponential e^-|u|.
+// Items: (tile, unit, chunk of 256 lanes), unit < ncols a column whose APPs
+// are in A, else a row whose degree-1 APPs are in Ad; a lane takes V
+// adjacent frames of one node.  A bounded grid strides over the items in a
+// fixed assignment and each workgroup leaves one partial sum, so the loss
+// is run-to-run identical.
+// softplus(u) = max(u, 0) + log1p(e) and sigmoid(u) share e = e^-|u| (the
+// hardware base-2 exponential); log1p(e) is its series below 2^-6 (error
+// under e^5 / 5) and the hardware logarithm of 1 + e above.
 __device__ __forceinline__ void bce_term(float app, bool bit, float inv, float &l, float &g) {
-    const float u = bit ? app : -app;     // -(1 - 2x) APP
-    const float e = expf(-fabsf(u));
-    l = fmaxf(u, 0.0f) + log1pf(e);       // softplus(u)
-    const float sg = u >= 0.0f ? 1.0f / (1.0f + e) : e / (1.0f + e);  // sigmoid(u)
-    g = (bit ? sg : -sg) * inv;           // d softplus(u) / d APP
+    constexpr float kLog2e = 1.44269504088896341f, kLn2 = 0.693147180559945309f;
+    const float u = bit ? app : -app;  // -(1 - 2x) APP
+    const float e = __builtin_amdgcn_exp2f(-fabsf(u) * kLog2e);
+    const float ser = e * (1.0f - e * (0.5f - e * (0.33333333f - 0.25f * e)));
+    const float lp = e < 0x1p-6f ? ser : __builtin_amdgcn_logf(1.0f + e) * kLn2;
+    l = fmaxf(u, 0.0f) + lp;  // softplus(u)
+    const float r = __builtin_amdgcn_rcpf(1.0f + e);
+    const float sg = u >= 0.0f ? r : e * r;  // sigmoid(u)
+    g = (bit ? sg : -sg) * inv;              // d softplus(u) / d APP
 }
 
+template <int V>
+__device__ __forceinline__ void bce_lanes(const float *__restrict__ src, const uint8_t *__restrict__ xs,
+                                          float *__restrict__ dst, bool (&real)[V], float inv, float &l) {
+    float a[V], g[V];
+    bool bit[V];
+    if constexpr (V == 4) {
+        const float4 av = *reinterpret_cast<const float4 *>(src);
+        const uchar4 xv = *reinterpret_cast<const uchar4 *>(xs);
+        a[0] = av.x; a[1] = av.y; a[2] = av.z; a[3] = av.w;
+        bit[0] = xv.x != 0; bit[1] = xv.y != 0; bit[2] = xv.z != 0; bit[3] = xv.w != 0;
+    } else {
+        a[0] = src[0];
+        bit[0] = xs[0] != 0;
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        float li, gi;
+        bce_term(a[v], bit[v], inv, li, gi);
+        g[v] = real[v] ? gi : 0.0f;
+        if (real[v]) l += li;
+    }
+    if constexpr (V == 4) *reinterpret_cast<float4 *>(dst) = make_float4(g[0], g[1], g[2], g[3]);
+    else dst[0] = g[0];
+}
+
+template <int V>
 __global__ void __launch_bounds__(256) k_bce(const float *__restrict__ A, const float *__restrict__ Ad,
                                              const uint8_t *__restrict__ X, float *__restrict__ gA,
                                              float *__restrict__ gAd, float *__restrict__ part,
@@ -359,6 +392,7 @@ __global__ void __launch_bounds__(256) k_bce(const float *__restrict__ A, const 
     __shared__ float lds[8];
     const int FT = 1 << ftl;
     const int64_t items = (int64_t)ntiles * chunks * (ncols + mb);
+    const int lanes = (Z << ftl) / V;  // lanes of one item
     float l = 0.0f;
 #pragma unroll 2
     for (int64_t b = blockIdx.x; b < items; b += gridDim.x) {
@@ -367,26 +401,25 @@ __global__ void __launch_bounds__(256) k_bce(const float *__restrict__ A, const 
         const int chunk = (int)(rest % chunks);
         const int unit = (int)(rest / chunks);
         const int idx = chunk * (int)blockDim.x + (int)threadIdx.x;
-        if (idx >= (Z << ftl)) continue;
-        const int k = idx >> ftl;
-        const int fl = idx & (FT - 1);
-        const bool real = tile * FT + fl < F;
-        float li, gi;
+        if (idx >= lanes) continue;
+        const int e0 = idx * V;  // k * FT + first frame of the lane
+        const int k = e0 >> ftl;
+        const int fl = e0 & (FT - 1);
+        bool real[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) real[v] = tile * FT + fl + v < F;
         if (unit < ncols) {
-            const int64_t o = (int64_t)tile * strideA + ((((int64_t)cols[unit] * Z + k) << ftl) + fl);
-            bce_term(A[o], X[o] != 0, inv_norm, li, gi);
-            gA[o] = real ? gi : 0.0f;
+            const int64_t o = (int64_t)tile * strideA + (((int64_t)cols[unit] * Z) << ftl) + e0;
+            bce_lanes<V>(A + o, X + o, gA + o, real, inv_norm, l);
         } else {
             ConstRowDesc *rd = as_const(rows + (unit - ncols));
             if (rd->d1col < 0) continue;
             int v = k + rd->d1shift;
             v = v >= Z ? v - Z : v;
-            const int64_t od = (int64_t)tile * strideM + ((((int64_t)rd->row * Z + k) << ftl) + fl);
+            const int64_t od = (int64_t)tile * strideM + (((int64_t)rd->row * Z) << ftl) + e0;
             const int64_t ox = (int64_t)tile * strideA + ((((int64_t)rd->d1col * Z + v) << ftl) + fl);
-            bce_term(Ad[od], X[ox] != 0, inv_norm, li, gi);
-            gAd[od] = real ? gi : 0.0f;
+            bce_lanes<V>(Ad + od, X + ox, gAd + od, real, inv_norm, l);
         }
-        if (real) l += li;
     }
     const float s = block_sum(l, lds);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
@@ -450,7 +483,14 @@ __device__ __forceinline__ void check_nms_bwd(const LaneCtx &c, ConstRowDesc *rd
         float ga[FPL], gro[FPL];
         bload_f32<FPL>(nd.rQ, vo4, ent_so[j], q[j]);
         bload_f32<FPL>(nd.rgA, aoff[j], col_so[j], ga);
-        bload_f32<FPL>(nd.rgR, vo4, ent_so[j], gro);
+        // a term's own sweep is the first reverse sweep of its window: no
+        // later sweep has sent anything back through these messages yet
+        if (c.last) {
+#pragma unroll
+            for (int f = 0; f < FPL; ++f) gro[f] = 0.0f;
+        } else {
+            bload_f32<FPL>(nd.rgR, vo4, ent_so[j], gro);
+        }
 #pragma unroll
         for (int f = 0; f < FPL; ++f) {
             neg[f] = neg[f] != (q[j][f] < 0.0f);
@@ -577,14 +617,17 @@ __global__ void __launch_bounds__(256) k_nms_bwd(const NmsBwdArgs ba) {
 // unrolls) the partials are finite but their float32 sum can overflow; the
 // result saturates at the largest float32 instead of becoming infinite, so
 // it keeps its sign for the optimiser.
-__global__ void k_grad_reduce(const float *part, float *grad, int T, int mb, int per_row) {
+__global__ void k_grad_reduce(const float *part, float *grad, int T, int mb, int per_row, int nsets,
+                              int64_t set_stride) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;  // (t, i, component)
     if (e >= T * mb * 4) return;
     const int comp = e & 3;
     const int ti = e >> 2;
-    const float *p = part + (int64_t)ti * per_row * 4 + comp;
     double s = 0.0;
-    for (int i = 0; i < per_row; ++i) s += (double)p[(int64_t)i * 4];
+    for (int k = 0; k < nsets; ++k) {
+        const float *p = part + k * set_stride + (int64_t)ti * per_row * 4 + comp;
+        for (int i = 0; i < per_row; ++i) s += (double)p[(int64_t)i * 4];
+    }
     constexpr double kMax = 3.4028234663852886e38;  // largest float32
     s = s > kMax ? kMax : s < -kMax ? -kMax : s;
     // part components: 0 dalpha(type 1), 1 dbeta(type 1), 2 dalpha(degree 1), 3 dbeta(degree 1)
@@ -707,28 +750,42 @@ hipError_t qm_launch_et_final(const uint32_t *act, int32_t *iters, int Fpad, int
     return hipGetLastError();
 }
 
+// frames per lane of the loss kernel: 4 (16-byte accesses) when a tile
+// holds at least 4 frames
+static int bce_frames_per_lane(const TileGeom &g) { return g.ft_log2 >= 2 ? 4 : 1; }
+static int bce_chunks(const TileGeom &g) {
+    return (((g.Z << g.ft_log2) / bce_frames_per_lane(g)) + 255) / 256;
+}
+
 // workgroups of the loss kernel (its grid strides over the items)
 int qm_bce_blocks(int ncols, int mb, const TileGeom &g) {
-    const int chunks = ((g.Z << g.ft_log2) + 255) / 256;
-    return (int)std::min<int64_t>((int64_t)g.ntiles * (ncols + mb) * chunks, 8192);
+    return (int)std::min<int64_t>((int64_t)g.ntiles * (ncols + mb) * bce_chunks(g), 8192);
 }
 
 hipError_t qm_launch_bce(const float *A, const float *Ad, const uint8_t *X, float *gA, float *gAd, float *part,
                          const int32_t *cols, int ncols, const RowDesc *rows, int mb, const TileGeom &g, int F,
                          float weight, int accumulate, float *loss, hipStream_t s) {
-    const int chunks = ((g.Z << g.ft_log2) + 255) / 256;
+    const int chunks = bce_chunks(g);
     const int blocks = qm_bce_blocks(ncols, mb, g);
     const float inv = weight / ((float)F * (float)g.n);
-    hipLaunchKernelGGL(k_bce, dim3((unsigned)blocks), dim3(256), 0, s, A, Ad, X, gA, gAd, part, cols, ncols, rows,
-                       mb, g.Z, g.ft_log2, g.ntiles, chunks, (int64_t)g.n << g.ft_log2, (int64_t)g.m << g.ft_log2,
-                       F, inv);
+    if (bce_frames_per_lane(g) == 4)
+        hipLaunchKernelGGL(k_bce<4>, dim3((unsigned)blocks), dim3(256), 0, s, A, Ad, X, gA, gAd, part, cols, ncols,
+                           rows, mb, g.Z, g.ft_log2, g.ntiles, chunks, (int64_t)g.n << g.ft_log2,
+                           (int64_t)g.m << g.ft_log2, F, inv);
+    else
+        hipLaunchKernelGGL(k_bce<1>, dim3((unsigned)blocks), dim3(256), 0, s, A, Ad, X, gA, gAd, part, cols, ncols,
+                           rows, mb, g.Z, g.ft_log2, g.ntiles, chunks, (int64_t)g.n << g.ft_log2,
+                           (int64_t)g.m << g.ft_log2, F, inv);
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, part, blocks, inv, accumulate, loss);
     return hipGetLastError();
 }
 
-hipError_t qm_launch_grad_reduce(const float *part, float *grad, int T, int mb, int per_row, hipStream_t s) {
+hipError_t qm_launch_grad_reduce(const float *part, float *grad, int T, int mb, int per_row, int nsets,
+                                 size_t set_stride, hipStream_t s) {
+    if (nsets < 1) return hipErrorInvalidValue;
     const int n = T * mb * 4;
-    hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, grad, T, mb, per_row);
+    hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, grad, T, mb, per_row,
+                       nsets, (int64_t)set_stride);
     return hipGetLastError();
 }
 

@@ -140,7 +140,8 @@ struct NmsBwdArgs {
     LayerArgs L;              // A (LLR in degree-1 columns), K, rows, geometry; L.last = last sweep
     const float *Q;           // q of this sweep (recomputed)
     float *gA;                // [ntiles][n][FT] dLoss/dAPP (in/out)
-    float *gR;                // [ntiles][nent1*Z][FT] dLoss/dr from later sweeps (in/out)
+    float *gR;                // [ntiles][nent1*Z][FT] dLoss/dr from later sweeps (in/out; not read
+                              // in the loss term's own sweep, L.last, which starts it)
     const float *gAd;         // [ntiles][m][FT] dLoss/dAPP of degree-1 variables (last sweep)
     const float *W;           // this sweep's weights
     float *part;              // per-workgroup sums [T][mb][ntiles][chunks][4], accumulated
@@ -247,7 +248,10 @@ int qm_bce_blocks(int ncols, int mb, const TileGeom &g);
 hipError_t qm_launch_bce(const float *A, const float *Ad, const uint8_t *X, float *gA, float *gAd, float *part,
                          const int32_t *cols, int ncols, const RowDesc *rows, int mb, const TileGeom &g, int F,
                          float weight, int accumulate, float *loss, hipStream_t s);
-hipError_t qm_launch_grad_reduce(const float *part, float *grad, int T, int mb, int per_row, hipStream_t s);
+// grad[t][i][c] = the sum of the per-workgroup partials of (t, i, c) over
+// nsets partial sets, set_stride floats apart (double accumulation, fixed order)
+hipError_t qm_launch_grad_reduce(const float *part, float *grad, int T, int mb, int per_row, int nsets,
+                                 size_t set_stride, hipStream_t s);
 hipError_t qm_launch_adam(float *w, const float *g, float *m, float *v, int n, float lr, float b1, float b2, float eps,
                           int step, hipStream_t s);
 

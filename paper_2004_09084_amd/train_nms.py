@@ -219,7 +219,7 @@ def main():
                     help="sweeps each loss term's gradient runs back through (0 = all)")
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--eval-frames", type=int, default=128)
+    ap.add_argument("--eval-frames", type=int, default=128, help="0: no evaluation")
     ap.add_argument("--train-snrs", default="0.161,0.15",
                     help="SNRs of the training frames, an equal share of each batch per SNR")
     ap.add_argument("--eval-snrs", default="0.161")
@@ -257,7 +257,7 @@ def main():
     w = extend_weights(w, args.T)
     if args.save:
         np.save(args.save, w.cpu().numpy())
-    for snr in [float(s) for s in args.eval_snrs.split(",") if s]:
+    for snr in [float(s) for s in args.eval_snrs.split(",") if s] if args.eval_frames > 0 else []:
         evaluate(spec, shifts, w, T_nms=args.T, frames=args.eval_frames, snr=snr)
 
 

@@ -617,21 +617,43 @@ __global__ void __launch_bounds__(256) k_nms_bwd(const NmsBwdArgs ba) {
 // unrolls) the partials are finite but their float32 sum can overflow; the
 // result saturates at the largest float32 instead of becoming infinite, so
 // it keeps its sign for the optimiser.
-__global__ void k_grad_reduce(const float *part, float *grad, int T, int mb, int per_row, int nsets,
-                              int64_t set_stride) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;  // (t, i, component)
-    if (e >= T * mb * 4) return;
-    const int comp = e & 3;
-    const int ti = e >> 2;
-    double s = 0.0;
+__global__ void __launch_bounds__(256) k_grad_reduce(const float *part, float *grad, int T, int mb, int per_row,
+                                                     int nsets, int64_t set_stride) {
+    // one workgroup per (sweep, row): each lane sums a fixed stride of the
+    // partials in double, then a fixed tree in LDS, so the sums are run-to-run
+    // identical
+    __shared__ double lds[4][256];
+    const int ti = (int)blockIdx.x;  // t * mb + i
+    const int tid = (int)threadIdx.x;
+    if (ti >= T * mb) return;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
     for (int k = 0; k < nsets; ++k) {
-        const float *p = part + k * set_stride + (int64_t)ti * per_row * 4 + comp;
-        for (int i = 0; i < per_row; ++i) s += (double)p[(int64_t)i * 4];
+        const float4 *p = reinterpret_cast<const float4 *>(part + k * set_stride + (int64_t)ti * per_row * 4);
+        for (int r = tid; r < per_row; r += 256) {
+            const float4 v = p[r];
+            s[0] += (double)v.x;
+            s[1] += (double)v.y;
+            s[2] += (double)v.z;
+            s[3] += (double)v.w;
+        }
     }
-    constexpr double kMax = 3.4028234663852886e38;  // largest float32
-    s = s > kMax ? kMax : s < -kMax ? -kMax : s;
-    // part components: 0 dalpha(type 1), 1 dbeta(type 1), 2 dalpha(degree 1), 3 dbeta(degree 1)
-    grad[(int64_t)ti * 4 + comp] = (float)s;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) lds[c][tid] = s[c];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) lds[c][tid] += lds[c][tid + w];
+        }
+        __syncthreads();
+    }
+    if (tid < 4) {
+        constexpr double kMax = 3.4028234663852886e38;  // largest float32
+        double v = lds[tid][0];
+        v = v > kMax ? kMax : v < -kMax ? -kMax : v;
+        // components: 0 dalpha(type 1), 1 dbeta(type 1), 2 dalpha(degree 1), 3 dbeta(degree 1)
+        grad[(int64_t)ti * 4 + tid] = (float)v;
+    }
 }
 
 // Adam (Kingma & Ba): m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
@@ -783,9 +805,10 @@ hipError_t qm_launch_bce(const float *A, const float *Ad, const uint8_t *X, floa
 hipError_t qm_launch_grad_reduce(const float *part, float *grad, int T, int mb, int per_row, int nsets,
                                  size_t set_stride, hipStream_t s) {
     if (nsets < 1) return hipErrorInvalidValue;
-    const int n = T * mb * 4;
-    hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, grad, T, mb, per_row,
-                       nsets, (int64_t)set_stride);
+    if ((set_stride & 3) != 0 || (reinterpret_cast<uintptr_t>(part) & 15) != 0) return hipErrorInvalidValue;
+    if (T * mb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)(T * mb)), dim3(256), 0, s, part, grad, T, mb, per_row, nsets,
+                       (int64_t)set_stride);
     return hipGetLastError();
 }
 

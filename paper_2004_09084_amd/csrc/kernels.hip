@@ -610,10 +610,11 @@ __global__ void __launch_bounds__(256) k_emit(const float *__restrict__ A, const
     __shared__ int32_t s_fr[64];
     const int FT = 1 << ftl;
     const int tid = threadIdx.x;
-    const int64_t items = ((N + kRun - 1) / kRun) * ntiles;
-    for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
-        const int tile = (int)(it % ntiles);
-        const int64_t v0 = (it / ntiles) * kRun;
+    // item arithmetic in 32 bits (the launcher checks the item count)
+    const uint32_t items = (uint32_t)((N + kRun - 1) / kRun) * (uint32_t)ntiles;
+    for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
+        const int tile = (int)(it % (uint32_t)ntiles);
+        const int64_t v0 = (int64_t)(it / (uint32_t)ntiles) * kRun;
         __syncthreads();  // the previous item is done with s_fr and lds
         if (tid < FT) s_fr[tid] = emit[tile * FT + tid];
         __syncthreads();
@@ -655,12 +656,14 @@ __global__ void __launch_bounds__(256) k_emit_d1(float *__restrict__ A, const fl
                                                  int ftl, int ntiles, int chunks, int mb, int64_t strideA,
                                                  int64_t strideM) {
     if (ctl[4] == 0) return;
-    const int64_t items = (int64_t)ntiles * chunks * mb;
-    for (int64_t b = blockIdx.x; b < items; b += gridDim.x) {
-        const int tile = (int)(b % ntiles);
-        const int64_t rest = b / ntiles;
-        const int chunk = (int)(rest % chunks);
-        const int rs = (int)(rest / chunks);
+    // item arithmetic in 32 bits (the launcher checks the item count): a
+    // 64-bit division per item would cost more than the item's own work
+    const uint32_t items = (uint32_t)ntiles * (uint32_t)chunks * (uint32_t)mb;
+    for (uint32_t b = blockIdx.x; b < items; b += gridDim.x) {
+        const int tile = (int)(b % (uint32_t)ntiles);
+        const uint32_t rest = b / (uint32_t)ntiles;
+        const int chunk = (int)(rest % (uint32_t)chunks);
+        const int rs = (int)(rest / (uint32_t)chunks);
         const int idx = chunk * (int)blockDim.x + (int)threadIdx.x;
         if (idx >= (Z << ftl)) continue;
         const int k = idx >> ftl;
@@ -1017,6 +1020,7 @@ hipError_t qm_launch_emit_d1(float *A, const float *Ad, const int32_t *emit, con
     const int chunks = ((g.Z << g.ft_log2) + 255) / 256;
     const int64_t items = (int64_t)g.ntiles * mb * chunks;
     if (items == 0) return hipSuccess;
+    if (items >= (1LL << 31)) return hipErrorInvalidValue;
     const unsigned blocks = (unsigned)std::min<int64_t>(items, 2048);
     const int64_t sA = (int64_t)g.n << g.ft_log2, sM = (int64_t)g.m << g.ft_log2;
 #define QM_ED(T)                                                                                                   \
@@ -1037,6 +1041,7 @@ hipError_t qm_launch_emit(const float *A, const int32_t *emit, const int32_t *ct
     if ((1 << g.ft_log2) > 64) return hipErrorInvalidValue;
     const int64_t items = ((g.n + kRun - 1) / kRun) * g.ntiles;
     if (items == 0) return hipSuccess;
+    if (items >= (1LL << 31)) return hipErrorInvalidValue;
     const unsigned blocks = (unsigned)std::min<int64_t>(items, 4096);
     const size_t lds = ((size_t)(kRun + 1) << g.ft_log2) * 4;
     hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(256), lds, s, A, emit, ctl, app, hard, g.n, g.ft_log2, g.ntiles);

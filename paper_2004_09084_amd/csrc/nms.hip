@@ -391,15 +391,16 @@ __global__ void __launch_bounds__(256) k_bce(const float *__restrict__ A, const 
                                              int F, float inv_norm) {
     __shared__ float lds[8];
     const int FT = 1 << ftl;
-    const int64_t items = (int64_t)ntiles * chunks * (ncols + mb);
+    // item arithmetic in 32 bits (the launcher checks the item count)
+    const uint32_t items = (uint32_t)ntiles * (uint32_t)chunks * (uint32_t)(ncols + mb);
     const int lanes = (Z << ftl) / V;  // lanes of one item
     float l = 0.0f;
 #pragma unroll 2
-    for (int64_t b = blockIdx.x; b < items; b += gridDim.x) {
-        const int tile = (int)(b % ntiles);
-        const int64_t rest = b / ntiles;
-        const int chunk = (int)(rest % chunks);
-        const int unit = (int)(rest / chunks);
+    for (uint32_t b = blockIdx.x; b < items; b += gridDim.x) {
+        const int tile = (int)(b % (uint32_t)ntiles);
+        const uint32_t rest = b / (uint32_t)ntiles;
+        const int chunk = (int)(rest % (uint32_t)chunks);
+        const int unit = (int)(rest / (uint32_t)chunks);
         const int idx = chunk * (int)blockDim.x + (int)threadIdx.x;
         if (idx >= lanes) continue;
         const int e0 = idx * V;  // k * FT + first frame of the lane
@@ -789,6 +790,7 @@ hipError_t qm_launch_bce(const float *A, const float *Ad, const uint8_t *X, floa
                          float weight, int accumulate, float *loss, hipStream_t s) {
     const int chunks = bce_chunks(g);
     const int blocks = qm_bce_blocks(ncols, mb, g);
+    if ((int64_t)g.ntiles * chunks * (ncols + mb) >= (1LL << 31)) return hipErrorInvalidValue;
     const float inv = weight / ((float)F * (float)g.n);
     if (bce_frames_per_lane(g) == 4)
         hipLaunchKernelGGL(k_bce<4>, dim3((unsigned)blocks), dim3(256), 0, s, A, Ad, X, gA, gAd, part, cols, ncols,

@@ -43,7 +43,6 @@ struct EtLane {
     const uint8_t *PS;        // this tile's packed syndrome bits per check
     int jl;                   // lane index in its check's lane group
     int lpl;                  // log2(lanes per check)
-    int esz;                  // bytes per packed field
 };
 
 // Hard decisions [v < 0] of the FT frames of this lane's check (its lane
@@ -116,7 +115,7 @@ struct D1Band<_Float16> {
 // the exact sum is formed from LLR_d (kept per check in Ad).  The APP
 // itself is formed only for the frames that stop (qm_launch_emit_d1, with
 // the same arithmetic): A's degree-1 slot keeps clip(S) with r_d's sign.
-template <typename MsgT, int FPL, bool MASKED>
+template <typename MsgT, int FPL, bool MASKED, typename PW>
 __device__ __forceinline__ void d1_early(const LaneCtx &c, ConstRowDesc *rd, const EtLane<FPL> &et,
                                          const float (&kap)[FPL], const bool (&neg)[FPL], const float (&acc)[FPL],
                                          uint64_t sw, uint32_t row_so, uint32_t col_bytes) {
@@ -154,7 +153,7 @@ __device__ __forceinline__ void d1_early(const LaneCtx &c, ConstRowDesc *rd, con
     const uint32_t off = shifted_off(c, rd->d1shift);
     store_live<MsgIO<float>, FPL, 0, MASKED>(c.rA, off, (uint32_t)rd->d1col * col_bytes, sd, et);
     const uint64_t w = group_signs<FPL>(bits, et.lpl);
-    if (et.leader) store_packed(et.Pd, (int64_t)rd->row * c.Z + c.k, et.esz, w);
+    if (et.leader) reinterpret_cast<PW *>(et.Pd)[(int64_t)rd->row * c.Z + c.k] = (PW)w;
 }
 
 // Update modes of the check kernel.
@@ -164,7 +163,7 @@ constexpr int kFlood = 2;    // flooding: messages only, the APPs of the previou
 
 // MASK (early termination only): some frame of the tile has stopped, so
 // stores go through the per-frame live mask; otherwise they are plain.
-template <typename MsgT, int D, int FPL, int AUX, int MODE, bool MASK>
+template <typename MsgT, int D, int FPL, int AUX, int MODE, bool MASK, typename PW>
 __device__ __forceinline__ void check_update(const LaneCtx &c, ConstRowDesc *rd, int last, const EtLane<FPL> &et) {
     constexpr bool ET = MODE == kEarly;
     constexpr bool MASKED = ET && MASK;
@@ -193,7 +192,7 @@ __device__ __forceinline__ void check_update(const LaneCtx &c, ConstRowDesc *rd,
     float lam[FPL];
     bload_f32<FPL, AUX>(c.rK, vo4, row_so, kap);
     uint64_t sw = 0;
-    if constexpr (ET) sw = load_packed(et.PS, (int64_t)rd->row * c.Z + c.k, et.esz);
+    if constexpr (ET) sw = (uint64_t)reinterpret_cast<const PW *>(et.PS)[(int64_t)rd->row * c.Z + c.k];
     // sign parities are per-lane booleans (lane masks in scalar registers)
     bool neg[FPL];
 #pragma unroll
@@ -245,7 +244,7 @@ __device__ __forceinline__ void check_update(const LaneCtx &c, ConstRowDesc *rd,
 
     }
     if constexpr (ET) {
-        if (d1col >= 0) d1_early<MsgT, FPL, MASKED>(c, rd, et, kap, neg, acc, sw, row_so, col_bytes);
+        if (d1col >= 0) d1_early<MsgT, FPL, MASKED, PW>(c, rd, et, kap, neg, acc, sw, row_so, col_bytes);
     } else if (last && d1col >= 0) {
         const uint32_t off = shifted_off(c, d1shift);
         const uint32_t so = (uint32_t)d1col * col_bytes;
@@ -263,22 +262,23 @@ __device__ __forceinline__ void check_update(const LaneCtx &c, ConstRowDesc *rd,
     }
 }
 
-template <typename MsgT, int D, int FPL, int AUX, int MODE, bool MASK = false>
+template <typename MsgT, int D, int FPL, int AUX, int MODE, bool MASK = false, typename PW = uint8_t>
 __device__ __forceinline__ void dispatch_degree(int d, const LaneCtx &c, ConstRowDesc *rd, int last,
                                                 const EtLane<FPL> &et) {
     if constexpr (D >= 0) {
         if (d == D) {
-            check_update<MsgT, D, FPL, AUX, MODE, MASK>(c, rd, last, et);
+            check_update<MsgT, D, FPL, AUX, MODE, MASK, PW>(c, rd, last, et);
             return;
         }
-        dispatch_degree<MsgT, D - 1, FPL, AUX, MODE, MASK>(d, c, rd, last, et);
+        dispatch_degree<MsgT, D - 1, FPL, AUX, MODE, MASK, PW>(d, c, rd, last, et);
     }
 }
 
 // Thread mapping: workgroup -> (frame tile, row of the layer, chunk of
 // lanes); consecutive workgroups cycle through the frame tiles, so with 8
 // tiles each tile's lanes stay on one XCD under round-robin dispatch.
-template <typename MsgT, int MAXD, int FPL, int AUX, int MODE = kLayered>
+// PW (early termination): the packed field's word type, max(FT, 8) bits.
+template <typename MsgT, int MAXD, int FPL, int AUX, int MODE = kLayered, typename PW = uint8_t>
 __device__ __forceinline__ void layer_body(const LayerArgs &a, int b) {
     constexpr bool ET = MODE == kEarly;
     constexpr int FPLL = LogOf<FPL>::v;
@@ -328,16 +328,15 @@ __device__ __forceinline__ void layer_body(const LayerArgs &a, int b) {
         et.rAd = make_rsrc(a.Ad + (int64_t)tile * a.strideK, (uint32_t)(a.strideK * 4));
         et.lpl = lpl;
         et.leader = (idx & ((1 << lpl) - 1)) == 0;
-        et.esz = qm_pack_bytes(c.ftl);
-        et.Pd = a.Pd + (int64_t)tile * (a.strideK >> c.ftl) * et.esz;
-        et.PS = a.PS + (int64_t)tile * (a.strideK >> c.ftl) * et.esz;
+        et.Pd = a.Pd + (int64_t)tile * (a.strideK >> c.ftl) * (int64_t)sizeof(PW);
+        et.PS = a.PS + (int64_t)tile * (a.strideK >> c.ftl) * (int64_t)sizeof(PW);
         et.jl = idx & ((1 << lpl) - 1);
     }
     if constexpr (ET) {
         // a wave-uniform choice: tiles whose frames all decode (the common
         // case) take the body without per-frame masks
-        if (et.tile_full) dispatch_degree<MsgT, MAXD, FPL, AUX, MODE, false>(rd->d, c, rd, a.last, et);
-        else dispatch_degree<MsgT, MAXD, FPL, AUX, MODE, true>(rd->d, c, rd, a.last, et);
+        if (et.tile_full) dispatch_degree<MsgT, MAXD, FPL, AUX, MODE, false, PW>(rd->d, c, rd, a.last, et);
+        else dispatch_degree<MsgT, MAXD, FPL, AUX, MODE, true, PW>(rd->d, c, rd, a.last, et);
     } else {
         dispatch_degree<MsgT, MAXD, FPL, AUX, MODE>(rd->d, c, rd, a.last, et);
     }
@@ -357,10 +356,10 @@ template <int MAXD>
 struct EtWaves {
     static constexpr int v = MAXD <= 5 ? 8 : MAXD <= 8 ? 6 : 1;
 };
-template <typename MsgT, int MAXD, int FPL, int AUX>
+template <typename MsgT, int MAXD, int FPL, int AUX, typename PW>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EtWaves<MAXD>::v)))
 k_layer_sp_et(const LayerArgs a) {
-    layer_body<MsgT, MAXD, FPL, AUX, kEarly>(a, (int)blockIdx.x);
+    layer_body<MsgT, MAXD, FPL, AUX, kEarly, PW>(a, (int)blockIdx.x);
 }
 
 // The check half of a flooding iteration: every row of the code in one
@@ -393,9 +392,16 @@ struct LayerSp {
     }
 };
 struct LayerSpEt {
+    // one kernel per packed word width, so that every packed load and store
+    // is one plain access of that width
     template <typename T, int D, int P, int H>
     static void go(dim3 g, dim3 b, hipStream_t s, const LayerArgs &a) {
-        hipLaunchKernelGGL((k_layer_sp_et<T, D, P, H>), g, b, a.shmem, s, a);
+        switch (qm_pack_bytes(a.ft_log2)) {
+            case 1: hipLaunchKernelGGL((k_layer_sp_et<T, D, P, H, uint8_t>), g, b, a.shmem, s, a); break;
+            case 2: hipLaunchKernelGGL((k_layer_sp_et<T, D, P, H, uint16_t>), g, b, a.shmem, s, a); break;
+            case 4: hipLaunchKernelGGL((k_layer_sp_et<T, D, P, H, uint32_t>), g, b, a.shmem, s, a); break;
+            default: hipLaunchKernelGGL((k_layer_sp_et<T, D, P, H, uint64_t>), g, b, a.shmem, s, a); break;
+        }
     }
 };
 struct LayerFlood {

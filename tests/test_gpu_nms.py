@@ -214,8 +214,8 @@ def test_training_lowers_the_loss_on_unseen_frames():
     assert lt < 0.85 * lp
 
 
-@pytest.mark.parametrize("T,every,window", [(5, True, 1), (5, True, 3), (5, False, 2), (25, True, 1), (25, True, 3),
-                                           (25, False, 25)])
+@pytest.mark.parametrize("T,every,window", [(1, True, 1), (2, True, 2), (3, True, 1), (5, True, 1), (5, True, 3),
+                                           (5, False, 2), (25, True, 1), (25, True, 3), (25, False, 25)])
 def test_nms_train_grad_matches_oracle(T, every, window):
     # the general objective (final-sweep loss or the mean over sweeps, each
     # term's gradient through a window of sweeps) against the oracle, up to

@@ -220,3 +220,12 @@ def test_early_fullsize_frames_equal_fixed_decodes():
     say("oracle frame", f0, "iters", int(ito[0]), "gpu", int(it[f0]))
     assert int(ito[0]) == int(it[f0]) and flo[0] == fl[f0]
     assert np.array_equal(ho[0], hard[f0])
+    # the first 16 frames against the oracle's early-stopping decode: the
+    # same stopping sweep, flag and 10^6 hard decisions, frame by frame
+    frames = list(range(16))
+    _, ho, flo, ito = oracle.decode_sp_early(wl.shifts, spec.Z, wl.llr[frames], wl.s[frames], T, threads=8)
+    say("oracle iters", ito.tolist(), "gpu", it[frames].tolist())
+    assert np.array_equal(ito, it[frames]) and np.array_equal(flo, fl[frames])
+    for i, f in enumerate(frames):
+        assert np.array_equal(ho[i], hard[f]), f"frame {f}"
+

@@ -229,3 +229,33 @@ def test_early_fullsize_frames_equal_fixed_decodes():
     for i, f in enumerate(frames):
         assert np.array_equal(ho[i], hard[f]), f"frame {f}"
 
+
+def test_early_fullsize_fp16_against_oracle():
+    # binary16 messages with early termination at n = 10^6 (128 frames, SNR
+    # 0.6): the first 8 frames stop at the oracle's binary16-mode count with
+    # its flag, and a converged frame's hard decisions and APPs agree with
+    # it (APPs within the FP32 tolerance plus the binary16 allowance)
+    import torch
+    T = 60
+    spec = W.RATE01
+    wl = W.build(spec, 128, snr=0.6, frame_seed=3)
+    code = Q.Code(wl.shifts, spec.Z)
+    dec = Q.Decoder([code], [128], flags=Q.QM_EARLY_STOP | Q.QM_MSG_FP16)
+    hard, app, fl, it = dec.decode_early(to_dev(wl.llr), to_dev(wl.s), T)
+    torch.cuda.synchronize()
+    it, fl = it.cpu().numpy(), fl.cpu().numpy()
+    hard = hard.cpu().numpy().reshape(128, -1)
+    app = app.cpu().numpy().reshape(128, -1)
+    frames = list(range(8))
+    appo, ho, flo, ito = oracle.decode_sp_early(wl.shifts, spec.Z, wl.llr[frames], wl.s[frames], T,
+                                                fp16_messages=True, threads=8)
+    say("oracle binary16 iters", ito.tolist(), "gpu", it[frames].tolist())
+    assert np.array_equal(ito, it[frames]) and np.array_equal(flo, fl[frames])
+    for i, f in enumerate(frames):
+        rows = compare(app[f:f + 1], hard[f:f + 1], fl[f:f + 1], appo[i:i + 1], ho[i:i + 1], flo[i:i + 1],
+                       extra=FP16_EXTRA)
+        assert rows[0]["bits_diff_confident"] == 0 and rows[0]["flag_o"] == rows[0]["flag_g"], (f, rows[0])
+        if rows[0]["flag_o"]:
+            # a converged frame: every hard decision and every APP in tolerance
+            assert rows[0]["bits_diff"] == 0 and rows[0]["app_viol"] == 0, (f, rows[0])
+

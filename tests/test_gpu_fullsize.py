@@ -125,6 +125,41 @@ def test_fullsize_minsum_first_sweeps(snr, sweeps):
     torch.cuda.empty_cache()
 
 
+def test_fullsize_minsum_early_stop_against_oracle():
+    # plain min-sum (alpha 1, beta 0) with the per-sweep syndrome test, the
+    # evaluation decoder of the learned form, over the 128-frame rate-0.1
+    # batch at SNR 0.6 (where it converges within a few sweeps): the first 8
+    # frames stop at the oracle's count with its flag, and their hard
+    # decisions and APPs agree with it
+    import torch
+    spec = W.RATE01
+    T = 20
+    frames = list(range(8))
+    wl = W.build(spec, F, graph_seed=0, frame_seed=0, snr=0.6)
+    code = Q.Code(wl.shifts, spec.Z)
+    dec = Q.Decoder([code], [F])
+    dec.nms_bind(T, train=False)
+    w = np.zeros((T, spec.mb, 2, 2), dtype=np.float32)
+    w[..., 0] = 1.0
+    hard, app, fl, it = dec.nms_decode(to_dev(w), to_dev(wl.llr), to_dev(wl.s), T, early_stop=True)
+    torch.cuda.synchronize()
+    hard = hard.cpu().numpy().reshape(F, -1)
+    app = app.cpu().numpy().reshape(F, -1)
+    fl, it = fl.cpu().numpy(), it.cpu().numpy()
+    del dec
+    torch.cuda.empty_cache()
+    appo, hardo, flo, ito = oracle.nms_decode(wl.shifts, spec.Z, wl.llr[frames], wl.s[frames], T,
+                                              np.ones((T, spec.mb, 2)), np.zeros((T, spec.mb, 2)),
+                                              early_stop=True, threads=8)
+    say("min-sum early stop: oracle iters", ito.tolist(), "gpu", it[frames].tolist())
+    assert np.array_equal(ito, it[frames]) and np.array_equal(flo, fl[frames])
+    rows = compare(app[frames], hard[frames], fl[frames], appo, hardo, flo)
+    for r in rows:
+        assert r["flag_o"] == r["flag_g"] and r["bits_diff_confident"] == 0, r
+        if r["flag_o"]:
+            assert r["bits_diff"] == 0 and r["app_viol"] == 0, r
+
+
 def test_fullsize_mixed_fp16_batch():
     # the mixed batch (64 rate-0.1 + 32 rate-0.05 + 32 rate-0.02 frames,
     # frame seed 1) with binary16 messages: after one and two sweeps each

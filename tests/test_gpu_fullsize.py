@@ -160,6 +160,38 @@ def test_fullsize_minsum_early_stop_against_oracle():
             assert r["bits_diff"] == 0 and r["app_viol"] == 0, r
 
 
+@pytest.mark.parametrize("snr,T", [(0.161, 1), (0.161, 2), (0.6, 10)])
+def test_fullsize_flooding_against_oracle(snr, T):
+    # the flooding schedule over the 128-frame rate-0.1 batch against the
+    # oracle on sampled frames: after one or two iterations at SNR 0.161
+    # every APP in tolerance; after 10 at SNR 0.6 (converged frames) flags,
+    # all hard decisions and every APP
+    import torch
+    spec = W.RATE01
+    frames = [0, 77]
+    wl = W.build(spec, F, graph_seed=0, frame_seed=0, snr=snr)
+    code = Q.Code(wl.shifts, spec.Z)
+    dec = Q.Decoder([code], [F], flags=Q.QM_FLOODING)
+    hard, app, fl = dec.decode(to_dev(wl.llr), to_dev(wl.s), T)
+    torch.cuda.synchronize()
+    hard = hard.cpu().numpy().reshape(F, -1)
+    app = app.cpu().numpy().reshape(F, -1)
+    fl = fl.cpu().numpy()
+    del dec
+    torch.cuda.empty_cache()
+    appo, hardo, flo, _ = oracle.decode_flood(wl.shifts, spec.Z, wl.llr[frames], wl.s[frames], T, threads=2)
+    rows = compare(app[frames], hard[frames], fl[frames], appo, hardo, flo)
+    say(f"flooding SNR {snr} T={T}", rows)
+    for r in rows:
+        assert r["flag_o"] == r["flag_g"] and r["bits_diff_confident"] == 0, r
+        if T <= 2 or r["flag_o"]:
+            assert r["app_viol"] == 0, r
+        if r["flag_o"]:
+            assert r["bits_diff"] == 0, r
+    if snr == 0.6:
+        assert flo.all()
+
+
 def test_fullsize_mixed_fp16_batch():
     # the mixed batch (64 rate-0.1 + 32 rate-0.05 + 32 rate-0.02 frames,
     # frame seed 1) with binary16 messages: after one and two sweeps each

@@ -13,7 +13,7 @@ import pytest
 import oracle
 from paper_2004_09084_amd import qcmet as Q
 from paper_2004_09084_amd import workload as W
-from tests.gpu_util import APP_TOL, FP16_EXTRA, compare, say, to_dev
+from tests.gpu_util import APP_TOL, FP16_EXTRA, compare, precision_bound, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -158,6 +158,34 @@ def test_fullsize_minsum_early_stop_against_oracle():
         assert r["flag_o"] == r["flag_g"] and r["bits_diff_confident"] == 0, r
         if r["flag_o"]:
             assert r["bits_diff"] == 0 and r["app_viol"] == 0, r
+
+
+@pytest.mark.parametrize("T", [1, 2])
+def test_fullsize_fp8_first_sweeps(T):
+    # 8-bit float messages over the 128-frame rate-0.1 batch against the
+    # oracle's e4m3 mode on sampled frames, held to the allowances of the
+    # oracle-only perturbation study (tests/golden/make_precision_bounds.py)
+    import torch
+    b = precision_bound(f"fp8_layered_T{T}")
+    spec = W.RATE01
+    frames = [0, 77]
+    wl = W.build(spec, F, graph_seed=0, frame_seed=0, snr=0.161)
+    code = Q.Code(wl.shifts, spec.Z)
+    dec = Q.Decoder([code], [F], flags=Q.QM_MSG_FP8)
+    hard, app, fl = dec.decode(to_dev(wl.llr), to_dev(wl.s), T)
+    torch.cuda.synchronize()
+    hard = hard.cpu().numpy().reshape(F, -1)
+    app = app.cpu().numpy().reshape(F, -1)
+    fl = fl.cpu().numpy()
+    del dec
+    torch.cuda.empty_cache()
+    appo, hardo, flo, _ = oracle.decode_sp(wl.shifts, spec.Z, wl.llr[frames], wl.s[frames], T, fp8_messages=True,
+                                           threads=2)
+    rows = compare(app[frames], hard[frames], fl[frames], appo, hardo, flo)
+    say(f"full-size fp8 T={T}", [(r["strict_viol"] / spec.n, r["max_rel"]) for r in rows])
+    for r in rows:
+        assert r["flag_o"] == r["flag_g"], r
+        assert r["strict_viol"] / spec.n <= b["bound_max_frac"] and r["max_rel"] <= b["bound_max_rel"], r
 
 
 @pytest.mark.parametrize("snr,T", [(0.161, 1), (0.161, 2), (0.6, 10)])

@@ -220,6 +220,48 @@ def test_fullsize_flooding_against_oracle(snr, T):
         assert flo.all()
 
 
+@pytest.mark.parametrize("every,window", [(True, 2), (False, 4)])
+def test_fullsize_training_gradient_against_oracle(every, window):
+    # the training step's loss and weight gradient at the configured batch
+    # (16 frames of 10^6 bits, rate 0.1) through 4 unrolled sweeps, against
+    # the oracle's same objective on the same frames (SNR 0.3, where the
+    # unrolled dynamics settle).  Each gradient component sums about 10^6
+    # per-edge terms here (about 3000 on the small code), so float32-level
+    # differences add up: the allowance adds twice the largest change of the
+    # oracle's own gradient when its LLRs move by 2e-6 relative (the FP32
+    # path's error level), computed here
+    import torch
+    spec = W.RATE01
+    Ft, T = 16, 4
+    wl = W.build(spec, Ft, graph_seed=0, frame_seed=4, snr=0.3)
+    rng = np.random.default_rng(3)
+    w = np.stack([rng.uniform(0.7, 1.0, (T, spec.mb, 2)), rng.uniform(0.0, 0.2, (T, spec.mb, 2))],
+                 axis=-1).astype(np.float32)
+    code = Q.Code(wl.shifts, spec.Z)
+    dec = Q.Decoder([code], [Ft])
+    dec.nms_bind(T, train=True)
+    loss, grad, clamped = dec.nms_train_grad(to_dev(w), to_dev(wl.llr), to_dev(wl.s), to_dev(wl.x), T, every, window)
+    torch.cuda.synchronize()
+    loss, grad, clamped = float(loss.cpu()), grad.cpu().numpy().reshape(T, spec.mb, 2, 2), int(clamped.cpu())
+    del dec
+    torch.cuda.empty_cache()
+    lo, ga, gb, _ = oracle.nms_train_grad(wl.shifts, spec.Z, wl.llr, wl.s, wl.x, T, w[..., 0].astype(np.float64),
+                                          w[..., 1].astype(np.float64), every, window, threads=8)
+    u = np.random.default_rng(11).uniform(-1.0, 1.0, wl.llr.shape)
+    Lp = (wl.llr.astype(np.float64) * (1.0 + 2e-6 * u)).astype(np.float32)
+    _, gap, gbp, _ = oracle.nms_train_grad(wl.shifts, spec.Z, Lp, wl.s, wl.x, T, w[..., 0].astype(np.float64),
+                                           w[..., 1].astype(np.float64), every, window, threads=8)
+    say(f"full-size training every={every} window={window}: loss gpu {loss:.8f} oracle {lo:.8f}")
+    assert clamped == 0
+    assert abs(loss - lo) <= 1e-5 * abs(lo)
+    for comp, ref, refp in ((0, ga, gap), (1, gb, gbp)):
+        err = np.abs(grad[..., comp].astype(np.float64) - ref)
+        sens = np.abs(ref - refp).max()
+        lim = 1e-3 * np.abs(ref) + 2.0 * sens
+        say(f"grad comp {comp}: max |g| {np.abs(ref).max():.3e} max err {err.max():.3e} oracle sensitivity {sens:.3e}")
+        assert np.all(err <= lim), (comp, np.argwhere(err > lim)[:5])
+
+
 def test_fullsize_mixed_fp16_batch():
     # the mixed batch (64 rate-0.1 + 32 rate-0.05 + 32 rate-0.02 frames,
     # frame seed 1) with binary16 messages: after one and two sweeps each

@@ -646,9 +646,11 @@ __global__ void __launch_bounds__(256) k_emit(const float *__restrict__ A, const
 // APP_d = LLR_d + r_d, |r_d| = Phi(clip S) rounded to the message type: the
 // arithmetic the fixed-sweep layer kernel applies in its last sweep, so the
 // outputs are the same bits.  Frames that stop before any sweep keep the
-// channel LLR.  Grid-stride over (tile, row, chunk of 256 (check, frame)
-// pairs) items; a lane works only for a listed slot, and a call that lists
-// no slot (most of them) exits at once.
+// channel LLR.  Grid-stride over (tile, chunk of 256 (check, frame) pairs)
+// items, each lane walking the rows; a lane works only for a listed slot,
+// and a call that lists no slot (most of them) exits at once.
+constexpr int kEmitRows = 4;  // rows per pass of k_emit_d1
+
 template <typename MsgT>
 __global__ void __launch_bounds__(256) k_emit_d1(float *__restrict__ A, const float *__restrict__ Ad,
                                                  const int32_t *__restrict__ emit, const int32_t *ctl,
@@ -656,29 +658,49 @@ __global__ void __launch_bounds__(256) k_emit_d1(float *__restrict__ A, const fl
                                                  int ftl, int ntiles, int chunks, int mb, int64_t strideA,
                                                  int64_t strideM) {
     if (ctl[4] == 0) return;
-    // item arithmetic in 32 bits (the launcher checks the item count): a
-    // 64-bit division per item would cost more than the item's own work
-    const uint32_t items = (uint32_t)ntiles * (uint32_t)chunks * (uint32_t)mb;
-    for (uint32_t b = blockIdx.x; b < items; b += gridDim.x) {
-        const int tile = (int)(b % (uint32_t)ntiles);
-        const uint32_t rest = b / (uint32_t)ntiles;
-        const int chunk = (int)(rest % (uint32_t)chunks);
-        const int rs = (int)(rest / (uint32_t)chunks);
+    // workgroups stride over (tile, chunk) pairs; each lane then walks the
+    // rows, kEmitRows at a time with all their loads issued first (rows have
+    // distinct degree-1 columns, so they never touch the same element).  The
+    // pair index is split once per pair, not per row: as a per-item
+    // division it cost more scalar instructions than the item's own work.
+    const uint32_t pairs = (uint32_t)ntiles * (uint32_t)chunks;
+    const int FT = 1 << ftl;
+    for (uint32_t pr = blockIdx.x; pr < pairs; pr += gridDim.x) {
+        const int tile = (int)(pr % (uint32_t)ntiles);
+        const int chunk = (int)(pr / (uint32_t)ntiles);
         const int idx = chunk * (int)blockDim.x + (int)threadIdx.x;
         if (idx >= (Z << ftl)) continue;
         const int k = idx >> ftl;
-        const int fl = idx & ((1 << ftl) - 1);
+        const int fl = idx & (FT - 1);
         const int f = emit[(tile << ftl) + fl];
         if (f < 0 || iters[f] == 0) continue;
-        ConstRowDesc *rd = as_const(rows + rs);
-        if (rd->d1col < 0) continue;
-        int v = k + rd->d1shift;
-        v = v >= Z ? v - Z : v;
-        const int64_t oa = (int64_t)tile * strideA + (((int64_t)rd->d1col * Z + v) << ftl) + fl;
-        const int64_t od = (int64_t)tile * strideM + (((int64_t)rd->row * Z + k) << ftl) + fl;
-        const float sd = A[oa];
-        const float mag = qm_phi(qm_clip(fabsf(sd)));
-        A[oa] = Ad[od] + MsgIO<MsgT>::round(sd < 0.0f ? -mag : mag);
+        const int64_t baseA = (int64_t)tile * strideA + fl, baseM = (int64_t)tile * strideM + fl;
+        for (int r0 = 0; r0 < mb; r0 += kEmitRows) {
+            int64_t oa[kEmitRows], od[kEmitRows];
+            bool on[kEmitRows];
+            float sd[kEmitRows], lam[kEmitRows];
+#pragma unroll
+            for (int u = 0; u < kEmitRows; ++u) {
+                const int rs = r0 + u < mb ? r0 + u : mb - 1;
+                ConstRowDesc *rd = as_const(rows + rs);
+                on[u] = r0 + u < mb && rd->d1col >= 0;
+                int v = k + rd->d1shift;
+                v = v >= Z ? v - Z : v;
+                oa[u] = on[u] ? baseA + ((((int64_t)rd->d1col * Z + v)) << ftl) : baseA;
+                od[u] = baseM + (((int64_t)rd->row * Z + k) << ftl);
+            }
+#pragma unroll
+            for (int u = 0; u < kEmitRows; ++u) {
+                sd[u] = A[oa[u]];
+                lam[u] = Ad[od[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < kEmitRows; ++u) {
+                if (!on[u]) continue;
+                const float mag = qm_phi(qm_clip(fabsf(sd[u])));
+                A[oa[u]] = lam[u] + MsgIO<MsgT>::round(sd[u] < 0.0f ? -mag : mag);
+            }
+        }
     }
 }
 
@@ -1018,10 +1040,10 @@ hipError_t qm_launch_emit_d1(float *A, const float *Ad, const int32_t *emit, con
                             const RowDesc *rows, int mb, int msgk, const TileGeom &g, hipStream_t s) {
     if ((1 << g.ft_log2) > 64) return hipErrorInvalidValue;
     const int chunks = ((g.Z << g.ft_log2) + 255) / 256;
-    const int64_t items = (int64_t)g.ntiles * mb * chunks;
-    if (items == 0) return hipSuccess;
-    if (items >= (1LL << 31)) return hipErrorInvalidValue;
-    const unsigned blocks = (unsigned)std::min<int64_t>(items, 2048);
+    const int64_t pairs = (int64_t)g.ntiles * chunks;
+    if (pairs == 0 || mb == 0) return hipSuccess;
+    if (pairs >= (1LL << 31)) return hipErrorInvalidValue;
+    const unsigned blocks = (unsigned)std::min<int64_t>(pairs, 2048);
     const int64_t sA = (int64_t)g.n << g.ft_log2, sM = (int64_t)g.m << g.ft_log2;
 #define QM_ED(T)                                                                                                   \
     hipLaunchKernelGGL(k_emit_d1<T>, dim3(blocks), dim3(256), 0, s, A, Ad, emit, ctl, iters, rows, g.Z, g.ft_log2, \

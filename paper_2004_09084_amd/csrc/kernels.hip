@@ -610,6 +610,10 @@ __global__ void __launch_bounds__(256) k_emit(const float *__restrict__ A, const
     __shared__ int32_t s_fr[64];
     const int FT = 1 << ftl;
     const int tid = threadIdx.x;
+    // vector stores where every row of the outputs starts 16-byte (APP) and
+    // 4-byte (hard) aligned
+    const bool vec = (N & 3) == 0 && (reinterpret_cast<uintptr_t>(app) & 15u) == 0 &&
+                     (reinterpret_cast<uintptr_t>(hard) & 3u) == 0;
     // item arithmetic in 32 bits (the launcher checks the item count)
     const uint32_t items = (uint32_t)((N + kRun - 1) / kRun) * (uint32_t)ntiles;
     for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
@@ -622,18 +626,51 @@ __global__ void __launch_bounds__(256) k_emit(const float *__restrict__ A, const
         for (int fl = 0; fl < FT; ++fl) any = any || s_fr[fl] >= 0;
         if (!any) continue;
         const float *a = A + ((int64_t)tile * N + v0) * FT;
-        for (int e = tid; e < (kRun << ftl); e += 256) {
-            const int vv = e >> ftl;
-            lds[(e & (FT - 1)) * (kRun + 1) + vv] = (v0 + vv < N) ? a[e] : 0.0f;
+        if (FT >= 4) {
+            // 16-byte loads: four frames of one node per lane
+            const float4 *a4 = reinterpret_cast<const float4 *>(a);
+            for (int e4 = tid; e4 < (kRun << ftl) / 4; e4 += 256) {
+                const int e = e4 * 4;
+                const int vv = e >> ftl;
+                const int fl = e & (FT - 1);
+                const float4 x = (v0 + vv < N) ? a4[e4] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                float *l = lds + fl * (kRun + 1) + vv;
+                l[0] = x.x;
+                l[kRun + 1] = x.y;
+                l[2 * (kRun + 1)] = x.z;
+                l[3 * (kRun + 1)] = x.w;
+            }
+        } else {
+            for (int e = tid; e < (kRun << ftl); e += 256) {
+                const int vv = e >> ftl;
+                lds[(e & (FT - 1)) * (kRun + 1) + vv] = (v0 + vv < N) ? a[e] : 0.0f;
+            }
         }
         __syncthreads();
-        for (int fl = tid / kRun; fl < FT; fl += 256 / kRun) {
-            const int f = s_fr[fl];
-            const int64_t v = v0 + (tid % kRun);
-            if (f >= 0 && v < N) {
-                const float x = lds[fl * (kRun + 1) + tid % kRun];
-                if (app) app[(int64_t)f * N + v] = x;
-                hard[(int64_t)f * N + v] = x < 0.0f ? 1 : 0;
+        if (vec) {
+            // four adjacent nodes per lane: 16-byte APP and 4-byte hard stores
+            constexpr int LPR = kRun / 4;  // lanes per frame
+            for (int fl = tid / LPR; fl < FT; fl += 256 / LPR) {
+                const int f = s_fr[fl];
+                const int j = (tid % LPR) * 4;
+                const int64_t v = v0 + j;  // N and v are multiples of 4, so v + 3 < N
+                if (f >= 0 && v < N) {
+                    const float *l = lds + fl * (kRun + 1) + j;
+                    const float4 x = make_float4(l[0], l[1], l[2], l[3]);
+                    if (app) *reinterpret_cast<float4 *>(app + (int64_t)f * N + v) = x;
+                    *reinterpret_cast<uchar4 *>(hard + (int64_t)f * N + v) =
+                        make_uchar4(x.x < 0.0f, x.y < 0.0f, x.z < 0.0f, x.w < 0.0f);
+                }
+            }
+        } else {
+            for (int fl = tid / kRun; fl < FT; fl += 256 / kRun) {
+                const int f = s_fr[fl];
+                const int64_t v = v0 + (tid % kRun);
+                if (f >= 0 && v < N) {
+                    const float x = lds[fl * (kRun + 1) + tid % kRun];
+                    if (app) app[(int64_t)f * N + v] = x;
+                    hard[(int64_t)f * N + v] = x < 0.0f ? 1 : 0;
+                }
             }
         }
     }

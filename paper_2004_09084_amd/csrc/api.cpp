@@ -931,8 +931,7 @@ int enqueue_early_slot(qm_decoder &d, Slot &s, int32_t T, uint8_t *hard, float *
         QM_HIP(qm_launch_pack_cols(A, PA, cols1, (int)s.cols1.size(), ctl, la.fpl, g, st));
         QM_HIP(qm_launch_syndrome_packed(PA, Pd, PS, b.rows, c.mb, b.fail, ctl, la.fpl, g, st));
         QM_HIP(qm_launch_et_plan(b.fail, act, tmask, map, perm, it, emit, flags, s.F, ctl, Fpad, g.ft_log2, t, 0, st));
-        QM_HIP(qm_launch_emit_d1(A, Ad, emit, ctl, it, b.rows, c.mb, msgk, g, st));
-        QM_HIP(qm_launch_emit(A, emit, ctl, app, hard, g, st));
+        QM_HIP(qm_launch_emit(A, Ad, emit, ctl, it, b.rows, c.mb, msgk, app, hard, g, st));
         if (g.ntiles > 1) {  // with one tile left no compaction can be planned
             QM_HIP(qm_launch_compact(arr, narr, perm, ctl, g.ft_log2, st));
             QM_HIP(qm_launch_pack_syndrome(S, PS, ctl, 1, la.fpl, g, st));
@@ -1027,8 +1026,7 @@ int enqueue_early_slot(qm_decoder &d, Slot &s, int32_t T, uint8_t *hard, float *
     }
     // frames still decoding ran all T sweeps and failed the last test
     QM_HIP(qm_launch_et_plan(b.fail, act, tmask, map, perm, it, emit, flags, s.F, ctl, Fpad, g.ft_log2, T, 1, st));
-    QM_HIP(qm_launch_emit_d1(A, Ad, emit, ctl, it, b.rows, c.mb, msgk, g, st));
-    QM_HIP(qm_launch_emit(A, emit, ctl, app, hard, g, st));
+    QM_HIP(qm_launch_emit(A, Ad, emit, ctl, it, b.rows, c.mb, msgk, app, hard, g, st));
     if (iters_out && s.F > 0)
         QM_HIP(hipMemcpyAsync(iters_out, it, (size_t)s.F * 4, hipMemcpyDeviceToDevice, st));
     return QM_OK;

@@ -600,16 +600,36 @@ __global__ void __launch_bounds__(256) k_et_plan(uint32_t *fail, uint32_t *act, 
 // their slots before any data moves: frame-major APPs and hard decisions
 // (step 4: c = [APP < 0]), as k_finalize writes them.  Grid-stride over
 // (run of kRun nodes, tile) items of the first ntiles tiles; a tile without
-// an emitted slot is skipped.  (LDS: FT x (kRun + 1) floats, dynamic.)
-__global__ void __launch_bounds__(256) k_emit(const float *__restrict__ A, const int32_t *__restrict__ emit,
-                                              const int32_t *ctl, float *__restrict__ app,
-                                              uint8_t *__restrict__ hard, int64_t N, int ftl, int ntiles) {
+// an emitted slot is skipped.
+// Degree-1 variables: while a frame decodes, A's slot of each degree-1
+// variable holds clip(S) with the sign of r_d (S the check's Phi-sum over its
+// degree>=2 edges in the frame's last sweep; k_layer_sp_et); the value
+// written out is APP_d = LLR_d + r_d, |r_d| = Phi(clip S) rounded to the
+// message type: the arithmetic the fixed-sweep layer kernel applies in its
+// last sweep, so the outputs are the same bits.  Frames that stop before any
+// sweep keep the channel LLR.  (LDS, dynamic: FT x (kRun + 1) floats, then
+// nb column -> row entries.)
+template <typename MsgT>
+__global__ void __launch_bounds__(256) k_emit(const float *__restrict__ A, const float *__restrict__ Ad,
+                                              const int32_t *__restrict__ emit, const int32_t *ctl,
+                                              const int32_t *__restrict__ iters, const RowDesc *rows, int mb, int nb,
+                                              int Z, float *__restrict__ app, uint8_t *__restrict__ hard, int64_t N,
+                                              int ftl, int ntiles, int64_t strideM) {
     if (ctl[4] == 0) return;
     extern __shared__ uint32_t dyn_lds[];
     float *lds = reinterpret_cast<float *>(dyn_lds);
+    int32_t *d1row = reinterpret_cast<int32_t *>(dyn_lds) + ((kRun + 1) << ftl);
     __shared__ int32_t s_fr[64];
+    __shared__ int32_t s_swept[64];  // the slot's frame is listed and ran at least one sweep
     const int FT = 1 << ftl;
     const int tid = threadIdx.x;
+    // block column -> the row (schedule index) whose degree-1 variable it is
+    for (int c = tid; c < nb; c += 256) d1row[c] = -1;
+    __syncthreads();
+    for (int r = tid; r < mb; r += 256) {
+        const int c = rows[r].d1col;
+        if (c >= 0) d1row[c] = r;
+    }
     // vector stores where every row of the outputs starts 16-byte (APP) and
     // 4-byte (hard) aligned
     const bool vec = (N & 3) == 0 && (reinterpret_cast<uintptr_t>(app) & 15u) == 0 &&
@@ -619,13 +639,18 @@ __global__ void __launch_bounds__(256) k_emit(const float *__restrict__ A, const
     for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
         const int tile = (int)(it % (uint32_t)ntiles);
         const int64_t v0 = (int64_t)(it / (uint32_t)ntiles) * kRun;
-        __syncthreads();  // the previous item is done with s_fr and lds
-        if (tid < FT) s_fr[tid] = emit[tile * FT + tid];
+        __syncthreads();  // the previous item is done with s_fr and lds (and d1row is complete)
+        if (tid < FT) {
+            const int f = emit[tile * FT + tid];
+            s_fr[tid] = f;
+            s_swept[tid] = f >= 0 && iters[f] > 0;
+        }
         __syncthreads();
         bool any = false;
         for (int fl = 0; fl < FT; ++fl) any = any || s_fr[fl] >= 0;
         if (!any) continue;
         const float *a = A + ((int64_t)tile * N + v0) * FT;
+        const float *ad = Ad + (int64_t)tile * strideM;
         if (FT >= 4) {
             // 16-byte loads: four frames of one node per lane
             const float4 *a4 = reinterpret_cast<const float4 *>(a);
@@ -633,17 +658,54 @@ __global__ void __launch_bounds__(256) k_emit(const float *__restrict__ A, const
                 const int e = e4 * 4;
                 const int vv = e >> ftl;
                 const int fl = e & (FT - 1);
-                const float4 x = (v0 + vv < N) ? a4[e4] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                const int64_t v = v0 + vv;
+                float x[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                if (v < N) {
+                    const float4 xv = a4[e4];
+                    x[0] = xv.x; x[1] = xv.y; x[2] = xv.z; x[3] = xv.w;
+                    const uint32_t vu = (uint32_t)v;  // n < 2^31
+                    const int c = (int)(vu / (uint32_t)Z);
+                    const int r = d1row[c];
+                    if (r >= 0) {
+                        int k = (int)(vu - (uint32_t)c * (uint32_t)Z) - rows[r].d1shift;
+                        k = k < 0 ? k + Z : k;
+                        const float4 lv = *reinterpret_cast<const float4 *>(
+                            ad + (((int64_t)rows[r].row * Z + k) << ftl) + fl);
+                        const float lam[4] = {lv.x, lv.y, lv.z, lv.w};
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            if (!s_swept[fl + i]) continue;
+                            const float mag = qm_phi(qm_clip(fabsf(x[i])));
+                            x[i] = lam[i] + MsgIO<MsgT>::round(x[i] < 0.0f ? -mag : mag);
+                        }
+                    }
+                }
                 float *l = lds + fl * (kRun + 1) + vv;
-                l[0] = x.x;
-                l[kRun + 1] = x.y;
-                l[2 * (kRun + 1)] = x.z;
-                l[3 * (kRun + 1)] = x.w;
+                l[0] = x[0];
+                l[kRun + 1] = x[1];
+                l[2 * (kRun + 1)] = x[2];
+                l[3 * (kRun + 1)] = x[3];
             }
         } else {
             for (int e = tid; e < (kRun << ftl); e += 256) {
                 const int vv = e >> ftl;
-                lds[(e & (FT - 1)) * (kRun + 1) + vv] = (v0 + vv < N) ? a[e] : 0.0f;
+                const int fl = e & (FT - 1);
+                const int64_t v = v0 + vv;
+                float x = 0.0f;
+                if (v < N) {
+                    x = a[e];
+                    const uint32_t vu = (uint32_t)v;  // n < 2^31
+                    const int c = (int)(vu / (uint32_t)Z);
+                    const int r = d1row[c];
+                    if (r >= 0 && s_swept[fl]) {
+                        int k = (int)(vu - (uint32_t)c * (uint32_t)Z) - rows[r].d1shift;
+                        k = k < 0 ? k + Z : k;
+                        const float lam = ad[(((int64_t)rows[r].row * Z + k) << ftl) + fl];
+                        const float mag = qm_phi(qm_clip(fabsf(x)));
+                        x = lam + MsgIO<MsgT>::round(x < 0.0f ? -mag : mag);
+                    }
+                }
+                lds[fl * (kRun + 1) + vv] = x;
             }
         }
         __syncthreads();
@@ -671,71 +733,6 @@ __global__ void __launch_bounds__(256) k_emit(const float *__restrict__ A, const
                     if (app) app[(int64_t)f * N + v] = x;
                     hard[(int64_t)f * N + v] = x < 0.0f ? 1 : 0;
                 }
-            }
-        }
-    }
-}
-
-// Degree-1 APPs of the frames that stopped in the last planning call, before
-// k_emit copies them out.  While a frame decodes, A's slot of each degree-1
-// variable holds clip(S) with the sign of r_d (S the check's Phi-sum over its
-// degree>=2 edges in the frame's last sweep; k_layer_sp_et); here it becomes
-// APP_d = LLR_d + r_d, |r_d| = Phi(clip S) rounded to the message type: the
-// arithmetic the fixed-sweep layer kernel applies in its last sweep, so the
-// outputs are the same bits.  Frames that stop before any sweep keep the
-// channel LLR.  Grid-stride over (tile, chunk of 256 (check, frame) pairs)
-// items, each lane walking the rows; a lane works only for a listed slot,
-// and a call that lists no slot (most of them) exits at once.
-constexpr int kEmitRows = 4;  // rows per pass of k_emit_d1
-
-template <typename MsgT>
-__global__ void __launch_bounds__(256) k_emit_d1(float *__restrict__ A, const float *__restrict__ Ad,
-                                                 const int32_t *__restrict__ emit, const int32_t *ctl,
-                                                 const int32_t *__restrict__ iters, const RowDesc *rows, int Z,
-                                                 int ftl, int ntiles, int chunks, int mb, int64_t strideA,
-                                                 int64_t strideM) {
-    if (ctl[4] == 0) return;
-    // workgroups stride over (tile, chunk) pairs; each lane then walks the
-    // rows, kEmitRows at a time with all their loads issued first (rows have
-    // distinct degree-1 columns, so they never touch the same element).  The
-    // pair index is split once per pair, not per row: as a per-item
-    // division it cost more scalar instructions than the item's own work.
-    const uint32_t pairs = (uint32_t)ntiles * (uint32_t)chunks;
-    const int FT = 1 << ftl;
-    for (uint32_t pr = blockIdx.x; pr < pairs; pr += gridDim.x) {
-        const int tile = (int)(pr % (uint32_t)ntiles);
-        const int chunk = (int)(pr / (uint32_t)ntiles);
-        const int idx = chunk * (int)blockDim.x + (int)threadIdx.x;
-        if (idx >= (Z << ftl)) continue;
-        const int k = idx >> ftl;
-        const int fl = idx & (FT - 1);
-        const int f = emit[(tile << ftl) + fl];
-        if (f < 0 || iters[f] == 0) continue;
-        const int64_t baseA = (int64_t)tile * strideA + fl, baseM = (int64_t)tile * strideM + fl;
-        for (int r0 = 0; r0 < mb; r0 += kEmitRows) {
-            int64_t oa[kEmitRows], od[kEmitRows];
-            bool on[kEmitRows];
-            float sd[kEmitRows], lam[kEmitRows];
-#pragma unroll
-            for (int u = 0; u < kEmitRows; ++u) {
-                const int rs = r0 + u < mb ? r0 + u : mb - 1;
-                ConstRowDesc *rd = as_const(rows + rs);
-                on[u] = r0 + u < mb && rd->d1col >= 0;
-                int v = k + rd->d1shift;
-                v = v >= Z ? v - Z : v;
-                oa[u] = on[u] ? baseA + ((((int64_t)rd->d1col * Z + v)) << ftl) : baseA;
-                od[u] = baseM + (((int64_t)rd->row * Z + k) << ftl);
-            }
-#pragma unroll
-            for (int u = 0; u < kEmitRows; ++u) {
-                sd[u] = A[oa[u]];
-                lam[u] = Ad[od[u]];
-            }
-#pragma unroll
-            for (int u = 0; u < kEmitRows; ++u) {
-                if (!on[u]) continue;
-                const float mag = qm_phi(qm_clip(fabsf(sd[u])));
-                A[oa[u]] = lam[u] + MsgIO<MsgT>::round(sd[u] < 0.0f ? -mag : mag);
             }
         }
     }
@@ -1073,37 +1070,27 @@ hipError_t qm_launch_et_plan(uint32_t *fail, uint32_t *act, uint64_t *tmask, int
     return hipGetLastError();
 }
 
-hipError_t qm_launch_emit_d1(float *A, const float *Ad, const int32_t *emit, const int32_t *ctl, const int32_t *iters,
-                            const RowDesc *rows, int mb, int msgk, const TileGeom &g, hipStream_t s) {
-    if ((1 << g.ft_log2) > 64) return hipErrorInvalidValue;
-    const int chunks = ((g.Z << g.ft_log2) + 255) / 256;
-    const int64_t pairs = (int64_t)g.ntiles * chunks;
-    if (pairs == 0 || mb == 0) return hipSuccess;
-    if (pairs >= (1LL << 31)) return hipErrorInvalidValue;
-    const unsigned blocks = (unsigned)std::min<int64_t>(pairs, 2048);
-    const int64_t sA = (int64_t)g.n << g.ft_log2, sM = (int64_t)g.m << g.ft_log2;
-#define QM_ED(T)                                                                                                   \
-    hipLaunchKernelGGL(k_emit_d1<T>, dim3(blocks), dim3(256), 0, s, A, Ad, emit, ctl, iters, rows, g.Z, g.ft_log2, \
-                       g.ntiles, chunks, mb, sA, sM)
-    switch (msgk) {
-        case QM_MSGK_F32: QM_ED(float); break;
-        case QM_MSGK_F16: QM_ED(_Float16); break;
-        case QM_MSGK_F8: QM_ED(Fp8Msg); break;
-        default: return hipErrorInvalidValue;
-    }
-#undef QM_ED
-    return hipGetLastError();
-}
-
-hipError_t qm_launch_emit(const float *A, const int32_t *emit, const int32_t *ctl, float *app, uint8_t *hard,
+hipError_t qm_launch_emit(const float *A, const float *Ad, const int32_t *emit, const int32_t *ctl,
+                          const int32_t *iters, const RowDesc *rows, int mb, int msgk, float *app, uint8_t *hard,
                           const TileGeom &g, hipStream_t s) {
-    if ((1 << g.ft_log2) > 64) return hipErrorInvalidValue;
+    if ((1 << g.ft_log2) > 64 || g.Z < 1 || g.n % g.Z != 0 || g.n >= (1LL << 31)) return hipErrorInvalidValue;
     const int64_t items = ((g.n + kRun - 1) / kRun) * g.ntiles;
     if (items == 0) return hipSuccess;
     if (items >= (1LL << 31)) return hipErrorInvalidValue;
+    const int nb = (int)(g.n / g.Z);
     const unsigned blocks = (unsigned)std::min<int64_t>(items, 4096);
-    const size_t lds = ((size_t)(kRun + 1) << g.ft_log2) * 4;
-    hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(256), lds, s, A, emit, ctl, app, hard, g.n, g.ft_log2, g.ntiles);
+    const size_t lds = (((size_t)(kRun + 1) << g.ft_log2) + (size_t)nb) * 4;
+    const int64_t sM = (int64_t)g.m << g.ft_log2;
+#define QM_EM(T)                                                                                              \
+    hipLaunchKernelGGL(k_emit<T>, dim3(blocks), dim3(256), lds, s, A, Ad, emit, ctl, iters, rows, mb, nb, g.Z, \
+                       app, hard, g.n, g.ft_log2, g.ntiles, sM)
+    switch (msgk) {
+        case QM_MSGK_F32: QM_EM(float); break;
+        case QM_MSGK_F16: QM_EM(_Float16); break;
+        case QM_MSGK_F8: QM_EM(Fp8Msg); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef QM_EM
     return hipGetLastError();
 }
 

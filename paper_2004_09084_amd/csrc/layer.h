@@ -113,8 +113,9 @@ struct D1Band<_Float16> {
 // degree>=2 edges; sign(r_d) = s ^ xor_j [q_j < 0]).  Outside the band of
 // D1Band the comparison of |K| with clip(S) decides it (no Phi); inside,
 // the exact sum is formed from LLR_d (kept per check in Ad).  The APP
-// itself is formed only for the frames that stop (qm_launch_emit_d1, with
-// the same arithmetic): A's degree-1 slot keeps clip(S) with r_d's sign.
+// itself is formed only for the frames that stop, as they are written out
+// (qm_launch_emit, with the same arithmetic): A's degree-1 slot keeps
+// clip(S) with r_d's sign.
 template <typename MsgT, int FPL, bool MASKED, typename PW>
 __device__ __forceinline__ void d1_early(const LaneCtx &c, ConstRowDesc *rd, const EtLane<FPL> &et,
                                          const float (&kap)[FPL], const bool (&neg)[FPL], const float (&acc)[FPL],

@@ -207,10 +207,11 @@ hipError_t qm_launch_et_plan(uint32_t *fail, uint32_t *act, uint64_t *tmask, int
                              int32_t *iters, int32_t *emit, uint8_t *flags, int F, int32_t *ctl, int Fpad, int ft_log2,
                              int t, int final_pass, hipStream_t s);
 // frame-major APPs and hard decisions of the frames the planning kernel
-// stopped (emit[slot] = frame or -1), from the first g.ntiles tiles
-hipError_t qm_launch_emit_d1(float *A, const float *Ad, const int32_t *emit, const int32_t *ctl, const int32_t *iters,
-                            const RowDesc *rows, int mb, int msgk, const TileGeom &g, hipStream_t s);
-hipError_t qm_launch_emit(const float *A, const int32_t *emit, const int32_t *ctl, float *app, uint8_t *hard,
+// stopped (emit[slot] = frame or -1), from the first g.ntiles tiles; the
+// degree-1 APPs are formed from A's signed sums and Ad's channel LLRs for
+// frames that ran at least one sweep (iters)
+hipError_t qm_launch_emit(const float *A, const float *Ad, const int32_t *emit, const int32_t *ctl,
+                          const int32_t *iters, const RowDesc *rows, int mb, int msgk, float *app, uint8_t *hard,
                           const TileGeom &g, hipStream_t s);
 // move the planned frames (slot perm[s] into slot s) in every per-node array
 struct CompactArray {

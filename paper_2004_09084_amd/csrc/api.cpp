@@ -135,6 +135,8 @@ struct Slot {
     // early termination (decoders created with QM_EARLY_STOP)
     size_t oAd = 0, oAct = 0, oTmask = 0, oMap = 0, oPerm = 0, oIt = 0, oCtl = 0, oEmit = 0, oPA = 0, oPd = 0, oPS = 0;
     std::vector<RowDesc> hrows;  // schedule order
+    std::vector<int32_t> d1row;  // block column -> schedule index of the row whose degree-1 column it is, or -1
+    size_t oD1Row = 0;           // its device copy (early termination)
     std::vector<int32_t> gptr;
     std::vector<int32_t> cols1;  // degree>=2 block columns (LDS order)
     size_t oGptr = 0, oCols1 = 0;
@@ -269,6 +271,7 @@ void layout(qm_decoder &d) {
             s.oPA = off; off = align_up(off + fp * (size_t)s.n);
             s.oPd = off; off = align_up(off + fp * (size_t)s.m);
             s.oPS = off; off = align_up(off + fp * (size_t)s.m);
+            s.oD1Row = off; off = align_up(off + s.d1row.size() * 4);
         }
     }
     d.oErr = off;
@@ -897,6 +900,7 @@ int enqueue_early_slot(qm_decoder &d, Slot &s, int32_t T, uint8_t *hard, float *
     uint8_t *Pd = reinterpret_cast<uint8_t *>(d.ws + s.oPd);
     uint8_t *PS = reinterpret_cast<uint8_t *>(d.ws + s.oPS);
     const int32_t *cols1 = reinterpret_cast<const int32_t *>(d.ws + s.oCols1);
+    const int32_t *d1row = reinterpret_cast<const int32_t *>(d.ws + s.oD1Row);
     const int64_t nR = (int64_t)c.nent1 * c.Z;  // message nodes
 
     // The current frame-tile geometry and per-node arrays (A, R, S, Ad).
@@ -931,7 +935,7 @@ int enqueue_early_slot(qm_decoder &d, Slot &s, int32_t T, uint8_t *hard, float *
         QM_HIP(qm_launch_pack_cols(A, PA, cols1, (int)s.cols1.size(), ctl, la.fpl, g, st));
         QM_HIP(qm_launch_syndrome_packed(PA, Pd, PS, b.rows, c.mb, b.fail, ctl, la.fpl, g, st));
         QM_HIP(qm_launch_et_plan(b.fail, act, tmask, map, perm, it, emit, flags, s.F, ctl, Fpad, g.ft_log2, t, 0, st));
-        QM_HIP(qm_launch_emit(A, Ad, emit, ctl, it, b.rows, c.mb, msgk, app, hard, g, st));
+        QM_HIP(qm_launch_emit(A, Ad, emit, ctl, it, b.rows, d1row, msgk, app, hard, g, st));
         if (g.ntiles > 1) {  // with one tile left no compaction can be planned
             QM_HIP(qm_launch_compact(arr, narr, perm, ctl, g.ft_log2, st));
             QM_HIP(qm_launch_pack_syndrome(S, PS, ctl, 1, la.fpl, g, st));
@@ -1026,7 +1030,7 @@ int enqueue_early_slot(qm_decoder &d, Slot &s, int32_t T, uint8_t *hard, float *
     }
     // frames still decoding ran all T sweeps and failed the last test
     QM_HIP(qm_launch_et_plan(b.fail, act, tmask, map, perm, it, emit, flags, s.F, ctl, Fpad, g.ft_log2, T, 1, st));
-    QM_HIP(qm_launch_emit(A, Ad, emit, ctl, it, b.rows, c.mb, msgk, app, hard, g, st));
+    QM_HIP(qm_launch_emit(A, Ad, emit, ctl, it, b.rows, d1row, msgk, app, hard, g, st));
     if (iters_out && s.F > 0)
         QM_HIP(hipMemcpyAsync(iters_out, it, (size_t)s.F * 4, hipMemcpyDeviceToDevice, st));
     return QM_OK;
@@ -1306,6 +1310,9 @@ int qm_decoder_create(const qm_code *const *codes, int32_t ncodes, const int32_t
             return fail(QM_ERR_UNSUPPORTED, "code too wide for 32-bit in-tile byte offsets");
         }
         for (int i : s.code->rows) s.hrows.push_back(make_desc(*s.code, i));
+        s.d1row.assign(s.code->nb, -1);
+        for (size_t r = 0; r < s.hrows.size(); ++r)
+            if (s.hrows[r].d1col >= 0) s.d1row[s.hrows[r].d1col] = (int32_t)r;
         s.gptr = s.code->gptr;
         for (int j = 0; j < s.code->nb; ++j)
             if (s.code->col_deg[j] >= 2) s.cols1.push_back(j);
@@ -1385,6 +1392,8 @@ int qm_decoder_bind_workspace(qm_decoder *d, void *dev, size_t bytes) {
     for (Slot &s : d->slots) {
         QM_HIP(hipMemcpy(d->ws + s.oRows, s.hrows.data(), s.hrows.size() * sizeof(RowDesc), hipMemcpyHostToDevice));
         QM_HIP(hipMemcpy(d->ws + s.oGptr, s.gptr.data(), s.gptr.size() * 4, hipMemcpyHostToDevice));
+        if (d->flags & QM_EARLY_STOP)
+            QM_HIP(hipMemcpy(d->ws + s.oD1Row, s.d1row.data(), s.d1row.size() * 4, hipMemcpyHostToDevice));
         if (!s.cols1.empty())
             QM_HIP(hipMemcpy(d->ws + s.oCols1, s.cols1.data(), s.cols1.size() * 4, hipMemcpyHostToDevice));
         if (!s.hcols.empty())
@@ -1555,6 +1564,8 @@ int qm_decode_on_workspace(qm_decoder *d, char *ws, size_t ws_bytes, const float
         QM_HIP(hipMemcpyAsync(ws + s.oRows, s.hrows.data(), s.hrows.size() * sizeof(RowDesc), hipMemcpyHostToDevice,
                               st));
         QM_HIP(hipMemcpyAsync(ws + s.oGptr, s.gptr.data(), s.gptr.size() * 4, hipMemcpyHostToDevice, st));
+        if (d->flags & QM_EARLY_STOP)
+            QM_HIP(hipMemcpyAsync(ws + s.oD1Row, s.d1row.data(), s.d1row.size() * 4, hipMemcpyHostToDevice, st));
         if (!s.cols1.empty())
             QM_HIP(hipMemcpyAsync(ws + s.oCols1, s.cols1.data(), s.cols1.size() * 4, hipMemcpyHostToDevice, st));
         if (!s.hcols.empty())

@@ -612,24 +612,17 @@ __global__ void __launch_bounds__(256) k_et_plan(uint32_t *fail, uint32_t *act, 
 template <typename MsgT>
 __global__ void __launch_bounds__(256) k_emit(const float *__restrict__ A, const float *__restrict__ Ad,
                                               const int32_t *__restrict__ emit, const int32_t *ctl,
-                                              const int32_t *__restrict__ iters, const RowDesc *rows, int mb, int nb,
-                                              int Z, float *__restrict__ app, uint8_t *__restrict__ hard, int64_t N,
+                                              const int32_t *__restrict__ iters, const RowDesc *rows,
+                                              const int32_t *__restrict__ d1row, int Z, float *__restrict__ app,
+                                              uint8_t *__restrict__ hard, int64_t N,
                                               int ftl, int ntiles, int64_t strideM) {
     if (ctl[4] == 0) return;
     extern __shared__ uint32_t dyn_lds[];
     float *lds = reinterpret_cast<float *>(dyn_lds);
-    int32_t *d1row = reinterpret_cast<int32_t *>(dyn_lds) + ((kRun + 1) << ftl);
     __shared__ int32_t s_fr[64];
     __shared__ int32_t s_swept[64];  // the slot's frame is listed and ran at least one sweep
     const int FT = 1 << ftl;
     const int tid = threadIdx.x;
-    // block column -> the row (schedule index) whose degree-1 variable it is
-    for (int c = tid; c < nb; c += 256) d1row[c] = -1;
-    __syncthreads();
-    for (int r = tid; r < mb; r += 256) {
-        const int c = rows[r].d1col;
-        if (c >= 0) d1row[c] = r;
-    }
     // vector stores where every row of the outputs starts 16-byte (APP) and
     // 4-byte (hard) aligned
     const bool vec = (N & 3) == 0 && (reinterpret_cast<uintptr_t>(app) & 15u) == 0 &&
@@ -639,7 +632,7 @@ __global__ void __launch_bounds__(256) k_emit(const float *__restrict__ A, const
     for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
         const int tile = (int)(it % (uint32_t)ntiles);
         const int64_t v0 = (int64_t)(it / (uint32_t)ntiles) * kRun;
-        __syncthreads();  // the previous item is done with s_fr and lds (and d1row is complete)
+        __syncthreads();  // the previous item is done with s_fr and lds
         if (tid < FT) {
             const int f = emit[tile * FT + tid];
             s_fr[tid] = f;
@@ -1071,18 +1064,17 @@ hipError_t qm_launch_et_plan(uint32_t *fail, uint32_t *act, uint64_t *tmask, int
 }
 
 hipError_t qm_launch_emit(const float *A, const float *Ad, const int32_t *emit, const int32_t *ctl,
-                          const int32_t *iters, const RowDesc *rows, int mb, int msgk, float *app, uint8_t *hard,
-                          const TileGeom &g, hipStream_t s) {
+                          const int32_t *iters, const RowDesc *rows, const int32_t *d1row, int msgk, float *app,
+                          uint8_t *hard, const TileGeom &g, hipStream_t s) {
     if ((1 << g.ft_log2) > 64 || g.Z < 1 || g.n % g.Z != 0 || g.n >= (1LL << 31)) return hipErrorInvalidValue;
     const int64_t items = ((g.n + kRun - 1) / kRun) * g.ntiles;
     if (items == 0) return hipSuccess;
     if (items >= (1LL << 31)) return hipErrorInvalidValue;
-    const int nb = (int)(g.n / g.Z);
     const unsigned blocks = (unsigned)std::min<int64_t>(items, 4096);
-    const size_t lds = (((size_t)(kRun + 1) << g.ft_log2) + (size_t)nb) * 4;
+    const size_t lds = ((size_t)(kRun + 1) << g.ft_log2) * 4;
     const int64_t sM = (int64_t)g.m << g.ft_log2;
 #define QM_EM(T)                                                                                              \
-    hipLaunchKernelGGL(k_emit<T>, dim3(blocks), dim3(256), lds, s, A, Ad, emit, ctl, iters, rows, mb, nb, g.Z, \
+    hipLaunchKernelGGL(k_emit<T>, dim3(blocks), dim3(256), lds, s, A, Ad, emit, ctl, iters, rows, d1row, g.Z, \
                        app, hard, g.n, g.ft_log2, g.ntiles, sM)
     switch (msgk) {
         case QM_MSGK_F32: QM_EM(float); break;

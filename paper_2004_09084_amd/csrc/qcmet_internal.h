@@ -209,10 +209,11 @@ hipError_t qm_launch_et_plan(uint32_t *fail, uint32_t *act, uint64_t *tmask, int
 // frame-major APPs and hard decisions of the frames the planning kernel
 // stopped (emit[slot] = frame or -1), from the first g.ntiles tiles; the
 // degree-1 APPs are formed from A's signed sums and Ad's channel LLRs for
-// frames that ran at least one sweep (iters)
+// frames that ran at least one sweep (iters); d1row[c] is the schedule
+// index of the row whose degree-1 column is block column c, or -1
 hipError_t qm_launch_emit(const float *A, const float *Ad, const int32_t *emit, const int32_t *ctl,
-                          const int32_t *iters, const RowDesc *rows, int mb, int msgk, float *app, uint8_t *hard,
-                          const TileGeom &g, hipStream_t s);
+                          const int32_t *iters, const RowDesc *rows, const int32_t *d1row, int msgk, float *app,
+                          uint8_t *hard, const TileGeom &g, hipStream_t s);
 // move the planned frames (slot perm[s] into slot s) in every per-node array
 struct CompactArray {
     void *p;                  // [ntiles][N][FT] elements of esz bytes

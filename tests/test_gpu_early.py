@@ -259,3 +259,58 @@ def test_early_fullsize_fp16_against_oracle():
             # a converged frame: every hard decision and every APP in tolerance
             assert rows[0]["bits_diff"] == 0 and rows[0]["app_viol"] == 0, (f, rows[0])
 
+
+
+def _many_column_code(C, rowdeg, Z, seed):
+    """mb = 2C/rowdeg rows; C columns of degree 2, rowdeg per row, and one
+    degree-1 column per row: nb = C + mb base columns."""
+    rng = np.random.default_rng(seed)
+    mb = 2 * C // rowdeg
+    slots = rng.permutation(np.repeat(np.arange(C), 2)).reshape(mb, rowdeg)
+    for _ in range(100):
+        bad = [i for i in range(mb) if len(set(slots[i].tolist())) < rowdeg]
+        if not bad:
+            break
+        for i in bad:  # swap a repeated column with a random slot elsewhere
+            j, a, b = int(rng.integers(0, mb)), int(rng.integers(0, rowdeg)), int(rng.integers(0, rowdeg))
+            slots[i, b], slots[j, a] = slots[j, a], slots[i, b]
+    assert all(len(set(r.tolist())) == rowdeg for r in slots)
+    H = np.full((mb, C + mb), -1, dtype=np.int32)
+    for i in range(mb):
+        H[i, slots[i]] = rng.integers(0, Z, rowdeg)
+        H[i, C + i] = rng.integers(0, Z)
+    return H
+
+
+def _sparse_frames(H, Z, snrs, seed):
+    mb, nb = H.shape
+    n, m = nb * Z, mb * Z
+    rng = np.random.default_rng(seed)
+    ii, jj = np.nonzero(H >= 0)
+    k = np.arange(Z)
+    rows = (ii[:, None] * Z + k[None, :]).ravel()
+    cols = (jj[:, None] * Z + (k[None, :] + H[ii, jj][:, None]) % Z).ravel()
+    L, S = [], []
+    for snr in snrs:
+        x = rng.integers(0, 2, n).astype(np.uint8)
+        y = 1.0 - 2.0 * x + rng.normal(0.0, np.sqrt(1.0 / snr), n)
+        s = np.zeros(m, dtype=np.uint8)
+        np.bitwise_xor.at(s, rows, x[cols])
+        L.append((2.0 * y * snr).astype(np.float32))
+        S.append(s)
+    return np.array(L), np.array(S)
+
+
+def test_early_very_many_base_columns():
+    # 40000 base columns (a column-to-row table of them would take 160 KB,
+    # more than one workgroup's LDS): the output pass forms every stopped
+    # frame's degree-1 APPs, bit-exact against fixed decodes at its count
+    T, Z = 12, 2
+    H = _many_column_code(32000, 8, Z, 0)
+    assert H.shape == (8000, 40000)
+    L, S = _sparse_frames(H, Z, np.repeat([4.0, 5.0, 6.0, 8.0], 4), 1)
+    say("early, 40000 base columns")
+    res = _early(H, Z, L, S, T)
+    say("iters", res[3].tolist())
+    assert (res[3] < T).sum() >= 4 and len(set(res[3].tolist())) >= 3
+    _assert_frozen_equal_fixed(H, Z, L, S, res)

@@ -327,21 +327,26 @@ def test_code_streams_graph_replays_match_eager():
         torch.ones(8, device="cuda").mul_(2.0)
 
 
-def test_fused_mixed_batch_matches_oracle_per_code():
+@pytest.mark.parametrize("fp16", [False, True], ids=["fp32", "fp16"])
+@pytest.mark.parametrize("fuse", [1, 2], ids=["fused", "streams"])
+def test_fused_mixed_batch_matches_oracle_per_code(fuse, fp16):
+    # each code's frames of a mixed batch against the oracle's decode of that
+    # code alone, with fused launches and with a stream per code; binary16
+    # messages against the oracle's binary16 mode
     import torch
     specs = [SMALL, W.RATE005.with_Z(16), W.RATE002.with_Z(16)]
     Fs = [5, 3, 4]
     wls, codes, L, S = _mixed(specs, Fs, snr_scale=3.0)
-    dec = Q.Decoder(codes, Fs, tuning=dict(fuse_codes=1))
+    dec = Q.Decoder(codes, Fs, flags=Q.QM_MSG_FP16 if fp16 else 0, tuning=dict(fuse_codes=fuse))
     for T in (1, 2):
         h, a, f = dec.decode(L, S, T)
         torch.cuda.synchronize()
         a, h, f = a.cpu().numpy(), h.cpu().numpy(), f.cpu().numpy()
         on = of = 0
         for w, s, F in zip(wls, specs, Fs):
-            appo, hardo, flo, _ = oracle.decode_sp(w.shifts, s.Z, w.llr, w.s, T)
+            appo, hardo, flo, _ = oracle.decode_sp(w.shifts, s.Z, w.llr, w.s, T, fp16_messages=fp16)
             rows = compare(a[on:on + F * s.n].reshape(F, -1), h[on:on + F * s.n].reshape(F, -1), f[of:of + F],
-                           appo, hardo, flo)
+                           appo, hardo, flo, extra=FP16_EXTRA if fp16 else 0.0)
             for r in rows:
                 assert r["app_viol"] == 0 and r["bits_diff_confident"] == 0 and r["flag_o"] == r["flag_g"], (s.name, r)
             on += F * s.n

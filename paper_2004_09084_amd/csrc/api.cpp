@@ -971,7 +971,12 @@ int enqueue_early_slot(qm_decoder &d, Slot &s, int32_t T, uint8_t *hard, float *
         la.Ad = Ad;
         la.K = K;
         la.ft_log2 = ftl;
-        la.fpl = std::min(la.fpl, Fpad);
+        // one frame per lane in the narrowed tile: its launches are short and
+        // bound by each lane's chain of dependent loads, which a lane with one
+        // frame finishes sooner (8 frames, one-row layer: 5.5 against 6.6 us);
+        // the packed layouts follow fpl, and every packed array the next test
+        // reads is rewritten under it (PS here, Pd by the sweep, PA by the test)
+        la.fpl = 1;
         la.chunks = ((c.Z << ftl) / la.fpl + d.tun.block - 1) / d.tun.block;
         la.strideA = s.n << ftl;
         la.strideR = nR << ftl;

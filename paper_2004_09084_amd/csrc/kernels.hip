@@ -426,6 +426,69 @@ __global__ void __launch_bounds__(256) k_pack_syndrome(const uint8_t *__restrict
                                            pack_node0(ftl, bx), m, ftl, fpl);
 }
 
+// Node-per-lane packing, for fields of at least 16 bytes (FT syndrome bytes
+// with FT >= 16, FT APPs with FT >= 4) on 16-byte aligned tiles: a lane reads
+// its node's FT values with 16-byte loads and assembles the packed field in
+// registers (frame fl at bit qm_pack_bit), which takes fewer instructions
+// per byte than a one-value-per-lane pass with ballots.
+template <typename T>
+struct FieldBit;
+template <>
+struct FieldBit<uint8_t> {  // a syndrome byte: its bit 0
+    __device__ static bool get(uint32_t word, int byte) { return ((word >> (8 * byte)) & 1u) != 0u; }
+};
+template <>
+struct FieldBit<float> {  // an APP: the hard decision x < 0
+    __device__ static bool get(uint32_t word, int) { return __uint_as_float(word) < 0.0f; }
+};
+
+template <typename T, int FT, int FPL>
+__device__ __forceinline__ uint64_t pack_node_field(const T *__restrict__ x) {
+    constexpr int NL = FT * (int)sizeof(T) / 16;  // 16-byte loads per node
+    static_assert(NL >= 1 && FT % FPL == 0, "field shape");
+    uint4 r[NL];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) r[i] = reinterpret_cast<const uint4 *>(x)[i];
+    constexpr int lpc = FT / FPL;
+    uint64_t w = 0;
+#pragma unroll
+    for (int fl = 0; fl < FT; ++fl) {
+        const int byte = fl * (int)sizeof(T);
+        const uint4 &q = r[byte / 16];
+        const int k = (byte % 16) / 4;
+        const uint32_t word = k == 0 ? q.x : k == 1 ? q.y : k == 2 ? q.z : q.w;
+        w |= (uint64_t)FieldBit<T>::get(word, byte % 4) << ((fl % FPL) * lpc + fl / FPL);
+    }
+    return w;
+}
+
+// every node of the tiles (below ctl[1] and, after a compaction, only when
+// one was planned, as k_pack_syndrome)
+template <typename T, int FT, int FPL>
+__global__ void __launch_bounds__(256) k_pack_nodes(const T *__restrict__ X, uint8_t *__restrict__ P, int64_t N,
+                                                    const int32_t *ctl, int after_compaction) {
+    const int64_t tile = blockIdx.y;
+    if (ctl && (tile >= ctl[1] || (after_compaction && ctl[2] == 0))) return;
+    constexpr int PB = FT <= 8 ? 1 : FT / 8;  // bytes of a packed field
+    const T *x = X + tile * N * FT;
+    uint8_t *p = P + tile * N * PB;
+    for (int64_t node = (int64_t)blockIdx.x * 256 + threadIdx.x; node < N; node += (int64_t)gridDim.x * 256)
+        store_packed(p, node, PB, pack_node_field<T, FT, FPL>(x + node * FT));
+}
+
+// the degree>=2 columns (cols1) of the tiles below ctl[1], as k_pack_cols
+template <int FT, int FPL>
+__global__ void __launch_bounds__(256) k_pack_cols_nodes(const float *__restrict__ A, uint8_t *__restrict__ P,
+                                                         const int32_t *cols1, int Z, int64_t n, const int32_t *ctl) {
+    const int64_t tile = blockIdx.z;
+    if (tile >= ctl[1]) return;
+    const int i = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    if (i >= Z) return;
+    constexpr int PB = FT <= 8 ? 1 : FT / 8;
+    const int64_t node = (int64_t)cols1[blockIdx.y] * Z + i;
+    store_packed(P + tile * n * PB, node, PB, pack_node_field<float, FT, FPL>(A + (tile * n + node) * FT));
+}
+
 // ---------------------------------------------------------------------------
 // Early termination (Results, Table tabearly): after every sweep each frame's
 // hard decisions are tested against its syndrome (k_syndrome over the tiles
@@ -1010,6 +1073,30 @@ hipError_t qm_launch_syndrome_packed(const uint8_t *PA, const uint8_t *Pd, const
     return hipGetLastError();
 }
 
+// The node-per-lane packing applies when a node's field of FT values is at
+// least 16 bytes, every tile starts 16-byte aligned, and a lane holds one or
+// two frames.
+static bool node_fields(const void *X, int64_t N, int ftl, int fpl, size_t esz) {
+    const size_t field = esz << ftl;
+    return field >= 16 && field % 16 == 0 && (reinterpret_cast<uintptr_t>(X) & 15u) == 0 &&
+           ((size_t)N * field) % 16 == 0 && (fpl == 1 || fpl == 2) && ftl <= 6;
+}
+static unsigned node_blocks(int64_t N) { return (unsigned)std::min<int64_t>((N + 255) / 256, 65535); }
+// float fields: FT = 4 .. 64, one or two frames per lane
+#define QM_NODE_DISPATCH(ftl, fpl, M)        \
+    switch ((ftl) * 2 + (fpl) - 1) {         \
+        case 4: M(4, 1); break;              \
+        case 5: M(4, 2); break;              \
+        case 6: M(8, 1); break;              \
+        case 7: M(8, 2); break;              \
+        case 8: M(16, 1); break;             \
+        case 9: M(16, 2); break;             \
+        case 10: M(32, 1); break;            \
+        case 11: M(32, 2); break;            \
+        case 12: M(64, 1); break;            \
+        default: M(64, 2); break;            \
+    }
+
 // blocks of 256 lanes for a packing pass over N nodes
 static unsigned pack_blocks(int64_t N, int ftl, int U = kPackU) {
     const int64_t per_block = 4LL * U * (64 >> ftl);
@@ -1019,6 +1106,13 @@ static unsigned pack_blocks(int64_t N, int ftl, int U = kPackU) {
 hipError_t qm_launch_pack_signs(const float *X, uint8_t *P, int64_t N, int fpl, const TileGeom &g, hipStream_t s) {
     if ((1 << g.ft_log2) > 64 || fpl < 1 || fpl > (1 << g.ft_log2)) return hipErrorInvalidValue;
     if (N == 0 || g.ntiles == 0) return hipSuccess;
+    if (node_fields(X, N, g.ft_log2, fpl, sizeof(float))) {
+        dim3 grid(node_blocks(N), (unsigned)g.ntiles);
+#define QM_PN(FT, FPL) hipLaunchKernelGGL((k_pack_nodes<float, FT, FPL>), grid, dim3(256), 0, s, X, P, N, nullptr, 0)
+        QM_NODE_DISPATCH(g.ft_log2, fpl, QM_PN);
+#undef QM_PN
+        return hipGetLastError();
+    }
     dim3 grid(pack_blocks(N, g.ft_log2), (unsigned)g.ntiles);
     hipLaunchKernelGGL(k_pack_signs, grid, dim3(256), 0, s, X, P, N, g.ft_log2, fpl);
     return hipGetLastError();
@@ -1028,6 +1122,14 @@ hipError_t qm_launch_pack_cols(const float *A, uint8_t *P, const int32_t *cols1,
                                const TileGeom &g, hipStream_t s) {
     if ((1 << g.ft_log2) > 64 || fpl < 1 || fpl > (1 << g.ft_log2) || !ctl) return hipErrorInvalidValue;
     if (ncols1 == 0 || g.ntiles == 0) return hipSuccess;
+    if (node_fields(A, g.n, g.ft_log2, fpl, sizeof(float))) {
+        dim3 grid((unsigned)((g.Z + 255) / 256), (unsigned)ncols1, (unsigned)g.ntiles);
+#define QM_PC(FT, FPL) \
+    hipLaunchKernelGGL((k_pack_cols_nodes<FT, FPL>), grid, dim3(256), 0, s, A, P, cols1, g.Z, g.n, ctl)
+        QM_NODE_DISPATCH(g.ft_log2, fpl, QM_PC);
+#undef QM_PC
+        return hipGetLastError();
+    }
     dim3 grid(pack_blocks(g.Z, g.ft_log2, kPackColsU), (unsigned)ncols1, (unsigned)g.ntiles);
     hipLaunchKernelGGL(k_pack_cols, grid, dim3(256), 0, s, A, P, cols1, g.Z, g.n, g.ft_log2, fpl, ctl);
     return hipGetLastError();
@@ -1037,6 +1139,22 @@ hipError_t qm_launch_pack_syndrome(const uint8_t *Sil, uint8_t *PS, const int32_
                                    const TileGeom &g, hipStream_t s) {
     if ((1 << g.ft_log2) > 64 || fpl < 1 || fpl > (1 << g.ft_log2)) return hipErrorInvalidValue;
     if (g.m == 0 || g.ntiles == 0) return hipSuccess;
+    if (g.ft_log2 >= 4 && node_fields(Sil, g.m, g.ft_log2, fpl, 1)) {
+        const unsigned nb = node_blocks(g.m);
+        dim3 grid(after_compaction ? std::min(nb, 512u) : nb, (unsigned)g.ntiles);
+#define QM_PS(FT, FPL)                                                                                              \
+    hipLaunchKernelGGL((k_pack_nodes<uint8_t, FT, FPL>), grid, dim3(256), 0, s, Sil, PS, g.m, ctl, after_compaction)
+        switch (g.ft_log2 * 2 + fpl - 1) {
+            case 8: QM_PS(16, 1); break;
+            case 9: QM_PS(16, 2); break;
+            case 10: QM_PS(32, 1); break;
+            case 11: QM_PS(32, 2); break;
+            case 12: QM_PS(64, 1); break;
+            default: QM_PS(64, 2); break;
+        }
+#undef QM_PS
+        return hipGetLastError();
+    }
     const unsigned bx = after_compaction ? std::min(pack_blocks(g.m, g.ft_log2), 512u) : pack_blocks(g.m, g.ft_log2);
     dim3 grid(bx, (unsigned)g.ntiles);
     hipLaunchKernelGGL(k_pack_syndrome, grid, dim3(256), 0, s, Sil, PS, g.m, g.ft_log2, fpl, ctl, after_compaction);

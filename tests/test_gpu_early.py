@@ -71,14 +71,16 @@ def test_early_matches_oracle(fp16):
             assert r["bits_diff"] == 0 and r["app_viol"] == 0, r
 
 
+@pytest.mark.parametrize("fpl", [2, 1])
 @pytest.mark.parametrize("ft", [1, 4, 16, 32, 64])
-def test_early_frames_equal_fixed_decodes(ft):
+def test_early_frames_equal_fixed_decodes(ft, fpl):
     # 64 frames at a waterfall SNR: frames stop after 3 to 6 sweeps or never,
-    # so tiles empty at several sweeps and frames are compacted several times
+    # so tiles empty at several sweeps and frames are compacted several times;
+    # every packed layout (frames per tile and per lane) of the tests
     T = 30
     H, L, S = _frames(SMALL, 64, 0.25, 12)
-    tun = {"frames_per_tile": ft}
-    say(f"early vs fixed, FT={ft}")
+    tun = {"frames_per_tile": ft, "frames_per_lane": fpl}
+    say(f"early vs fixed, FT={ft}, {fpl} frames per lane")
     res = _early(H, SMALL.Z, L, S, T, tuning=tun)
     say("iters", np.bincount(res[3]).tolist())
     assert (res[3] < T).sum() >= 16

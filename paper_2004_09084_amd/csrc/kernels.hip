@@ -59,27 +59,32 @@ __global__ void __launch_bounds__(256) k_kappa(const float *__restrict__ A, cons
 constexpr int kRun = 128;
 
 // Frame-major [F][N] -> frame tiles [ntiles][N][FT] (padding frames = 0),
-// through a kRun-node x FT-frame LDS tile so both sides are coalesced.
-// (LDS: FT x (kRun + 1) elements, dynamic.)
-template <typename T>
+// through a RUN-node x FT-frame LDS tile so both sides are coalesced.
+// (LDS: FT x (RUN + 1) elements, dynamic.)  Byte arrays take longer runs, so
+// that a workgroup moves as many bytes as a float one.
+template <typename T, int RUN>
 __global__ void __launch_bounds__(256) k_to_tiles(const T *__restrict__ in, T *__restrict__ out, int F,
                                                   int64_t N, int ftl) {
+    static_assert((RUN & (RUN - 1)) == 0 && RUN >= 128, "run of nodes");
     extern __shared__ uint32_t dyn_lds[];
     T *lds = reinterpret_cast<T *>(dyn_lds);
     const int tile = blockIdx.y;
-    const int64_t v0 = (int64_t)blockIdx.x * kRun;
+    const int64_t v0 = (int64_t)blockIdx.x * RUN;
     const int FT = 1 << ftl;
     const int tid = threadIdx.x;
-    for (int fl = tid / kRun; fl < FT; fl += 256 / kRun) {
+#pragma unroll 4
+    for (int e = tid; e < (RUN << ftl); e += 256) {
+        const int fl = e / RUN;
+        const int vv = e % RUN;
         const int f = tile * FT + fl;
-        const int64_t v = v0 + (tid % kRun);
-        lds[fl * (kRun + 1) + tid % kRun] = (f < F && v < N) ? in[(int64_t)f * N + v] : (T)0;
+        const int64_t v = v0 + vv;
+        lds[fl * (RUN + 1) + vv] = (f < F && v < N) ? in[(int64_t)f * N + v] : (T)0;
     }
     __syncthreads();
     T *o = out + ((int64_t)tile * N + v0) * FT;
-    for (int e = tid; e < (kRun << ftl); e += 256) {
+    for (int e = tid; e < (RUN << ftl); e += 256) {
         const int vv = e >> ftl;
-        if (v0 + vv < N) o[e] = lds[(e & (FT - 1)) * (kRun + 1) + vv];
+        if (v0 + vv < N) o[e] = lds[(e & (FT - 1)) * (RUN + 1) + vv];
     }
 }
 
@@ -909,15 +914,16 @@ hipError_t qm_launch_to_tiles_f32(const float *in, float *out, int F, int64_t N,
                                   hipStream_t s) {
     dim3 grid((unsigned)((N + kRun - 1) / kRun), (unsigned)ntiles);
     const size_t lds = ((size_t)(kRun + 1) << ft_log2) * 4;
-    hipLaunchKernelGGL(k_to_tiles<float>, grid, dim3(256), lds, s, in, out, F, N, ft_log2);
+    hipLaunchKernelGGL((k_to_tiles<float, kRun>), grid, dim3(256), lds, s, in, out, F, N, ft_log2);
     return hipGetLastError();
 }
 
 hipError_t qm_launch_to_tiles_u8(const uint8_t *in, uint8_t *out, int F, int64_t N, int ft_log2, int ntiles,
                                  hipStream_t s) {
-    dim3 grid((unsigned)((N + kRun - 1) / kRun), (unsigned)ntiles);
-    const size_t lds = (((size_t)(kRun + 1) << ft_log2) + 3) / 4 * 4;
-    hipLaunchKernelGGL(k_to_tiles<uint8_t>, grid, dim3(256), lds, s, in, out, F, N, ft_log2);
+    constexpr int run = 4 * kRun;
+    dim3 grid((unsigned)((N + run - 1) / run), (unsigned)ntiles);
+    const size_t lds = (((size_t)(run + 1) << ft_log2) + 3) / 4 * 4;
+    hipLaunchKernelGGL((k_to_tiles<uint8_t, run>), grid, dim3(256), lds, s, in, out, F, N, ft_log2);
     return hipGetLastError();
 }
 

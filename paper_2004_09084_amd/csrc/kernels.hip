@@ -88,6 +88,40 @@ __global__ void __launch_bounds__(256) k_to_tiles(const T *__restrict__ in, T *_
     }
 }
 
+// The same transpose for bytes, moved as 4-byte words (N a multiple of 4,
+// both buffers 4-byte aligned, FT >= 4): a lane loads a word of 4 nodes of
+// one frame, and builds each output word (4 frames of one node) from 4 LDS
+// words.  LDS: FT rows of kRun + 1 words (4 kRun nodes).
+__global__ void __launch_bounds__(256) k_to_tiles_u8w(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
+                                                      int F, int64_t N, int ftl) {
+    extern __shared__ uint32_t dyn_lds[];
+    const int tile = blockIdx.y;
+    const int64_t v0 = (int64_t)blockIdx.x * (4 * kRun);
+    const int FT = 1 << ftl;
+    const int tid = threadIdx.x;
+    const int64_t Nw = N >> 2;  // words per frame row
+#pragma unroll 4
+    for (int e = tid; e < (kRun << ftl); e += 256) {
+        const int fl = e / kRun;
+        const int w = e % kRun;
+        const int f = tile * FT + fl;
+        const int64_t v = v0 + 4 * w;  // v < N implies v + 3 < N
+        dyn_lds[fl * (kRun + 1) + w] = (f < F && v < N) ? in[(int64_t)f * Nw + (v >> 2)] : 0u;
+    }
+    __syncthreads();
+    const int qn = FT / 4;  // output words per node
+    uint32_t *o = out + (((int64_t)tile * N + v0) << ftl) / 4;
+    for (int e = tid; e < (kRun << ftl); e += 256) {
+        const int vv = e / qn;
+        const int q = e % qn;
+        if (v0 + vv >= N) continue;
+        const int sh = 8 * (vv & 3);
+        const uint32_t *l = dyn_lds + (4 * q) * (kRun + 1) + (vv >> 2);
+        o[e] = ((l[0] >> sh) & 0xffu) | (((l[kRun + 1] >> sh) & 0xffu) << 8) |
+               (((l[2 * (kRun + 1)] >> sh) & 0xffu) << 16) | (((l[3 * (kRun + 1)] >> sh) & 0xffu) << 24);
+    }
+}
+
 // Frame tiles -> frame-major APP and hard decisions (step 4: c = [APP < 0]);
 // also the per-frame flags from the syndrome pass.  Slots whose frame is
 // >= F are padding.
@@ -920,6 +954,14 @@ hipError_t qm_launch_to_tiles_f32(const float *in, float *out, int F, int64_t N,
 
 hipError_t qm_launch_to_tiles_u8(const uint8_t *in, uint8_t *out, int F, int64_t N, int ft_log2, int ntiles,
                                  hipStream_t s) {
+    if (N % 4 == 0 && ft_log2 >= 2 && (reinterpret_cast<uintptr_t>(in) & 3u) == 0 &&
+        (reinterpret_cast<uintptr_t>(out) & 3u) == 0) {
+        dim3 grid((unsigned)((N + 4 * kRun - 1) / (4 * kRun)), (unsigned)ntiles);
+        const size_t lds = ((size_t)(kRun + 1) << ft_log2) * 4;
+        hipLaunchKernelGGL(k_to_tiles_u8w, grid, dim3(256), lds, s, reinterpret_cast<const uint32_t *>(in),
+                           reinterpret_cast<uint32_t *>(out), F, N, ft_log2);
+        return hipGetLastError();
+    }
     constexpr int run = 4 * kRun;
     dim3 grid((unsigned)((N + run - 1) / run), (unsigned)ntiles);
     const size_t lds = (((size_t)(run + 1) << ft_log2) + 3) / 4 * 4;
